@@ -1,0 +1,166 @@
+/*
+ * lst.h - C ABI of the MI355X line-segment-tracking object builder.
+ *
+ * The library builds, from one event's (or a batch of events') outer-tracker
+ * hits, the four LST track-segment collections of the paper's Table 1 steps
+ * 1-4 (arXiv:2403.13166, Sec. 1):
+ *   mini-doublets (MD): two hits on the two sensors of one pT-module;
+ *   line segments (LS): two MDs on adjacent modules with consistent pT;
+ *   triplets (T3):      two LSs sharing an MD;
+ *   quintuplets (T5):   two T3s sharing an MD,
+ * each passing geometric cuts, and scores every T5 with the T5-DNN of Sec. 2
+ * (two hidden layers of 32 nodes, sigmoid output).
+ *
+ * Conventions (all entry points):
+ *  - Every pointer named *_dev, and every pointer inside lst_hits and
+ *    lst_objects, is a DEVICE pointer owned by the caller. Blobs and the
+ *    lst_* structs themselves are host memory owned by the caller.
+ *  - Work is ordered on the HIP stream passed as `stream` (NULL = default
+ *    stream). The library allocates device memory only in lst_load_geometry
+ *    and lst_load_model (its own tables, freed by lst_destroy); build and
+ *    score calls never allocate: scratch is the caller's workspace.
+ *  - Every function returns an lst_status; details of the last error are in
+ *    lst_last_error(ctx). A context is not thread safe; calls that share a
+ *    workspace must not overlap.
+ */
+#ifndef LST_H
+#define LST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lst_status;
+#define LST_OK 0
+#define LST_E_INVAL (-1)     /* bad argument, bad blob, or sensor id out of range */
+#define LST_E_STATE (-2)     /* geometry / model not loaded */
+#define LST_E_CAPACITY (-3)  /* an output or candidate capacity was too small */
+#define LST_E_HIP (-4)       /* a HIP runtime call failed */
+#define LST_E_NOMEM (-5)     /* device allocation failed (load calls only) */
+
+/* lst_options.mode */
+#define LST_MODE_DNN 0       /* T5-DNN scores every T5; no r-phi fit cut (Sec. 2) */
+#define LST_MODE_PRE_DNN 1   /* r-phi circle-fit chi2 cut instead of the DNN (Sec. 2, Table 2) */
+/* precision of the T5-DNN / lst_score */
+#define LST_PREC_F32 0       /* FP32 vector ALU */
+#define LST_PREC_BF16 1      /* BF16 inputs and weights on MFMA, FP32 accumulation */
+/* lst_options.flags */
+#define LST_ASYNC 1          /* do not synchronise; counts stay on the device */
+/* lst_score x_dtype */
+#define LST_DTYPE_F32 0
+#define LST_DTYPE_BF16 1
+
+/* counts_dev layout (int64 each) */
+#define LST_COUNT_MD 0
+#define LST_COUNT_LS 1
+#define LST_COUNT_T3 2
+#define LST_COUNT_T5 3
+#define LST_COUNT_ERR 4      /* bit 0 bad sensor id, bit 1 candidate cap, bit 2 object cap */
+#define LST_COUNT_MAXCAND 5  /* largest candidate count of any stage (required cand cap) */
+#define LST_COUNTS_LEN 8
+
+#define LST_N_FEATURES 42
+
+typedef struct lst_ctx lst_ctx;
+
+/* Hits, structure of arrays, device pointers, n entries each. Batched calls
+ * concatenate events; x, y, z in cm; sensor = 2 * module + (0 anchor sensor,
+ * 1 other sensor) in the numbering of the geometry blob. */
+typedef struct {
+    const float *x, *y, *z;
+    const int32_t *sensor;
+    int64_t n;
+} lst_hits;
+
+/* Capacities that size the workspace; the output arrays of lst_objects must
+ * hold at least md / ls / t3 / t5 entries. cand bounds the candidate pairs
+ * examined by any one stage (all events of a batch together). */
+typedef struct {
+    int64_t hits, events, md, ls, t3, t5, cand;
+} lst_caps;
+
+/* Output collections (device pointers, caller-owned). Objects are given by
+ * index: MD by the input indices of its (anchor, other) hits, LS by its
+ * (inner, outer) MD indices, T3 by its (inner, outer) LS indices, T5 by its
+ * (inner, outer) T3 indices; for batches all indices are into the batch's
+ * concatenated arrays. Order within a collection is deterministic (sorted by
+ * event, then by the anchor MD or module) but not otherwise specified. */
+typedef struct {
+    int32_t *md_hits;            /* [caps.md][2] */
+    int32_t *ls_md;              /* [caps.ls][2] */
+    int32_t *t3_ls;              /* [caps.t3][2] */
+    int32_t *t5_t3;              /* [caps.t5][2] */
+    float *t5_score;             /* [caps.t5], NaN in PRE_DNN mode */
+    float *t5_chi2_rphi;         /* [caps.t5] */
+    float *t5_chi2_rz;           /* [caps.t5] */
+    float *t5_feat;              /* optional [caps.t5][42] DNN inputs before standardisation, or NULL */
+    int64_t *counts_dev;         /* [LST_COUNTS_LEN] required counts and error bits */
+    int64_t n_md, n_ls, n_t3, n_t5;   /* host copies, filled unless LST_ASYNC */
+} lst_objects;
+
+typedef struct {
+    int32_t mode;                /* LST_MODE_DNN or LST_MODE_PRE_DNN */
+    int32_t precision;           /* LST_PREC_F32 or LST_PREC_BF16 (T5-DNN) */
+    float score_min;             /* keep T5 with score >= score_min (DNN mode); NaN keeps all */
+    int32_t flags;               /* LST_ASYNC */
+} lst_options;
+
+/* Create a context on HIP device `device` (the device is made current). */
+lst_status lst_create(int device, lst_ctx **out);
+void lst_destroy(lst_ctx *ctx);
+
+/* Load the detector geometry and module map ("LSTG" blob v1, host memory,
+ * copied): module records (barrel cylinder patches / endcap annulus sectors,
+ * two sensors each, Sec. 1 pT-modules), the module map that defines which
+ * module pairs are "adjacent" for line segments (Sec. 1), and the selection
+ * parameters. Per-module FP32 thresholds are derived here from the FP64
+ * parameters. LST_E_INVAL on a malformed blob. */
+lst_status lst_load_geometry(lst_ctx *ctx, const void *blob, size_t nbytes);
+
+/* Load the T5-DNN ("LSTM" blob v1, host memory, copied): 42 -> 32 -> 32 -> 1
+ * weights (Sec. 2) and the per-feature standardisation. */
+lst_status lst_load_model(lst_ctx *ctx, const void *blob, size_t nbytes);
+
+/* Bytes of device workspace a build call with these capacities needs
+ * (256-byte aligned base required). */
+lst_status lst_workspace_size(const lst_ctx *ctx, const lst_caps *caps, size_t *bytes);
+
+/* Build MD, LS, T3, T5 and T5 scores for ONE event (Table 1 steps 1-4 and the
+ * Sec. 2 T5-DNN). Returns LST_E_CAPACITY (after a sync) when any count
+ * exceeds its capacity: out->n_* / counts_dev then hold the required counts
+ * and the output contents are unspecified. With LST_ASYNC nothing is checked
+ * on the host; read counts_dev after the stream completes. */
+lst_status lst_build_objects(lst_ctx *ctx, const lst_hits *hits, const lst_options *opt,
+                             const lst_caps *caps, lst_objects *out, void *workspace,
+                             size_t ws_bytes, void *stream);
+
+/* Same for a batch of n_events events whose hits are concatenated:
+ * event e owns hits [event_offsets_dev[e], event_offsets_dev[e + 1]) (int64,
+ * device, n_events + 1 entries, event_offsets_dev[0] = 0, last = hits->n).
+ * Objects of all events go to one set of collections, grouped by event; on
+ * return event_obj_offsets_dev (int64 device [4][n_events + 1], may be NULL)
+ * holds for MD, LS, T3, T5 the first index of each event's objects. Grid
+ * shapes depend only on caps, so the call can be captured in a HIP graph. */
+lst_status lst_build_objects_batched(lst_ctx *ctx, const lst_hits *hits,
+                                     const int64_t *event_offsets_dev, int32_t n_events,
+                                     const lst_options *opt, const lst_caps *caps,
+                                     lst_objects *out, int64_t *event_obj_offsets_dev,
+                                     void *workspace, size_t ws_bytes, void *stream);
+
+/* Score n feature rows with the loaded T5-DNN (Sec. 2): X_dev is [n][42]
+ * row-major, FP32 or BF16 (x_dtype), features before standardisation (the
+ * model's mu / sd are applied); scores_dev receives n FP32 sigmoid outputs.
+ * precision LST_PREC_F32 runs on the vector ALU, LST_PREC_BF16 on MFMA. */
+lst_status lst_score(lst_ctx *ctx, const void *X_dev, int32_t x_dtype, int64_t n,
+                     float *scores_dev, int32_t precision, void *stream);
+
+const char *lst_status_string(lst_status s);
+const char *lst_last_error(const lst_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LST_H */

@@ -1,0 +1,166 @@
+"""ctypes binding of the C ABI in include/lst.h (argument marshalling only).
+
+Every function here has the name of the C entry point it wraps. Loading fails
+loudly (RuntimeError) when the HIP library has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblst.so")
+
+LST_OK = 0
+LST_E_INVAL = -1
+LST_E_STATE = -2
+LST_E_CAPACITY = -3
+LST_E_HIP = -4
+LST_E_NOMEM = -5
+
+LST_MODE_DNN = 0
+LST_MODE_PRE_DNN = 1
+LST_PREC_F32 = 0
+LST_PREC_BF16 = 1
+LST_ASYNC = 1
+LST_DTYPE_F32 = 0
+LST_DTYPE_BF16 = 1
+LST_COUNTS_LEN = 8
+LST_COUNT_ERR = 4
+LST_COUNT_MAXCAND = 5
+N_FEATURES = 42
+
+EXPORTED = ("lst_create", "lst_destroy", "lst_load_geometry", "lst_load_model", "lst_workspace_size",
+            "lst_build_objects", "lst_build_objects_batched", "lst_score", "lst_status_string",
+            "lst_last_error")
+
+
+class LstHits(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("sensor", C.c_void_p),
+                ("n", C.c_int64)]
+
+
+class LstCaps(C.Structure):
+    _fields_ = [("hits", C.c_int64), ("events", C.c_int64), ("md", C.c_int64), ("ls", C.c_int64),
+                ("t3", C.c_int64), ("t5", C.c_int64), ("cand", C.c_int64)]
+
+
+class LstObjects(C.Structure):
+    _fields_ = [("md_hits", C.c_void_p), ("ls_md", C.c_void_p), ("t3_ls", C.c_void_p),
+                ("t5_t3", C.c_void_p), ("t5_score", C.c_void_p), ("t5_chi2_rphi", C.c_void_p),
+                ("t5_chi2_rz", C.c_void_p), ("t5_feat", C.c_void_p), ("counts_dev", C.c_void_p),
+                ("n_md", C.c_int64), ("n_ls", C.c_int64), ("n_t3", C.c_int64), ("n_t5", C.c_int64)]
+
+
+class LstOptions(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("precision", C.c_int32), ("score_min", C.c_float),
+                ("flags", C.c_int32)]
+
+
+class LstError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"LST HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build() or paper_2403_13166_amd/build_lib.py)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.lst_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.lst_create.restype = i32
+        L.lst_destroy.argtypes = [vp]
+        L.lst_destroy.restype = None
+        L.lst_load_geometry.argtypes = [vp, C.c_char_p, C.c_size_t]
+        L.lst_load_geometry.restype = i32
+        L.lst_load_model.argtypes = [vp, C.c_char_p, C.c_size_t]
+        L.lst_load_model.restype = i32
+        L.lst_workspace_size.argtypes = [vp, C.POINTER(LstCaps), C.POINTER(C.c_size_t)]
+        L.lst_workspace_size.restype = i32
+        L.lst_build_objects.argtypes = [vp, C.POINTER(LstHits), C.POINTER(LstOptions), C.POINTER(LstCaps),
+                                        C.POINTER(LstObjects), vp, C.c_size_t, vp]
+        L.lst_build_objects.restype = i32
+        L.lst_build_objects_batched.argtypes = [vp, C.POINTER(LstHits), vp, i32, C.POINTER(LstOptions),
+                                                C.POINTER(LstCaps), C.POINTER(LstObjects), vp, vp,
+                                                C.c_size_t, vp]
+        L.lst_build_objects_batched.restype = i32
+        L.lst_score.argtypes = [vp, vp, i32, i64, vp, i32, vp]
+        L.lst_score.restype = i32
+        L.lst_status_string.argtypes = [i32]
+        L.lst_status_string.restype = C.c_char_p
+        L.lst_last_error.argtypes = [vp]
+        L.lst_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(ctx, status: int, what: str):
+    if status != LST_OK:
+        detail = lib().lst_last_error(ctx).decode() if ctx else ""
+        raise LstError(status, f"{what}: {lib().lst_status_string(status).decode()}: {detail}")
+
+
+def lst_create(device: int = 0):
+    h = C.c_void_p()
+    _check(None, lib().lst_create(int(device), C.byref(h)), "lst_create")
+    return h
+
+
+def lst_destroy(ctx) -> None:
+    lib().lst_destroy(ctx)
+
+
+def lst_load_geometry(ctx, blob: bytes) -> None:
+    _check(ctx, lib().lst_load_geometry(ctx, blob, len(blob)), "lst_load_geometry")
+
+
+def lst_load_model(ctx, blob: bytes) -> None:
+    _check(ctx, lib().lst_load_model(ctx, blob, len(blob)), "lst_load_model")
+
+
+def lst_workspace_size(ctx, caps: LstCaps) -> int:
+    n = C.c_size_t()
+    _check(ctx, lib().lst_workspace_size(ctx, C.byref(caps), C.byref(n)), "lst_workspace_size")
+    return int(n.value)
+
+
+def lst_build_objects(ctx, hits: LstHits, opts: LstOptions, caps: LstCaps, out: LstObjects, ws: int,
+                      ws_bytes: int, stream: int, check: bool = True) -> int:
+    st = lib().lst_build_objects(ctx, C.byref(hits), C.byref(opts), C.byref(caps), C.byref(out), ws,
+                                 ws_bytes, stream)
+    if check:
+        _check(ctx, st, "lst_build_objects")
+    return st
+
+
+def lst_build_objects_batched(ctx, hits: LstHits, event_offsets_dev: int, n_events: int, opts: LstOptions,
+                              caps: LstCaps, out: LstObjects, event_obj_offsets_dev: int, ws: int,
+                              ws_bytes: int, stream: int, check: bool = True) -> int:
+    st = lib().lst_build_objects_batched(ctx, C.byref(hits), event_offsets_dev, int(n_events), C.byref(opts),
+                                         C.byref(caps), C.byref(out), event_obj_offsets_dev, ws, ws_bytes,
+                                         stream)
+    if check:
+        _check(ctx, st, "lst_build_objects_batched")
+    return st
+
+
+def lst_score(ctx, X_dev: int, x_dtype: int, n: int, scores_dev: int, precision: int, stream: int) -> None:
+    _check(ctx, lib().lst_score(ctx, X_dev, int(x_dtype), int(n), scores_dev, int(precision), stream),
+           "lst_score")
+
+
+def lst_status_string(status: int) -> str:
+    return lib().lst_status_string(int(status)).decode()
+
+
+def lst_last_error(ctx) -> str:
+    return lib().lst_last_error(ctx).decode()

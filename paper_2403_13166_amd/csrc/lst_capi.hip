@@ -1,0 +1,358 @@
+// C ABI of the LST object builder: context, geometry / model loading,
+// workspace layout and the build / score entry points declared in lst.h.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lst.h"
+#include "lst_internal.h"
+
+using namespace lst;
+
+struct lst_ctx {
+    int device = 0;
+    std::string err;
+    // geometry
+    bool geom_loaded = false;
+    int32_t n_mod = 0, n_barrel = 0, n_map = 0;
+    CutParams cp{};
+    ModConst *d_mod = nullptr;
+    int32_t *d_map_off = nullptr, *d_map_tgt = nullptr;
+    // model
+    bool model_loaded = false;
+    float *d_model = nullptr;
+    ModelDev md{};
+};
+
+static lst_status fail(lst_ctx *c, lst_status s, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(ctx, LST_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" {
+
+const char *lst_status_string(lst_status s) {
+    switch (s) {
+        case LST_OK: return "ok";
+        case LST_E_INVAL: return "invalid argument";
+        case LST_E_STATE: return "geometry or model not loaded";
+        case LST_E_CAPACITY: return "capacity exceeded";
+        case LST_E_HIP: return "HIP runtime error";
+        case LST_E_NOMEM: return "out of device memory";
+        default: return "unknown status";
+    }
+}
+
+const char *lst_last_error(const lst_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+lst_status lst_create(int device, lst_ctx **out) {
+    if (!out) return LST_E_INVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LST_E_INVAL;
+    if (hipSetDevice(device) != hipSuccess) return LST_E_HIP;
+    lst_ctx *c = new lst_ctx();
+    c->device = device;
+    *out = c;
+    return LST_OK;
+}
+
+static void free_geom(lst_ctx *c) {
+    if (c->d_mod) (void)hipFree(c->d_mod);
+    if (c->d_map_off) (void)hipFree(c->d_map_off);
+    if (c->d_map_tgt) (void)hipFree(c->d_map_tgt);
+    c->d_mod = nullptr; c->d_map_off = c->d_map_tgt = nullptr;
+    c->geom_loaded = false;
+}
+
+void lst_destroy(lst_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    free_geom(c);
+    if (c->d_model) (void)hipFree(c->d_model);
+    delete c;
+}
+
+static uint32_t rd32(const unsigned char *b) {
+    uint32_t v;
+    memcpy(&v, b, 4);
+    return v;
+}
+
+// transverse arc length from the beam line to radius r at half-curvature c
+static double arc_len(double c, double r) {
+    double x = c * r;
+    if (x < 1e-4) return r * (1.0 + x * x / 6.0);
+    if (x >= 1.0) x = 1.0;
+    return asin(x) / c;
+}
+
+lst_status lst_load_geometry(lst_ctx *c, const void *blob, size_t nbytes) {
+    if (!c || !blob) return LST_E_INVAL;
+    const unsigned char *b = (const unsigned char *)blob;
+    if (nbytes < 152 || memcmp(b, "LSTG", 4) != 0 || rd32(b + 4) != 1)
+        return fail(c, LST_E_INVAL, "geometry blob: bad magic or version");
+    uint32_t nm = rd32(b + 8), nb = rd32(b + 12), nmap = rd32(b + 16), npar = rd32(b + 20);
+    if (npar != 16) return fail(c, LST_E_INVAL, "geometry blob: expected 16 parameters");
+    size_t need = 152 + (size_t)nm * 64 + ((size_t)nm + 1) * 4 + (size_t)nmap * 4;
+    if (nbytes != need || nm == 0 || nm > (1u << 24))
+        return fail(c, LST_E_INVAL, "geometry blob: size %zu, expected %zu", nbytes, need);
+    double prm[16];
+    memcpy(prm, b + 24, sizeof(prm));
+    // parameters: k_b, pt_min, z_lum, n_sigma, sigma_rphi, sigma_z, sigma_r, gap,
+    //             chi2_rz_max, chi2_rphi_max, md_e2_slack, ls3_slack
+    const double kb = prm[0], cmax = kb / (2.0 * prm[1]), ns = prm[3], srphi = prm[4];
+    CutParams p{};
+    p.kb = (float)kb; p.cmax = (float)cmax; p.zlum = (float)prm[2]; p.nsig = (float)ns;
+    p.srphi = (float)srphi; p.sz = (float)prm[5]; p.sr = (float)prm[6]; p.e2slack = (float)prm[10];
+    p.ls3slack = (float)prm[11]; p.chi2rz = (float)prm[8]; p.chi2rphi = (float)prm[9];
+    p.kb_d = kb; p.cmax_d = cmax; p.zlum_d = prm[2]; p.nsig_d = ns; p.srphi_d = srphi;
+    p.sz_d = prm[5]; p.sr_d = prm[6];
+    std::vector<ModConst> mods(nm);
+    const unsigned char *r = b + 152;
+    for (uint32_t m = 0; m < nm; ++m, r += 64) {
+        int32_t kind, layer;
+        double pp[6];
+        memcpy(&kind, r, 4);
+        memcpy(&layer, r + 4, 4);
+        memcpy(pp, r + 16, 48);
+        ModConst mc{};
+        mc.kind = kind; mc.layer = layer;
+        mc.gap = (float)fabs(pp[1] - pp[0]);
+        if (kind == 0) {
+            // barrel MD thresholds: largest bend of a beam-line track with
+            // |c| <= c_max between the two sensors, plus resolution; r-z ratios
+            const double rlo = pp[0], rup = pp[1];
+            mc.b1_t = (float)(asin(cmax * rup) - asin(cmax * rlo)
+                              + ns * srphi * sqrt(1.0 / (rlo * rlo) + 1.0 / (rup * rup)));
+            mc.rho0 = (float)((rup - rlo) / rlo);
+            const double slo = arc_len(cmax, rlo);
+            mc.rho1 = (float)((arc_len(cmax, rup) - slo) / slo);
+        } else if (kind != 1) {
+            return fail(c, LST_E_INVAL, "geometry blob: module %u has kind %d", m, kind);
+        }
+        mods[m] = mc;
+    }
+    std::vector<int32_t> moff(nm + 1), mtgt(nmap ? nmap : 1);
+    for (uint32_t i = 0; i <= nm; ++i) moff[i] = (int32_t)rd32(r + 4 * i);
+    const unsigned char *t = r + 4 * ((size_t)nm + 1);
+    for (uint32_t i = 0; i < nmap; ++i) {
+        mtgt[i] = (int32_t)rd32(t + 4 * i);
+        if (mtgt[i] < 0 || (uint32_t)mtgt[i] >= nm) return fail(c, LST_E_INVAL, "module map target out of range");
+    }
+    if ((uint32_t)moff[nm] != nmap) return fail(c, LST_E_INVAL, "module map offsets inconsistent");
+    for (uint32_t i = 0; i < nm; ++i)
+        if (moff[i + 1] < moff[i]) return fail(c, LST_E_INVAL, "module map offsets not monotone");
+    HIP_TRY(c, hipSetDevice(c->device));
+    free_geom(c);
+    if (hipMalloc(&c->d_mod, sizeof(ModConst) * nm) != hipSuccess ||
+        hipMalloc(&c->d_map_off, sizeof(int32_t) * (nm + 1)) != hipSuccess ||
+        hipMalloc(&c->d_map_tgt, sizeof(int32_t) * mtgt.size()) != hipSuccess) {
+        free_geom(c);
+        return fail(c, LST_E_NOMEM, "geometry tables");
+    }
+    HIP_TRY(c, hipMemcpy(c->d_mod, mods.data(), sizeof(ModConst) * nm, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_map_off, moff.data(), sizeof(int32_t) * (nm + 1), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_map_tgt, mtgt.data(), sizeof(int32_t) * mtgt.size(), hipMemcpyHostToDevice));
+    c->n_mod = (int32_t)nm; c->n_barrel = (int32_t)nb; c->n_map = (int32_t)nmap;
+    c->cp = p;
+    c->geom_loaded = true;
+    return LST_OK;
+}
+
+lst_status lst_load_model(lst_ctx *c, const void *blob, size_t nbytes) {
+    if (!c || !blob) return LST_E_INVAL;
+    const unsigned char *b = (const unsigned char *)blob;
+    if (nbytes < 24 || memcmp(b, "LSTM", 4) != 0 || rd32(b + 4) != 1)
+        return fail(c, LST_E_INVAL, "model blob: bad magic or version");
+    if (rd32(b + 8) != kNFeat || rd32(b + 12) != kH1 || rd32(b + 16) != kH2)
+        return fail(c, LST_E_INVAL, "model blob: expected a %d-%d-%d-1 network", kNFeat, kH1, kH2);
+    const size_t nf = 2 * kNFeat + kH1 * kNFeat + kH1 + kH2 * kH1 + kH2 + kH2 + 1;
+    if (nbytes != 24 + 4 * nf) return fail(c, LST_E_INVAL, "model blob: size %zu", nbytes);
+    std::vector<float> w(nf);
+    memcpy(w.data(), b + 24, 4 * nf);
+    for (int k = 0; k < kNFeat; ++k)
+        if (!(w[kNFeat + k] > 0.0f)) return fail(c, LST_E_INVAL, "model blob: non-positive scale");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (c->d_model) { (void)hipFree(c->d_model); c->d_model = nullptr; c->model_loaded = false; }
+    if (hipMalloc(&c->d_model, 4 * nf) != hipSuccess) return fail(c, LST_E_NOMEM, "model");
+    HIP_TRY(c, hipMemcpy(c->d_model, w.data(), 4 * nf, hipMemcpyHostToDevice));
+    float *d = c->d_model;
+    ModelDev m{};
+    m.mu = d; d += kNFeat;
+    m.sd = d; d += kNFeat;
+    m.W1 = d; d += kH1 * kNFeat;
+    m.b1 = d; d += kH1;
+    m.W2 = d; d += kH2 * kH1;
+    m.b2 = d; d += kH2;
+    m.w3 = d; d += kH2;
+    m.b3 = w[nf - 1];
+    c->md = m;
+    c->model_loaded = true;
+    return LST_OK;
+}
+
+// Carve the workspace; with base == nullptr only the size is computed.
+static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const int64_t nsens = 2 * (int64_t)c->n_mod, nmod = c->n_mod;
+    const int64_t ev = k->events > 0 ? k->events : 1;
+    const int64_t md = k->md > 0 ? k->md : 1;
+    const int64_t max_tiles = (k->cand + kTile - 1) / kTile + 1;
+    int64_t anchors = ev * nmod;
+    if (md > anchors) anchors = md;
+    Work x{};
+    x.cap_hits = k->hits; x.cap_ev = ev; x.cap_md = md; x.cap_ls = k->ls; x.cap_t3 = k->t3;
+    x.cap_t5 = k->t5; x.cap_cand = k->cand; x.max_tiles = max_tiles; x.n_anchor_cap = anchors;
+    x.bin_cnt = (int32_t *)take(4 * ev * nsens);
+    x.bin_off = (int64_t *)take(8 * (ev * nsens + 1));
+    x.bin_hit = (float4 *)take(16 * (k->hits > 0 ? k->hits : 1));
+    x.cand_off = (int64_t *)take(8 * (anchors + 1));
+    x.scan_part = (int64_t *)take(8 * (kScanBlocks + 1));
+    x.tile_anchor = (int32_t *)take(4 * (max_tiles + 1));
+    x.tile_state = (unsigned long long *)take(8 * max_tiles);
+    x.ticket = (uint32_t *)take(32);
+    x.md_a = (float4 *)take(16 * md);
+    x.md_o = (float2 *)take(8 * md);
+    x.md_mod_off = (int64_t *)take(8 * (ev * nmod + 1));
+    x.rsum = (int32_t *)take(4 * ev * nmod);
+    x.rpref = (int32_t *)take(4 * ev * (c->n_map > 0 ? c->n_map : 1));
+    x.ls_off = (int64_t *)take(8 * (md + 1));
+    x.lsT_off = (int64_t *)take(8 * (md + 1));
+    x.lsT_idx = (int32_t *)take(4 * (k->ls > 0 ? k->ls : 1));
+    x.bucket_cnt = (int32_t *)take(4 * md);
+    x.t3_mds = (int4 *)take(16 * (k->t3 > 0 ? k->t3 : 1));
+    x.t3i_off = (int64_t *)take(8 * (md + 1));
+    x.t3i_idx = (int32_t *)take(4 * (k->t3 > 0 ? k->t3 : 1));
+    x.t3o_off = (int64_t *)take(8 * (md + 1));
+    x.t3o_idx = (int32_t *)take(4 * (k->t3 > 0 ? k->t3 : 1));
+    x.t5_feat = (float *)take(4 * kNFeat * (k->t5 > 0 ? k->t5 : 1));
+    x.ev_off = (int64_t *)take(16);
+    if (w) *w = x;
+    return off;
+}
+
+static lst_status check_caps(lst_ctx *c, const lst_caps *k) {
+    if (!k) return fail(c, LST_E_INVAL, "null caps");
+    if (k->hits < 0 || k->events < 1 || k->md < 1 || k->ls < 1 || k->t3 < 1 || k->t5 < 1 || k->cand < 1)
+        return fail(c, LST_E_INVAL, "capacities must be positive");
+    const int64_t lim = (int64_t)1 << 31;
+    if (k->hits >= lim || k->md >= lim || k->ls >= lim || k->t3 >= lim || k->t5 >= lim ||
+        k->events * 2 * (int64_t)c->n_mod >= lim || k->cand > ((int64_t)1 << 40))
+        return fail(c, LST_E_INVAL, "capacity beyond the 32-bit object index range");
+    return LST_OK;
+}
+
+lst_status lst_workspace_size(const lst_ctx *c, const lst_caps *k, size_t *bytes) {
+    if (!c || !bytes) return LST_E_INVAL;
+    if (!c->geom_loaded) return LST_E_STATE;
+    lst_status s = check_caps(const_cast<lst_ctx *>(c), k);
+    if (s != LST_OK) return s;
+    *bytes = layout(c, k, nullptr, nullptr);
+    return LST_OK;
+}
+
+static lst_status build_common(lst_ctx *c, const lst_hits *h, const int64_t *ev_off, int32_t n_ev,
+                               const lst_options *opt, const lst_caps *k, lst_objects *out,
+                               int64_t *ev_obj_off, void *ws, size_t ws_bytes, void *stream, bool single) {
+    if (!c) return LST_E_INVAL;
+    if (!c->geom_loaded || !c->model_loaded) return fail(c, LST_E_STATE, "load geometry and model first");
+    if (!h || !opt || !out || !ws) return fail(c, LST_E_INVAL, "null argument");
+    lst_status s = check_caps(c, k);
+    if (s != LST_OK) return s;
+    if (h->n < 0 || h->n > k->hits) return fail(c, LST_E_INVAL, "hit count %lld exceeds caps.hits", (long long)h->n);
+    if (h->n > 0 && (!h->x || !h->y || !h->z || !h->sensor)) return fail(c, LST_E_INVAL, "null hit array");
+    if (n_ev < 1 || n_ev > k->events) return fail(c, LST_E_INVAL, "event count %d outside [1, caps.events]", n_ev);
+    if (!single && !ev_off) return fail(c, LST_E_INVAL, "null event offsets");
+    if (!out->md_hits || !out->ls_md || !out->t3_ls || !out->t5_t3 || !out->t5_score || !out->t5_chi2_rphi ||
+        !out->t5_chi2_rz || !out->counts_dev)
+        return fail(c, LST_E_INVAL, "null output array");
+    if (opt->mode != LST_MODE_DNN && opt->mode != LST_MODE_PRE_DNN) return fail(c, LST_E_INVAL, "bad mode");
+    if (opt->precision != LST_PREC_F32 && opt->precision != LST_PREC_BF16)
+        return fail(c, LST_E_INVAL, "bad precision");
+    if (((uintptr_t)ws & 255) != 0) return fail(c, LST_E_INVAL, "workspace must be 256-byte aligned");
+    size_t need = layout(c, k, nullptr, nullptr);
+    if (ws_bytes < need) return fail(c, LST_E_INVAL, "workspace %zu bytes, need %zu", ws_bytes, need);
+    HIP_TRY(c, hipSetDevice(c->device));
+    Work w{};
+    layout(c, k, (char *)ws, &w);
+    hipStream_t st = (hipStream_t)stream;
+    if (single) {
+        HIP_TRY(c, set_single_event(w.ev_off, h->n, st));
+        ev_off = w.ev_off;
+    }
+    RunArgs a{};
+    a.g.mod = c->d_mod; a.g.map_off = c->d_map_off; a.g.map_tgt = c->d_map_tgt;
+    a.g.n_mod = c->n_mod; a.g.n_sens = 2 * c->n_mod; a.g.n_map = c->n_map;
+    a.p = c->cp; a.m = c->md;
+    a.x = h->x; a.y = h->y; a.z = h->z; a.sensor = h->sensor; a.n_hits = h->n;
+    a.ev_off = ev_off; a.n_ev = n_ev;
+    a.mode = opt->mode; a.precision = opt->precision; a.score_min = opt->score_min;
+    a.ev_obj_off = ev_obj_off;
+    Outputs o{};
+    o.md_hits = (int2 *)out->md_hits; o.ls_md = (int2 *)out->ls_md; o.t3_ls = (int2 *)out->t3_ls;
+    o.t5_t3 = (int2 *)out->t5_t3; o.t5_score = out->t5_score; o.t5_chi2_rphi = out->t5_chi2_rphi;
+    o.t5_chi2_rz = out->t5_chi2_rz; o.t5_feat = out->t5_feat; o.counts = out->counts_dev;
+    HIP_TRY(c, run_pipeline(a, w, o, st));
+    if (opt->flags & LST_ASYNC) return LST_OK;
+    int64_t cnt[LST_COUNTS_LEN];
+    HIP_TRY(c, hipMemcpyAsync(cnt, out->counts_dev, sizeof(cnt), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    out->n_md = cnt[0]; out->n_ls = cnt[1]; out->n_t3 = cnt[2]; out->n_t5 = cnt[3];
+    if (cnt[LST_COUNT_ERR] & 1) return fail(c, LST_E_INVAL, "sensor id out of range in the hits");
+    if ((cnt[LST_COUNT_ERR] & 2) || cnt[0] > k->md || cnt[1] > k->ls || cnt[2] > k->t3 || cnt[3] > k->t5)
+        return fail(c, LST_E_CAPACITY, "capacity exceeded: md %lld/%lld ls %lld/%lld t3 %lld/%lld t5 %lld/%lld cand %lld/%lld",
+                    (long long)cnt[0], (long long)k->md, (long long)cnt[1], (long long)k->ls, (long long)cnt[2],
+                    (long long)k->t3, (long long)cnt[3], (long long)k->t5, (long long)cnt[LST_COUNT_MAXCAND],
+                    (long long)k->cand);
+    return LST_OK;
+}
+
+lst_status lst_build_objects(lst_ctx *c, const lst_hits *h, const lst_options *opt, const lst_caps *k,
+                             lst_objects *out, void *ws, size_t ws_bytes, void *stream) {
+    return build_common(c, h, nullptr, 1, opt, k, out, nullptr, ws, ws_bytes, stream, true);
+}
+
+lst_status lst_build_objects_batched(lst_ctx *c, const lst_hits *h, const int64_t *ev_off, int32_t n_ev,
+                                     const lst_options *opt, const lst_caps *k, lst_objects *out,
+                                     int64_t *ev_obj_off, void *ws, size_t ws_bytes, void *stream) {
+    return build_common(c, h, ev_off, n_ev, opt, k, out, ev_obj_off, ws, ws_bytes, stream, false);
+}
+
+lst_status lst_score(lst_ctx *c, const void *X, int32_t x_dtype, int64_t n, float *scores, int32_t precision,
+                     void *stream) {
+    if (!c) return LST_E_INVAL;
+    if (!c->model_loaded) return fail(c, LST_E_STATE, "load a model first");
+    if (n < 0 || (n > 0 && (!X || !scores))) return fail(c, LST_E_INVAL, "bad score arguments");
+    if (x_dtype != LST_DTYPE_F32 && x_dtype != LST_DTYPE_BF16) return fail(c, LST_E_INVAL, "bad x_dtype");
+    if (precision != LST_PREC_F32 && precision != LST_PREC_BF16) return fail(c, LST_E_INVAL, "bad precision");
+    if (n == 0) return LST_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, run_score(c->md, X, x_dtype, n, scores, precision, (hipStream_t)stream));
+    return LST_OK;
+}
+
+}  // extern "C"

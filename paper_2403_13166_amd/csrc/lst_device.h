@@ -1,0 +1,360 @@
+// Device-side data layout and arithmetic of the LST object builder (gfx950).
+//
+// Cuts (paper Sec. 1: "pre-defined quality selections ... consistency with a
+// continuous, helical trajectory") are evaluated in FP32; the paper gives no
+// formulas, so they follow this project's reading, derived from the helix of a
+// track from the beam line: half-curvature c = 1 / (2R), radius along the arc
+// r(s) = sin(c s) / c, z linear in s. Every cut is "pass iff v <= t" written
+// as !(v <= t) -> reject, so NaN rejects. The quintuplet fits and the T5-DNN
+// features (Sec. 2) are evaluated in FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lst {
+
+constexpr int kNFeat = 42;
+constexpr int kH1 = 32;
+constexpr int kH2 = 32;
+constexpr int kTile = 256;          // candidates per compaction tile (= block size)
+
+// ------------------------------------------------------------------ layout
+
+// Per-module constants, derived on the host from the FP64 geometry.
+struct ModConst {
+    int32_t kind;      // 0 barrel, 1 endcap
+    int32_t layer;     // 1..6 barrel, 7..11 disks
+    float b1_t;        // barrel: MD bend threshold (envelope + resolution)
+    float rho0;        // barrel: (r_up - r_lo) / r_lo
+    float rho1;        // barrel: (S(r_up) - S(r_lo)) / S(r_lo) at c_max
+    float gap;         // sensor separation
+    float pad0, pad1;
+};
+
+struct CutParams {
+    float kb, cmax, zlum, nsig, srphi, sz, sr, e2slack, ls3slack, chi2rz, chi2rphi;
+    double kb_d, cmax_d, zlum_d, nsig_d, srphi_d, sz_d, sr_d;
+};
+
+struct ModelDev {
+    const float *mu, *sd, *W1, *b1, *W2, *b2, *w3;
+    float b3;
+};
+
+// Batch-wide geometry handles.
+struct GeomDev {
+    const ModConst *mod;
+    const int32_t *map_off;   // [n_mod + 1]
+    const int32_t *map_tgt;   // [n_map]
+    int32_t n_mod, n_sens, n_map;
+};
+
+// ------------------------------------------------------------ small helpers
+
+__device__ __forceinline__ float kahan_det(float a, float b, float c, float d) {
+    // a*d - b*c with Kahan's FMA compensation (error ~1 ulp of the result)
+    float w = b * c;
+    float e = __builtin_fmaf(-b, c, w);
+    float f = __builtin_fmaf(a, d, -w);
+    return f + e;
+}
+
+__device__ __forceinline__ float cross2(float ax, float ay, float bx, float by) {
+    return kahan_det(ax, ay, bx, by);
+}
+
+__device__ __forceinline__ float arc_len_f(float c, float r) {
+    float x = c * r;
+    if (x < 1e-4f) return r * (1.0f + x * x * (1.0f / 6.0f));
+    if (x >= 1.0f) x = 1.0f;
+    return asinf(x) / c;
+}
+
+__device__ __forceinline__ double arc_len_d(double c, double r) {
+    double x = c * r;
+    if (x < 1e-4) return r * (1.0 + x * x / 6.0);
+    if (x >= 1.0) x = 1.0;
+    return asin(x) / c;
+}
+
+struct P3 { float x, y, z; };
+
+// ------------------------------------------------------------ MD cuts (FP32)
+// anchor hit i, other hit j on module mc.
+__device__ __forceinline__ bool md_pass(const ModConst &mc, const CutParams &p, P3 hi, P3 hj) {
+    float cr = cross2(hi.x, hi.y, hj.x, hj.y);
+    float dt = hi.x * hj.x + hi.y * hj.y;
+    float ang = fabsf(atan2f(cr, dt));
+    if (mc.kind == 0) {
+        if (!(ang <= mc.b1_t)) return false;
+        float a0 = (hi.z - p.zlum) * mc.rho0, a1 = (hi.z + p.zlum) * mc.rho0;
+        float b0 = (hi.z - p.zlum) * mc.rho1, b1 = (hi.z + p.zlum) * mc.rho1;
+        float lo = fminf(fminf(a0, a1), fminf(b0, b1));
+        float hv = fmaxf(fmaxf(a0, a1), fmaxf(b0, b1));
+        float v = fabsf((hj.z - hi.z) - 0.5f * (lo + hv));
+        float t = 0.5f * (hv - lo) + p.nsig * 1.41421356f * p.sz;
+        return v <= t;
+    }
+    float ri = sqrtf(hi.x * hi.x + hi.y * hi.y), rj = sqrtf(hj.x * hj.x + hj.y * hj.y);
+    float az = fabsf(hi.z);
+    float xm = fminf(p.cmax * ri, 1.0f);
+    float asx = asinf(xm);
+    float cxm = sqrtf(1.0f - xm * xm);
+    float t1 = mc.gap * asx / (az - p.zlum)
+             + p.nsig * (p.srphi * sqrtf(1.0f / (ri * ri) + 1.0f / (rj * rj))
+                         + mc.gap * p.cmax * p.sr / ((az - p.zlum) * cxm));
+    if (!(ang <= t1)) return false;
+    float dr = ((hj.x - hi.x) * (hj.x + hi.x) + (hj.y - hi.y) * (hj.y + hi.y)) / (ri + rj);
+    float f = (xm < 1e-8f) ? 1.0f : cxm * asx / xm;
+    float lo = mc.gap * ri * f / (az + p.zlum), hv = mc.gap * ri / (az - p.zlum);
+    float v = fabsf(dr - 0.5f * (lo + hv));
+    float t = 0.5f * (hv - lo) + p.nsig * 1.41421356f * p.sr + p.e2slack;
+    return v <= t;
+}
+
+// ---------------------------------------------- anchor-pair cuts (FP32)
+// Beam-line circle through anchors X (inner) and Y (outer): curvature within
+// c_max plus resolution, ordering s_X < s_Y, and z0 pointing into the
+// luminous region. Returns pass; c_out = curvature, sgn_out = bending side.
+__device__ __forceinline__ bool pair_pass(const CutParams &p, P3 X, bool endX, P3 Y, bool endY,
+                                          float &c_out, float &sgn_out) {
+    float rX = sqrtf(X.x * X.x + X.y * X.y), rY = sqrtf(Y.x * Y.x + Y.y * Y.y);
+    float dx = Y.x - X.x, dy = Y.y - X.y;
+    float dl = sqrtf(dx * dx + dy * dy);
+    float cr = cross2(X.x, X.y, Y.x, Y.y);
+    float c = fabsf(cr) / (rX * rY * dl);
+    float srX = endX ? p.sr : 0.0f, srY = endY ? p.sr : 0.0f;
+    float szX = endX ? 0.0f : p.sz, szY = endY ? 0.0f : p.sz;
+    float sc = sqrtf(p.srphi * p.srphi * (1.0f / (rX * rX) + 1.0f / (rY * rY))
+                     + p.cmax * p.cmax * (srX * srX + srY * srY)) / dl;
+    c_out = c;
+    sgn_out = cr < 0.0f ? -1.0f : 1.0f;
+    if (!(c <= p.cmax + p.nsig * sc)) return false;
+    float cp = fminf(c, p.cmax);
+    float sX = arc_len_f(cp, rX), sY = arc_len_f(cp, rY);
+    if (!(sX < sY)) return false;
+    float ds = sY - sX;
+    float k = (Y.z - X.z) / ds;
+    float z0 = X.z - sX * k;
+    float a = sY * szX, b = sX * szY, e = sY * srX, f = sX * srY;
+    float var = (a * a + b * b + k * k * (e * e + f * f)) / (ds * ds);
+    return fabsf(z0) <= p.zlum + p.nsig * sqrtf(var);
+}
+
+// MD direction: the chord between the MD's hits follows the track direction at
+// the chord midpoint (angle asin(c'|M|) from radial, toward the bending side).
+__device__ __forceinline__ bool md_dir_pass(const CutParams &p, P3 hi, float ox, float oy, float cp,
+                                            float sgn) {
+    float dx = ox - hi.x, dy = oy - hi.y;
+    float mx = 0.5f * (hi.x + ox), my = 0.5f * (hi.y + oy);
+    float m = sqrtf(mx * mx + my * my);
+    float ux = mx / m, uy = my / m;
+    float s = fminf(cp * m, 1.0f);
+    float cb = sqrtf(1.0f - s * s);
+    float tx = cb * ux - sgn * s * uy;
+    float ty = cb * uy + sgn * s * ux;
+    float v = fabsf(atan2f(tx * dy - ty * dx, tx * dx + ty * dy));
+    float t = p.nsig * 1.41421356f * p.srphi / sqrtf(dx * dx + dy * dy) + p.ls3slack;
+    return v <= t;
+}
+
+// --------------------------------------------------- quintuplet fits (FP64)
+
+struct Fit5 {
+    double xm, ym, A, B, C, D;    // natural-form circle over centred coordinates, B^2+C^2-4AD = 1
+    double R, chi2_rphi;
+    double t, z0, chi2_rz;
+};
+
+__device__ __forceinline__ double circle_distance(double A, double B, double C, double D, double u,
+                                                  double v) {
+    double P = A * (u * u + v * v) + B * u + C * v + D;
+    return 2.0 * P / (1.0 + sqrt(1.0 + 4.0 * A * P));
+}
+
+// Weighted Taubin (1991) circle fit of 5 points in the frame of the chord from
+// the first to the last point: smallest root of the characteristic cubic of
+// the generalised eigenproblem by Newton from 0, null vector as the largest
+// cross product of two rows; straight lines give A = 0.
+__device__ inline void circle_fit5(const double *x, const double *y, const double *sig, Fit5 &f) {
+    double W = 0, xm = 0, ym = 0;
+    double w[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { w[i] = 1.0 / (sig[i] * sig[i]); W += w[i]; xm += w[i] * x[i]; ym += w[i] * y[i]; }
+    xm /= W; ym /= W;
+    double cx = x[4] - x[0], cy = y[4] - y[0], cl = sqrt(cx * cx + cy * cy);
+    double ca = cl > 0 ? cx / cl : 1.0, sa = cl > 0 ? cy / cl : 0.0;
+    double u[5], v[5];
+    double Mxx = 0, Myy = 0, Mxy = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        double wi = w[i] / W;
+        double u0 = x[i] - xm, v0 = y[i] - ym;
+        u[i] = ca * u0 + sa * v0; v[i] = -sa * u0 + ca * v0;
+        Mxx += wi * u[i] * u[i]; Myy += wi * v[i] * v[i]; Mxy += wi * u[i] * v[i];
+    }
+    double Mz = Mxx + Myy;
+    double Mxz = 0, Myz = 0, varz = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        double wi = w[i] / W;
+        double zt = u[i] * u[i] + v[i] * v[i] - Mz;
+        Mxz += wi * u[i] * zt; Myz += wi * v[i] * zt; varz += wi * zt * zt;
+    }
+    double cov = Mxx * Myy - Mxy * Mxy;
+    double c3 = 4.0 * Mz;
+    double c2 = -4.0 * Mz * Mz - varz;
+    double c1 = varz * Mz + 4.0 * cov * Mz - Mxz * Mxz - Myz * Myz;
+    double c0 = Mxz * (Mxz * Myy - Myz * Mxy) + Myz * (Myz * Mxx - Mxz * Mxy) - varz * cov;
+    double eta = 0.0, fprev = __builtin_huge_val();
+    for (int it = 0; it < 32; ++it) {
+        double fv = c0 + eta * (c1 + eta * (c2 + eta * c3));
+        if (fabs(fv) >= fabs(fprev)) break;
+        fprev = fv;
+        double df = c1 + eta * (2.0 * c2 + eta * 3.0 * c3);
+        double nx = eta - fv / df;
+        if (!(nx >= 0.0)) { eta = 0.0; break; }
+        if (fabs(nx - eta) <= 1e-14 * fabs(nx)) { eta = nx; break; }
+        eta = nx;
+    }
+    double k1[3] = {varz - 4.0 * Mz * eta, Mxz, Myz};
+    double k2[3] = {Mxz, Mxx - eta, Mxy};
+    double k3[3] = {Myz, Mxy, Myy - eta};
+    double bA = 0, bB = 0, bC = 0, bn = -1.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double *a = c == 0 ? k2 : c == 1 ? k3 : k1;
+        const double *b = c == 0 ? k3 : c == 1 ? k1 : k2;
+        double v0 = a[1] * b[2] - a[2] * b[1], v1 = a[2] * b[0] - a[0] * b[2], v2 = a[0] * b[1] - a[1] * b[0];
+        double nn = v0 * v0 + v1 * v1 + v2 * v2;
+        if (nn > bn) { bn = nn; bA = v0; bB = v1; bC = v2; }
+    }
+    double A = bA, B = bB, C = bC, D = -A * Mz;
+    double S = sqrt(B * B + C * C - 4.0 * A * D);
+    A /= S; D /= S;
+    double Br = (ca * B - sa * C) / S, Cr = (sa * B + ca * C) / S;
+    f.xm = xm; f.ym = ym; f.A = A; f.B = Br; f.C = Cr; f.D = D;
+    f.R = A != 0.0 ? 0.5 / fabs(A) : __builtin_huge_val();
+    double chi2 = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        double d = circle_distance(A, Br, Cr, D, x[i] - xm, y[i] - ym) / sig[i];
+        chi2 += d * d;
+    }
+    f.chi2_rphi = chi2;
+}
+
+// Both fits of a quintuplet from its five anchors (x, y, z) and endcap flags.
+__device__ inline void t5_fit(const CutParams &p, const double *x, const double *y, const double *z,
+                              const bool *endc, Fit5 &f) {
+    double sg[5], r[5], s[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { sg[i] = endc[i] ? p.sr_d : p.srphi_d; r[i] = sqrt(x[i] * x[i] + y[i] * y[i]); }
+    circle_fit5(x, y, sg, f);
+    double cf = fabs(f.A);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) s[i] = arc_len_d(cf, r[i]);
+    if (!(s[4] > s[0])) { f.t = __builtin_nan(""); f.z0 = __builtin_nan(""); f.chi2_rz = __builtin_huge_val(); return; }
+    double kAE = fabs((z[4] - z[0]) / (s[4] - s[0]));
+#pragma unroll
+    for (int i = 0; i < 5; ++i) sg[i] = endc[i] ? p.sr_d * (kAE > 0.1 ? kAE : 0.1) : p.sz_d;
+    double Wt = 0, sm = 0, zm = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { double wi = 1.0 / (sg[i] * sg[i]); Wt += wi; sm += wi * s[i]; zm += wi * z[i]; }
+    sm /= Wt; zm /= Wt;
+    double Sss = 0, Ssz = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        double wi = 1.0 / (sg[i] * sg[i]);
+        Sss += wi * (s[i] - sm) * (s[i] - sm); Ssz += wi * (s[i] - sm) * (z[i] - zm);
+    }
+    if (!(Sss > 0)) { f.t = __builtin_nan(""); f.z0 = __builtin_nan(""); f.chi2_rz = __builtin_huge_val(); return; }
+    double t = Ssz / Sss, z0 = zm - t * sm, chi2 = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { double d = z[i] - z0 - t * s[i]; chi2 += d * d / (sg[i] * sg[i]); }
+    f.t = t; f.z0 = z0; f.chi2_rz = chi2;
+}
+
+__device__ __forceinline__ double circumradius_d(double ax, double ay, double bx, double by, double cx,
+                                                 double cy) {
+    double ab = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
+    double bc = sqrt((cx - bx) * (cx - bx) + (cy - by) * (cy - by));
+    double ca = sqrt((ax - cx) * (ax - cx) + (ay - cy) * (ay - cy));
+    double cr = (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+    return ab * bc * ca / (2.0 * fabs(cr));
+}
+
+__device__ __forceinline__ double beam_curv_d(double ax, double ay, double bx, double by) {
+    double rA = sqrt(ax * ax + ay * ay), rB = sqrt(bx * bx + by * by);
+    double dl = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
+    return fabs(ax * by - ay * bx) / (rA * rB * dl);
+}
+
+__device__ __forceinline__ double clamp_log(double v) {
+    if (!(v >= 1e-3)) v = (v != v) ? 1e6 : 1e-3;
+    if (v > 1e6) v = 1e6;
+    return log(v);
+}
+
+// The 42 DNN inputs (Sec. 2 list plus this project's additions), FP64 -> FP32,
+// before standardisation.
+__device__ inline void t5_features(const CutParams &p, const double *x, const double *y,
+                                   const double *z, const int *layer, const bool *endc,
+                                   const Fit5 &f, float *ft) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        double r = sqrt(x[i] * x[i] + y[i] * y[i]);
+        ft[6 * i + 0] = (float)r;
+        ft[6 * i + 1] = (float)atan2(y[i], x[i]);
+        ft[6 * i + 2] = (float)z[i];
+        ft[6 * i + 3] = (float)asinh(z[i] / r);
+        ft[6 * i + 4] = (float)layer[i];
+        ft[6 * i + 5] = endc[i] ? 1.0f : 0.0f;
+    }
+    double cin = beam_curv_d(x[0], y[0], x[2], y[2]);
+    double cou = beam_curv_d(x[2], y[2], x[4], y[4]);
+    ft[30] = (float)clamp_log(p.kb_d / (2.0 * cin));
+    ft[31] = (float)clamp_log(circumradius_d(x[0], y[0], x[1], y[1], x[2], y[2]));
+    ft[32] = (float)clamp_log(p.kb_d / (2.0 * cou));
+    ft[33] = (float)clamp_log(circumradius_d(x[2], y[2], x[3], y[3], x[4], y[4]));
+    ft[34] = (float)clamp_log(p.kb_d * f.R);
+    ft[35] = (float)asinh(f.t);
+    double u0 = -f.xm, v0 = -f.ym;
+    double d0 = circle_distance(f.A, f.B, f.C, f.D, u0, v0);
+    double gx = 2.0 * f.A * u0 + f.B, gy = 2.0 * f.A * v0 + f.C;
+    double dx = -gy, dy = gx;
+    if (x[0] * dx + y[0] * dy < 0) { dx = -dx; dy = -dy; }
+    ft[36] = (float)atan2(dy, dx);
+    ft[37] = (float)clamp_log(circumradius_d(x[1], y[1], x[2], y[2], x[3], y[3]));
+    ft[38] = (float)log1p(f.chi2_rphi);
+    ft[39] = (float)log1p(f.chi2_rz);
+    ft[40] = (float)fabs(d0);
+    ft[41] = (float)f.z0;
+}
+
+// T5-DNN forward pass, FP32 vector ALU (weights read with wave-uniform
+// addresses, i.e. through the scalar cache).
+__device__ inline float mlp_f32(const ModelDev &m, const float *x) {
+    float xs[kNFeat];
+#pragma unroll
+    for (int k = 0; k < kNFeat; ++k) xs[k] = (x[k] - m.mu[k]) / m.sd[k];
+    float h1[kH1];
+#pragma unroll 4
+    for (int j = 0; j < kH1; ++j) {
+        float a = m.b1[j];
+#pragma unroll
+        for (int k = 0; k < kNFeat; ++k) a = __builtin_fmaf(m.W1[j * kNFeat + k], xs[k], a);
+        h1[j] = fmaxf(a, 0.0f);
+    }
+    float o = m.b3;
+#pragma unroll 4
+    for (int j = 0; j < kH2; ++j) {
+        float a = m.b2[j];
+#pragma unroll
+        for (int k = 0; k < kH1; ++k) a = __builtin_fmaf(m.W2[j * kH1 + k], h1[k], a);
+        o = __builtin_fmaf(m.w3[j], fmaxf(a, 0.0f), o);
+    }
+    return 1.0f / (1.0f + expf(-o));
+}
+
+}  // namespace lst

@@ -1,0 +1,81 @@
+// Host-side view of the workspace and the kernel launchers of the LST pipeline.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lst.h"
+#include "lst_device.h"
+
+namespace lst {
+
+// Work-item counts used to size grids; they depend only on capacities, never
+// on data, so a whole build can be captured into a HIP graph.
+constexpr int kBlock = 256;
+constexpr int kScanBlocks = 1024;
+constexpr int kEvalBlocks = 4096;     // persistent compaction blocks (256 CUs x 16)
+constexpr int kMaxStride = 8192;      // grid cap of grid-stride kernels
+
+struct Work {
+    // capacities
+    int64_t cap_hits, cap_ev, cap_md, cap_ls, cap_t3, cap_t5, cap_cand, max_tiles;
+    int64_t n_anchor_cap;             // largest anchor count of any stage + 1
+    // hits binned by (event, sensor)
+    int32_t *bin_cnt;                 // [cap_ev * n_sens]
+    int64_t *bin_off;                 // [cap_ev * n_sens + 1]
+    float4 *bin_hit;                  // [cap_hits] x, y, z, input index (bits)
+    // per-stage scratch
+    int64_t *cand_off;                // [n_anchor_cap + 1]
+    int64_t *scan_part;               // [kScanBlocks + 1]
+    int32_t *tile_anchor;             // [max_tiles + 1]
+    unsigned long long *tile_state;   // [max_tiles]
+    uint32_t *ticket;                 // [8]
+    // MD
+    float4 *md_a;                     // [cap_md] anchor x, y, z, global module (bits)
+    float2 *md_o;                     // [cap_md] other hit x, y
+    int64_t *md_mod_off;              // [cap_ev * n_mod + 1]
+    int32_t *rsum;                    // [cap_ev * n_mod] MDs in the mapped modules
+    int32_t *rpref;                   // [cap_ev * n_map] exclusive prefix over map entries
+    // LS
+    int64_t *ls_off;                  // [cap_md + 1] CSR by inner MD
+    int64_t *lsT_off;                 // [cap_md + 1] CSR by outer MD
+    int32_t *lsT_idx;                 // [cap_ls]
+    int32_t *bucket_cnt;              // [cap_md]
+    // T3
+    int4 *t3_mds;                     // [cap_t3] MDs (A, B, C)
+    int64_t *t3i_off;                 // [cap_md + 1] T3 by inner MD
+    int32_t *t3i_idx;                 // [cap_t3]
+    int64_t *t3o_off;                 // [cap_md + 1] T3 by outer MD
+    int32_t *t3o_idx;                 // [cap_t3]
+    float *t5_feat;                   // [cap_t5][42] feature rows for the MFMA scorer
+    int64_t *ev_off;                  // [2] event offsets of a single-event call
+};
+
+struct Outputs {
+    int2 *md_hits, *ls_md, *t3_ls, *t5_t3;
+    float *t5_score, *t5_chi2_rphi, *t5_chi2_rz, *t5_feat;
+    int64_t *counts;
+};
+
+struct RunArgs {
+    GeomDev g;
+    CutParams p;
+    ModelDev m;
+    const float *x, *y, *z;
+    const int32_t *sensor;
+    int64_t n_hits;
+    const int64_t *ev_off;            // device [n_ev + 1]
+    int32_t n_ev;
+    int32_t mode, precision;
+    float score_min;
+    int64_t *ev_obj_off;              // device [4][n_ev + 1] or null
+};
+
+// Enqueue the whole object-building pipeline on `stream`.
+hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipStream_t stream);
+// Enqueue standalone scoring of n rows (f32 or bf16 input).
+hipError_t run_score(const ModelDev &m, const void *X, int dtype, int64_t n, float *out,
+                     int precision, hipStream_t stream);
+// Fill a two-entry event-offset array {0, n} on the device.
+hipError_t set_single_event(int64_t *ev_off, int64_t n, hipStream_t stream);
+
+}  // namespace lst

@@ -1,0 +1,748 @@
+// LST object-building pipeline on gfx950: hit binning, mini-doublets, line
+// segments, triplets, quintuplets (paper Table 1 steps 1-4), each stage one
+// compaction kernel over its candidate pairs.
+//
+// Every stage has the same shape:
+//   * anchors (a module for MD, an MD for LS / T3 / T5) own a contiguous range
+//     of candidate pairs (left x right lists); a device-wide exclusive scan of
+//     the per-anchor counts gives the ranges and, for every 256-candidate tile,
+//     the anchor its first candidate belongs to;
+//   * a persistent kernel takes tiles in order from a ticket counter, each
+//     thread decodes one candidate and applies the cuts, the block compacts the
+//     survivors with a wavefront ballot + LDS scan, and tiles chain their
+//     output offsets with a decoupled look-back, so the output is in candidate
+//     order (deterministic) without per-object global atomics;
+//   * CSR offsets the next stage needs are filled from the sorted outputs.
+// Grid shapes depend only on capacities, never on data, so a whole build can be
+// captured into a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include "lst_internal.h"
+
+namespace lst {
+
+// ------------------------------------------------------------- utilities
+
+__device__ __forceinline__ int64_t grid_tid() {
+    return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+}
+__device__ __forceinline__ int64_t grid_stride() { return (int64_t)gridDim.x * blockDim.x; }
+
+__device__ __forceinline__ int64_t dev_count(const int64_t *p, int64_t cap) {
+    int64_t v = *p;
+    return v < cap ? v : cap;
+}
+
+static inline int grid_for(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > kMaxStride) g = kMaxStride;
+    return (int)g;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    for (int64_t i = grid_tid(); i < n; i += grid_stride()) p[i] = v;
+}
+
+__global__ void k_fill_i32_dev(int32_t *p, const int64_t *n_dev, int64_t cap, int32_t v) {
+    int64_t n = dev_count(n_dev, cap);
+    for (int64_t i = grid_tid(); i < n; i += grid_stride()) p[i] = v;
+}
+
+__global__ void k_fill_i64(int64_t *p, int64_t n, int64_t v) {
+    for (int64_t i = grid_tid(); i < n; i += grid_stride()) p[i] = v;
+}
+
+__global__ void k_set_single_event(int64_t *ev, int64_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) { ev[0] = 0; ev[1] = n; }
+}
+
+// wave64 inclusive scan of a 64-bit value
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// block (256 threads) inclusive scan; returns inclusive value, total in *tot
+__device__ __forceinline__ int64_t block_incl_scan(int64_t v, int64_t *tot) {
+    __shared__ int64_t s_w[kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t inc = wave_incl_scan(v);
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    int64_t off = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; ++k) {
+        if (k < wv) off += s_w[k];
+        all += s_w[k];
+    }
+    __syncthreads();
+    *tot = all;
+    return inc + off;
+}
+
+// ------------------------------------------------------------------ scan
+// Exclusive scan of count(i), i < n (n from device or host), into out[0..n],
+// out[n] = total. With tile_anchor != null also records, for every tile of
+// kTile scanned positions, the index i whose range holds the tile's start.
+
+template <class F>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(F f, const int64_t *n_dev, int64_t n_cap,
+                                                        int64_t *part) {
+    int64_t n = n_dev ? dev_count(n_dev, n_cap) : n_cap;
+    int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
+    int64_t s = 0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) s += f(i);
+    int64_t tot;
+    block_incl_scan(s, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_partials(int64_t *part, int nb) {
+    // single block of 1024 threads, nb <= 1024
+    __shared__ int64_t s_w[16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t v = threadIdx.x < nb ? part[threadIdx.x] : 0;
+    int64_t inc = wave_incl_scan(v);
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    int64_t off = 0, all = 0;
+    for (int k = 0; k < 16; ++k) { if (k < wv) off += s_w[k]; all += s_w[k]; }
+    __syncthreads();
+    if (threadIdx.x < nb) part[threadIdx.x] = inc + off - v;
+    if (threadIdx.x == 0) part[nb] = all;
+}
+
+template <class F>
+__global__ __launch_bounds__(kBlock) void k_scan_down(F f, const int64_t *n_dev, int64_t n_cap,
+                                                      const int64_t *part, int64_t *out,
+                                                      int32_t *tile_anchor, int64_t max_tiles) {
+    int64_t n = n_dev ? dev_count(n_dev, n_cap) : n_cap;
+    int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
+    int64_t run = part[blockIdx.x];
+    for (int64_t base = b0; base < b1; base += kBlock) {
+        int64_t i = base + threadIdx.x;
+        int64_t c = i < b1 ? f(i) : 0;
+        int64_t tot;
+        int64_t inc = block_incl_scan(c, &tot);
+        int64_t o = run + inc - c;
+        if (i < b1) {
+            out[i] = o;
+            if (tile_anchor && c > 0) {
+                int64_t t0 = (o + kTile - 1) / kTile, t1 = (o + c - 1) / kTile;
+                for (int64_t t = t0; t <= t1 && t < max_tiles; ++t) tile_anchor[t] = (int32_t)i;
+            }
+        }
+        run += tot;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[gridDim.x];
+}
+
+template <class F>
+static void scan(F f, const int64_t *n_dev, int64_t n_cap, const Work &w, int64_t *out,
+                 int32_t *tile_anchor, hipStream_t st) {
+    int nb = (int)((n_cap + kBlock - 1) / kBlock);
+    if (nb < 1) nb = 1;
+    if (nb > kScanBlocks) nb = kScanBlocks;
+    hipLaunchKernelGGL(k_scan_reduce<F>, dim3(nb), dim3(kBlock), 0, st, f, n_dev, n_cap, w.scan_part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, w.scan_part, nb);
+    hipLaunchKernelGGL(k_scan_down<F>, dim3(nb), dim3(kBlock), 0, st, f, n_dev, n_cap, w.scan_part,
+                       out, tile_anchor, w.max_tiles);
+}
+
+// ------------------------------------------------ compaction (one stage)
+
+// Reset the look-back state for the tiles of this stage and record the
+// candidate total (error bit 1 if it exceeds the candidate capacity).
+__global__ void k_stage_clear(const int64_t *cand_off, const int64_t *n_dev, int64_t n_cap,
+                              unsigned long long *state, int64_t max_tiles, uint32_t *ticket,
+                              int64_t *out_count, int64_t *counts, int64_t cap_cand) {
+    int64_t na = n_dev ? dev_count(n_dev, n_cap) : n_cap;
+    int64_t total = cand_off[na];
+    int64_t nt = (total + kTile - 1) / kTile;
+    if (nt > max_tiles) nt = max_tiles;
+    for (int64_t i = grid_tid(); i < nt; i += grid_stride()) state[i] = 0ull;
+    if (grid_tid() == 0) {
+        *ticket = 0u;
+        *out_count = 0;
+        atomicMax((unsigned long long *)&counts[LST_COUNT_MAXCAND], (unsigned long long)total);
+        if (total > cap_cand) atomicOr((unsigned long long *)&counts[LST_COUNT_ERR], 2ull);
+    }
+}
+
+constexpr unsigned long long kFlagAgg = 1ull << 62;
+constexpr unsigned long long kFlagPre = 2ull << 62;
+constexpr unsigned long long kValMask = (1ull << 62) - 1;
+
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_stage_eval(S st, const int64_t *cand_off,
+                                                       const int64_t *n_dev, int64_t n_cap,
+                                                       const int32_t *tile_anchor,
+                                                       unsigned long long *state, int64_t max_tiles,
+                                                       uint32_t *ticket, int64_t *out_count,
+                                                       int64_t cap_out) {
+    __shared__ int64_t s_tile, s_base;
+    __shared__ int64_t s_alo, s_ahi;
+    __shared__ int s_wcnt[kBlock / 64];
+    const int64_t na = n_dev ? dev_count(n_dev, n_cap) : n_cap;
+    const int64_t total = cand_off[na];
+    int64_t ntiles = (total + kTile - 1) / kTile;
+    if (ntiles > max_tiles) ntiles = max_tiles;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int64_t t = (int64_t)atomicAdd(ticket, 1u);
+            s_tile = t;
+            if (t < ntiles) {
+                s_alo = tile_anchor[t];
+                s_ahi = (t + 1 < ntiles) ? (int64_t)tile_anchor[t + 1] : na - 1;
+            }
+        }
+        __syncthreads();
+        const int64_t tile = s_tile;
+        if (tile >= ntiles) break;
+        const int64_t g = tile * kTile + threadIdx.x;
+        typename S::Rec rec;
+        bool pass = false;
+        if (g < total) {
+            // largest anchor a in [alo, ahi] with cand_off[a] <= g
+            int64_t lo = s_alo, hi = s_ahi + 1;
+            while (hi - lo > 1) {
+                int64_t mid = (lo + hi) >> 1;
+                if (cand_off[mid] <= g) lo = mid; else hi = mid;
+            }
+            pass = st.eval(lo, g - cand_off[lo], rec);
+        }
+        const unsigned long long m = __ballot(pass);
+        const int rank = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wcnt[wv] = __popcll(m);
+        __syncthreads();
+        int woff = 0, tcnt = 0;
+#pragma unroll
+        for (int k = 0; k < kBlock / 64; ++k) { if (k < wv) woff += s_wcnt[k]; tcnt += s_wcnt[k]; }
+        if (threadIdx.x == 0) {
+            int64_t excl = 0;
+            if (tile == 0) {
+                __hip_atomic_store(&state[0], kFlagPre | (unsigned long long)tcnt, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                __hip_atomic_store(&state[tile], kFlagAgg | (unsigned long long)tcnt, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                // decoupled look-back: every predecessor tile is held by a
+                // running block that publishes its aggregate before waiting
+                int64_t j = tile - 1;
+                for (;;) {
+                    unsigned long long sv = __hip_atomic_load(&state[j], __ATOMIC_ACQUIRE,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+                    unsigned long long fl = sv & ~kValMask;
+                    if (fl == 0ull) { __builtin_amdgcn_s_sleep(1); continue; }
+                    excl += (int64_t)(sv & kValMask);
+                    if (fl == kFlagPre) break;
+                    --j;
+                }
+                __hip_atomic_store(&state[tile], kFlagPre | (unsigned long long)(excl + tcnt),
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            s_base = excl;
+            if (tile == ntiles - 1) *out_count = excl + tcnt;
+        }
+        __syncthreads();
+        if (pass) {
+            int64_t pos = s_base + woff + rank;
+            if (pos < cap_out) st.write(pos, rec);
+        }
+        __syncthreads();
+    }
+}
+
+template <class S>
+struct StageCount {
+    S s;
+    __device__ int64_t operator()(int64_t a) const { return s.count(a); }
+};
+
+template <class S>
+static void run_stage(const S &s, const int64_t *n_dev, int64_t n_cap, const Work &w, int64_t *out_count,
+                      int64_t cap_out, int64_t *counts, hipStream_t st) {
+    scan(StageCount<S>{s}, n_dev, n_cap, w, w.cand_off, w.tile_anchor, st);
+    hipLaunchKernelGGL(k_stage_clear, dim3(grid_for(w.max_tiles)), dim3(kBlock), 0, st, w.cand_off,
+                       n_dev, n_cap, w.tile_state, w.max_tiles, w.ticket, out_count, counts, w.cap_cand);
+    int nb = (int)(w.max_tiles < kEvalBlocks ? w.max_tiles : kEvalBlocks);
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_stage_eval<S>, dim3(nb), dim3(kBlock), 0, st, s, w.cand_off, n_dev, n_cap,
+                       w.tile_anchor, w.tile_state, w.max_tiles, w.ticket, out_count, cap_out);
+}
+
+// ------------------------------------------------------------- binning
+
+__device__ __forceinline__ int event_of(const int64_t *ev_off, int n_ev, int64_t h) {
+    int lo = 0, hi = n_ev;   // largest e with ev_off[e] <= h
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (ev_off[mid] <= h) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_bin_count(const int32_t *sensor, int64_t n, const int64_t *ev_off, int n_ev, int n_sens,
+                            int32_t *cnt, int64_t *counts) {
+    for (int64_t h = grid_tid(); h < n; h += grid_stride()) {
+        int s = sensor[h];
+        if (s < 0 || s >= n_sens) { atomicOr((unsigned long long *)&counts[LST_COUNT_ERR], 1ull); continue; }
+        int e = event_of(ev_off, n_ev, h);
+        atomicAdd(&cnt[(int64_t)e * n_sens + s], 1);
+    }
+}
+
+__global__ void k_bin_scatter(const float *x, const float *y, const float *z, const int32_t *sensor,
+                              int64_t n, const int64_t *ev_off, int n_ev, int n_sens,
+                              const int64_t *off, int32_t *cnt, float4 *out) {
+    for (int64_t h = grid_tid(); h < n; h += grid_stride()) {
+        int s = sensor[h];
+        if (s < 0 || s >= n_sens) continue;
+        int64_t key = (int64_t)event_of(ev_off, n_ev, h) * n_sens + s;
+        int64_t pos = off[key] + (int64_t)atomicSub(&cnt[key], 1) - 1;
+        out[pos] = make_float4(x[h], y[h], z[h], __int_as_float((int)h));
+    }
+}
+
+// order each bin by input index so that every later stage is deterministic
+__global__ void k_bin_sort(const int64_t *off, int64_t nbins, float4 *hit) {
+    for (int64_t b = grid_tid(); b < nbins; b += grid_stride()) {
+        int64_t s = off[b], e = off[b + 1];
+        for (int64_t i = s + 1; i < e; ++i) {
+            float4 v = hit[i];
+            int key = __float_as_int(v.w);
+            int64_t j = i - 1;
+            while (j >= s && __float_as_int(hit[j].w) > key) { hit[j + 1] = hit[j]; --j; }
+            hit[j + 1] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------ MD stage
+
+struct MDStage {
+    const int64_t *bin_off;
+    const float4 *bin_hit;
+    const ModConst *mod;
+    CutParams p;
+    int32_t n_mod, n_sens;
+    int2 *md_hits;
+    float4 *md_a;
+    float2 *md_o;
+    struct Rec { int hl, hu; float4 a; float2 o; };
+
+    __device__ int64_t count(int64_t gm) const {
+        int64_t e = gm / n_mod, m = gm - e * n_mod;
+        int64_t b = e * n_sens + 2 * m;
+        return (bin_off[b + 1] - bin_off[b]) * (bin_off[b + 2] - bin_off[b + 1]);
+    }
+    __device__ bool eval(int64_t gm, int64_t local, Rec &r) const {
+        int64_t e = gm / n_mod, m = gm - e * n_mod;
+        int64_t b = e * n_sens + 2 * m;
+        int nR = (int)(bin_off[b + 2] - bin_off[b + 1]);
+        int l = (int)local / nR, rr = (int)local - l * nR;
+        float4 hi = bin_hit[bin_off[b] + l];
+        float4 hj = bin_hit[bin_off[b + 1] + rr];
+        bool ok = md_pass(mod[m], p, P3{hi.x, hi.y, hi.z}, P3{hj.x, hj.y, hj.z});
+        r.hl = __float_as_int(hi.w); r.hu = __float_as_int(hj.w);
+        r.a = make_float4(hi.x, hi.y, hi.z, __int_as_float((int)gm));
+        r.o = make_float2(hj.x, hj.y);
+        return ok;
+    }
+    __device__ void write(int64_t pos, const Rec &r) const {
+        md_hits[pos] = make_int2(r.hl, r.hu);
+        md_a[pos] = r.a;
+        md_o[pos] = r.o;
+    }
+};
+
+// CSR offsets from a sorted key column: off[k] = first i with key(i) >= k,
+// for k in [0, K]; every entry written exactly once.
+template <class KF>
+__global__ void k_fill_offsets(KF key, const int64_t *n_dev, int64_t n_cap, const int64_t *K_dev,
+                               int64_t K_cap, int64_t *off) {
+    int64_t n = n_dev ? dev_count(n_dev, n_cap) : n_cap;
+    int64_t K = K_dev ? dev_count(K_dev, K_cap) : K_cap;
+    for (int64_t i = grid_tid(); i <= n; i += grid_stride()) {
+        int64_t kc = i < n ? (int64_t)key(i) : K;
+        int64_t kp = i > 0 ? (int64_t)key(i - 1) : -1;
+        if (kc > K) kc = K;
+        for (int64_t k = kp + 1; k <= kc; ++k) off[k] = i;
+    }
+}
+
+// MDs available to the LS stage from every module: rsum[gm] and the
+// exclusive prefix over the module-map entries (per event).
+__global__ void k_ls_prefix(const int32_t *map_off, const int32_t *map_tgt, int32_t n_mod, int32_t n_map,
+                            int32_t n_ev, const int64_t *md_mod_off, int32_t *rsum, int32_t *rpref) {
+    int64_t N = (int64_t)n_ev * n_mod;
+    for (int64_t gm = grid_tid(); gm < N; gm += grid_stride()) {
+        int64_t e = gm / n_mod, m = gm - e * n_mod;
+        int32_t acc = 0;
+        for (int32_t k = map_off[m]; k < map_off[m + 1]; ++k) {
+            rpref[e * n_map + k] = acc;
+            int64_t t = e * n_mod + map_tgt[k];
+            acc += (int32_t)(md_mod_off[t + 1] - md_mod_off[t]);
+        }
+        rsum[gm] = acc;
+    }
+}
+
+// ------------------------------------------------------------ LS stage
+
+struct LSStage {
+    const float4 *md_a;
+    const float2 *md_o;
+    const int64_t *md_mod_off;
+    const int32_t *rsum, *rpref;
+    const int32_t *map_off, *map_tgt;
+    const ModConst *mod;
+    CutParams p;
+    int32_t n_mod, n_map;
+    int2 *ls_md;
+    struct Rec { int a, b; };
+
+    __device__ int64_t count(int64_t a) const { return rsum[__float_as_int(md_a[a].w)]; }
+    __device__ bool eval(int64_t a, int64_t local, Rec &r) const {
+        float4 A = md_a[a];
+        int gm = __float_as_int(A.w);
+        int e = gm / n_mod, m = gm - e * n_mod;
+        const int32_t *rp = rpref + (int64_t)e * n_map;
+        int lo = map_off[m], hi = map_off[m + 1];   // largest k with rp[k] <= local
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (rp[mid] <= local) lo = mid; else hi = mid;
+        }
+        int mb = map_tgt[lo];
+        int64_t b = md_mod_off[(int64_t)e * n_mod + mb] + (local - rp[lo]);
+        float4 B = md_a[b];
+        r.a = (int)a; r.b = (int)b;
+        bool eA = mod[m].kind != 0, eB = mod[mb].kind != 0;
+        float c, sg;
+        if (!pair_pass(p, P3{A.x, A.y, A.z}, eA, P3{B.x, B.y, B.z}, eB, c, sg)) return false;
+        float cp = fminf(c, p.cmax);
+        if (!eA) { float2 o = md_o[a]; if (!md_dir_pass(p, P3{A.x, A.y, A.z}, o.x, o.y, cp, sg)) return false; }
+        if (!eB) { float2 o = md_o[b]; if (!md_dir_pass(p, P3{B.x, B.y, B.z}, o.x, o.y, cp, sg)) return false; }
+        return true;
+    }
+    __device__ void write(int64_t pos, const Rec &r) const { ls_md[pos] = make_int2(r.a, r.b); }
+};
+
+// ---------------------------------------------------------- bucket sorts
+// Deterministic counting sort of item ids by key (ids ascending in a bucket).
+
+template <class KF>
+__global__ void k_bucket_count(KF key, const int64_t *n_dev, int64_t n_cap, int32_t *cnt) {
+    int64_t n = dev_count(n_dev, n_cap);
+    for (int64_t i = grid_tid(); i < n; i += grid_stride()) atomicAdd(&cnt[key(i)], 1);
+}
+
+template <class KF>
+__global__ void k_bucket_scatter(KF key, const int64_t *n_dev, int64_t n_cap, const int64_t *off,
+                                 int32_t *cnt, int32_t *idx) {
+    int64_t n = dev_count(n_dev, n_cap);
+    for (int64_t i = grid_tid(); i < n; i += grid_stride()) {
+        int k = key(i);
+        int64_t pos = off[k] + (int64_t)atomicSub(&cnt[k], 1) - 1;
+        idx[pos] = (int32_t)i;
+    }
+}
+
+__global__ void k_bucket_sort(const int64_t *off, const int64_t *K_dev, int64_t K_cap, int32_t *idx) {
+    int64_t K = dev_count(K_dev, K_cap);
+    for (int64_t b = grid_tid(); b < K; b += grid_stride()) {
+        int64_t s = off[b], e = off[b + 1];
+        for (int64_t i = s + 1; i < e; ++i) {
+            int32_t v = idx[i];
+            int64_t j = i - 1;
+            while (j >= s && idx[j] > v) { idx[j + 1] = idx[j]; --j; }
+            idx[j + 1] = v;
+        }
+    }
+}
+
+struct CntF {
+    const int32_t *c;
+    __device__ int64_t operator()(int64_t i) const { return c[i]; }
+};
+
+template <class KF>
+static void bucket_sort(KF key, const int64_t *n_dev, int64_t n_cap, const int64_t *K_dev, int64_t K_cap,
+                        const Work &w, int64_t *off, int32_t *idx, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_i32_dev, dim3(grid_for(K_cap)), dim3(kBlock), 0, st, w.bucket_cnt, K_dev,
+                       K_cap, 0);
+    hipLaunchKernelGGL(k_bucket_count<KF>, dim3(grid_for(n_cap)), dim3(kBlock), 0, st, key, n_dev, n_cap,
+                       w.bucket_cnt);
+    scan(CntF{w.bucket_cnt}, K_dev, K_cap, w, off, nullptr, st);
+    hipLaunchKernelGGL(k_bucket_scatter<KF>, dim3(grid_for(n_cap)), dim3(kBlock), 0, st, key, n_dev, n_cap,
+                       off, w.bucket_cnt, idx);
+    hipLaunchKernelGGL(k_bucket_sort, dim3(grid_for(K_cap)), dim3(kBlock), 0, st, off, K_dev, K_cap, idx);
+}
+
+// ------------------------------------------------------------ T3 stage
+
+struct T3Stage {
+    const int2 *ls_md;
+    const int64_t *ls_off, *lsT_off;
+    const int32_t *lsT_idx;
+    const float4 *md_a;
+    const float2 *md_o;
+    const ModConst *mod;
+    CutParams p;
+    int32_t n_mod;
+    int2 *t3_ls;
+    int4 *t3_mds;
+    struct Rec { int li, lo, A, B, C; };
+
+    __device__ int64_t count(int64_t B) const {
+        return (lsT_off[B + 1] - lsT_off[B]) * (ls_off[B + 1] - ls_off[B]);
+    }
+    __device__ bool eval(int64_t B, int64_t local, Rec &r) const {
+        int nR = (int)(ls_off[B + 1] - ls_off[B]);
+        int l = (int)local / nR, rr = (int)local - l * nR;
+        int li = lsT_idx[lsT_off[B] + l];
+        int lo = (int)(ls_off[B] + rr);
+        int A = ls_md[li].x, C = ls_md[lo].y;
+        r.li = li; r.lo = lo; r.A = A; r.B = (int)B; r.C = C;
+        float4 a = md_a[A], b = md_a[B], c = md_a[C];
+        int ma = __float_as_int(a.w) % n_mod, mb = __float_as_int(b.w) % n_mod, mc = __float_as_int(c.w) % n_mod;
+        float cv, sg;
+        if (!pair_pass(p, P3{a.x, a.y, a.z}, mod[ma].kind != 0, P3{c.x, c.y, c.z}, mod[mc].kind != 0, cv, sg))
+            return false;
+        if (mod[mb].kind == 0) {
+            float2 o = md_o[B];
+            if (!md_dir_pass(p, P3{b.x, b.y, b.z}, o.x, o.y, fminf(cv, p.cmax), sg)) return false;
+        }
+        return true;
+    }
+    __device__ void write(int64_t pos, const Rec &r) const {
+        t3_ls[pos] = make_int2(r.li, r.lo);
+        t3_mds[pos] = make_int4(r.A, r.B, r.C, 0);
+    }
+};
+
+// ------------------------------------------------------------ T5 stage
+
+struct T5Stage {
+    const int4 *t3_mds;
+    const int64_t *t3o_off, *t3i_off;
+    const int32_t *t3o_idx, *t3i_idx;
+    const float4 *md_a;
+    const ModConst *mod;
+    CutParams p;
+    ModelDev mdl;
+    int32_t n_mod, mode;
+    float score_min;
+    int2 *t5_t3;
+    float *chi2_rphi, *chi2_rz;
+    struct Rec { int u, v; float cr, cz; };
+
+    __device__ int64_t count(int64_t C) const {
+        return (t3o_off[C + 1] - t3o_off[C]) * (t3i_off[C + 1] - t3i_off[C]);
+    }
+    __device__ bool eval(int64_t C, int64_t local, Rec &r) const {
+        int nR = (int)(t3i_off[C + 1] - t3i_off[C]);
+        int l = (int)local / nR, rr = (int)local - l * nR;
+        int u = t3o_idx[t3o_off[C] + l];
+        int v = t3i_idx[t3i_off[C] + rr];
+        int4 m1 = t3_mds[u], m2 = t3_mds[v];
+        r.u = u; r.v = v; r.cr = 0.f; r.cz = 0.f;
+        int ids[5] = {m1.x, m1.y, m1.z, m2.y, m2.z};
+        float4 an[5];
+        bool endc[5];
+        int lay[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            an[i] = md_a[ids[i]];
+            const ModConst &mc = mod[__float_as_int(an[i].w) % n_mod];
+            endc[i] = mc.kind != 0;
+            lay[i] = mc.layer;
+        }
+        float cv, sg;
+        if (!pair_pass(p, P3{an[0].x, an[0].y, an[0].z}, endc[0], P3{an[4].x, an[4].y, an[4].z}, endc[4], cv, sg))
+            return false;
+        double x[5], y[5], z[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) { x[i] = an[i].x; y[i] = an[i].y; z[i] = an[i].z; }
+        Fit5 f;
+        t5_fit(p, x, y, z, endc, f);
+        r.cr = (float)f.chi2_rphi; r.cz = (float)f.chi2_rz;
+        if (!(f.chi2_rz <= (double)p.chi2rz)) return false;
+        if (mode == 1 && !(f.chi2_rphi <= (double)p.chi2rphi)) return false;
+        if (mode == 0 && score_min == score_min) {
+            float ft[kNFeat];
+            t5_features(p, x, y, z, lay, endc, f, ft);
+            if (!(score_min <= mlp_f32(mdl, ft))) return false;
+        }
+        return true;
+    }
+    __device__ void write(int64_t pos, const Rec &r) const {
+        t5_t3[pos] = make_int2(r.u, r.v);
+        chi2_rphi[pos] = r.cr;
+        chi2_rz[pos] = r.cz;
+    }
+};
+
+// T5 features and T5-DNN score, one thread per T5 (FP32 vector ALU).
+__global__ __launch_bounds__(kBlock) void k_t5_score_f32(T5Stage s, const int64_t *n_dev, int64_t cap,
+                                                         float *score, float *feat, int do_mlp) {
+    int64_t n = dev_count(n_dev, cap);
+    for (int64_t i = grid_tid(); i < n; i += grid_stride()) {
+        int2 uv = s.t5_t3[i];
+        int4 m1 = s.t3_mds[uv.x], m2 = s.t3_mds[uv.y];
+        int ids[5] = {m1.x, m1.y, m1.z, m2.y, m2.z};
+        double x[5], y[5], z[5];
+        bool endc[5];
+        int lay[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            float4 a = s.md_a[ids[k]];
+            const ModConst &mc = s.mod[__float_as_int(a.w) % s.n_mod];
+            x[k] = a.x; y[k] = a.y; z[k] = a.z; endc[k] = mc.kind != 0; lay[k] = mc.layer;
+        }
+        Fit5 f;
+        t5_fit(s.p, x, y, z, endc, f);
+        float ft[kNFeat];
+        t5_features(s.p, x, y, z, lay, endc, f, ft);
+        if (feat) {
+#pragma unroll
+            for (int k = 0; k < kNFeat; ++k) feat[i * kNFeat + k] = ft[k];
+        }
+        if (do_mlp) score[i] = s.mode == 0 ? mlp_f32(s.mdl, ft) : __builtin_nanf("");
+    }
+}
+
+// BF16 MFMA scoring of the T5 features written by the pass above (defined in
+// the scoring translation unit).
+hipError_t score_rows_dev(const ModelDev &m, const float *X, const int64_t *n_dev, int64_t n_cap,
+                          float *out, hipStream_t st);
+
+// ---------------------------------------------------- per-event offsets
+
+__global__ void k_event_offsets(const int64_t *md_mod_off, const int64_t *ls_off, const int4 *t3_mds,
+                                const int2 *t5_t3, const int64_t *counts, int64_t cap_md, int64_t cap_ls,
+                                int64_t cap_t3, int64_t cap_t5, int32_t n_mod, int32_t n_ev, int64_t *out) {
+    int e = threadIdx.x + blockIdx.x * blockDim.x;
+    if (e > n_ev) return;
+    int64_t nmd = dev_count(counts + 0, cap_md), nls = dev_count(counts + 1, cap_ls);
+    int64_t nt3 = dev_count(counts + 2, cap_t3), nt5 = dev_count(counts + 3, cap_t5);
+    int64_t md0 = md_mod_off[(int64_t)e * n_mod];
+    if (md0 > nmd) md0 = nmd;
+    int64_t ls0 = ls_off[md0];
+    // T3 are sorted by middle MD, T5 by their shared MD: first with MD >= md0
+    int64_t lo = 0, hi = nt3;
+    while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (t3_mds[mid].y < md0) lo = mid + 1; else hi = mid; }
+    int64_t t30 = lo;
+    lo = 0; hi = nt5;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (t3_mds[t5_t3[mid].x].z < md0) lo = mid + 1; else hi = mid;
+    }
+    out[0 * (n_ev + 1) + e] = md0;
+    out[1 * (n_ev + 1) + e] = e == n_ev ? nls : ls0;
+    out[2 * (n_ev + 1) + e] = t30;
+    out[3 * (n_ev + 1) + e] = lo;
+}
+
+// ------------------------------------------------------------- pipeline
+
+struct GmKey {
+    const float4 *md_a;
+    __device__ int operator()(int64_t i) const { return __float_as_int(md_a[i].w); }
+};
+struct LsInKey {
+    const int2 *ls;
+    __device__ int operator()(int64_t i) const { return ls[i].x; }
+};
+struct LsOutKey {
+    const int2 *ls;
+    __device__ int operator()(int64_t i) const { return ls[i].y; }
+};
+struct T3InKey {
+    const int4 *t;
+    __device__ int operator()(int64_t i) const { return t[i].x; }
+};
+struct T3OutKey {
+    const int4 *t;
+    __device__ int operator()(int64_t i) const { return t[i].z; }
+};
+
+hipError_t set_single_event(int64_t *ev_off, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_single_event, dim3(1), dim3(64), 0, st, ev_off, n);
+    return hipGetLastError();
+}
+
+hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipStream_t st) {
+    const int32_t n_mod = a.g.n_mod, n_sens = a.g.n_sens, n_map = a.g.n_map;
+    const int64_t nbins = (int64_t)a.n_ev * n_sens;
+    const int64_t ngm = (int64_t)a.n_ev * n_mod;
+    int64_t *cnt = o.counts;
+
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, cnt, (int64_t)LST_COUNTS_LEN, (int64_t)0);
+    // a1: bin hits by (event, sensor)
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nbins)), dim3(kBlock), 0, st, w.bin_cnt, nbins, 0);
+    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(a.n_hits)), dim3(kBlock), 0, st, a.sensor, a.n_hits, a.ev_off,
+                       a.n_ev, n_sens, w.bin_cnt, cnt);
+    scan(CntF{w.bin_cnt}, nullptr, nbins, w, w.bin_off, nullptr, st);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(a.n_hits)), dim3(kBlock), 0, st, a.x, a.y, a.z, a.sensor,
+                       a.n_hits, a.ev_off, a.n_ev, n_sens, w.bin_off, w.bin_cnt, w.bin_hit);
+    hipLaunchKernelGGL(k_bin_sort, dim3(grid_for(nbins)), dim3(kBlock), 0, st, w.bin_off, nbins, w.bin_hit);
+
+    // a2: mini-doublets, anchored on (event, module)
+    MDStage md{w.bin_off, w.bin_hit, a.g.mod, a.p, n_mod, n_sens, o.md_hits, w.md_a, w.md_o};
+    run_stage(md, nullptr, ngm, w, cnt + LST_COUNT_MD, w.cap_md, cnt, st);
+    hipLaunchKernelGGL(k_fill_offsets<GmKey>, dim3(grid_for(w.cap_md)), dim3(kBlock), 0, st, GmKey{w.md_a},
+                       cnt + LST_COUNT_MD, w.cap_md, nullptr, ngm, w.md_mod_off);
+    hipLaunchKernelGGL(k_ls_prefix, dim3(grid_for(ngm)), dim3(kBlock), 0, st, a.g.map_off, a.g.map_tgt, n_mod,
+                       n_map, a.n_ev, w.md_mod_off, w.rsum, w.rpref);
+
+    // a3: line segments, anchored on the inner MD, over the mapped modules
+    LSStage ls{w.md_a, w.md_o, w.md_mod_off, w.rsum, w.rpref, a.g.map_off, a.g.map_tgt, a.g.mod, a.p,
+               n_mod, n_map, o.ls_md};
+    run_stage(ls, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st);
+    hipLaunchKernelGGL(k_fill_offsets<LsInKey>, dim3(grid_for(w.cap_ls)), dim3(kBlock), 0, st, LsInKey{o.ls_md},
+                       cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w.ls_off);
+    bucket_sort(LsOutKey{o.ls_md}, cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w, w.lsT_off,
+                w.lsT_idx, st);
+
+    // a4: triplets, anchored on the shared (middle) MD
+    T3Stage t3{o.ls_md, w.ls_off, w.lsT_off, w.lsT_idx, w.md_a, w.md_o, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
+    run_stage(t3, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st);
+    bucket_sort(T3InKey{w.t3_mds}, cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w, w.t3i_off,
+                w.t3i_idx, st);
+    bucket_sort(T3OutKey{w.t3_mds}, cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w, w.t3o_off,
+                w.t3o_idx, st);
+
+    // a5: quintuplets, anchored on the shared MD; FP64 fits
+    T5Stage t5{w.t3_mds, w.t3o_off, w.t3i_off, w.t3o_idx, w.t3i_idx, w.md_a, a.g.mod, a.p, a.m, n_mod,
+               a.mode, a.score_min, o.t5_t3, o.t5_chi2_rphi, o.t5_chi2_rz};
+    run_stage(t5, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st);
+
+    // a6: features and T5-DNN scores (BF16 MFMA runs over the feature rows;
+    // a score cut forces the FP32 path, which the T5 stage itself applied)
+    bool mfma = a.mode == 0 && a.precision == 1 && !(a.score_min == a.score_min);
+    float *feat = o.t5_feat ? o.t5_feat : (mfma ? w.t5_feat : nullptr);
+    hipLaunchKernelGGL(k_t5_score_f32, dim3(grid_for(w.cap_t5)), dim3(kBlock), 0, st, t5,
+                       cnt + LST_COUNT_T5, w.cap_t5, o.t5_score, feat, (int)!mfma);
+    if (mfma) {
+        hipError_t e = score_rows_dev(a.m, feat, cnt + LST_COUNT_T5, w.cap_t5, o.t5_score, st);
+        if (e != hipSuccess) return e;
+    }
+    if (a.ev_obj_off) {
+        hipLaunchKernelGGL(k_event_offsets, dim3((a.n_ev + 64) / 64), dim3(64), 0, st, w.md_mod_off, w.ls_off,
+                           w.t3_mds, o.t5_t3, cnt, w.cap_md, w.cap_ls, w.cap_t3, w.cap_t5, n_mod, a.n_ev,
+                           a.ev_obj_off);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lst

@@ -1,0 +1,229 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Object sets must agree with zero violations (only marginal / inherited
+differences, see tests/compare.py); T5 scores within 1e-5 absolute on the
+FP32 path and 2e-2 on the BF16-MFMA path; chi2 values within FP32 rounding.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2403_13166_amd.synth import geometry as G, events as E, model as M
+from tests import compare as CMP
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def geo_b():
+    return G.make_geometry(False)
+
+
+@pytest.fixture(scope="module")
+def geo_f():
+    return G.make_geometry(True)
+
+
+@pytest.fixture(scope="module")
+def mdl():
+    return M.make_model()
+
+
+@pytest.fixture(scope="module")
+def builder_f(geo_f, mdl):
+    from paper_2403_13166_amd.runtime import Builder
+    b = Builder(geo_f.to_blob(), mdl.to_blob(), 0)
+    yield b
+    b.close()
+
+
+@pytest.fixture(scope="module")
+def builder_b(geo_b, mdl):
+    from paper_2403_13166_amd.runtime import Builder
+    b = Builder(geo_b.to_blob(), mdl.to_blob(), 0)
+    yield b
+    b.close()
+
+
+def run_gpu(builder, ev, **kw):
+    from paper_2403_13166_amd.runtime import to_device
+    x, y, z, s = to_device(ev, builder.device)
+    out = builder.build(x, y, z, s, **kw)
+    torch.cuda.synchronize()
+    return out.to_host()
+
+
+def check_parity(geo, mdl, ev, gh, mode=0, score_tol=1e-5, label=""):
+    og, om = O.Geom(geo.to_blob()), O.Model(mdl.to_blob())
+    orc = O.build_objects(og, om, ev.x, ev.y, ev.z, ev.sensor, mode=mode)
+    reps = CMP.compare(og, om, ev, gh, orc, mode)
+    for st, r in zip(("MD", "LS", "T3", "T5"), reps):
+        _say(f"{label} {st}: gpu {r.n_gpu} oracle {r.n_oracle} marginal {r.marginal} "
+             f"inherited {r.inherited} violation {r.violation} dup {r.duplicates} {r.examples[:2]}")
+        assert r.violation == 0, (st, r.examples)
+        assert r.duplicates == 0, st
+    err = CMP.score_errors(gh, orc)
+    _say(f"{label} score/chi2 errors: {err}")
+    if mode == 0:
+        assert err["score"][0] <= score_tol
+    else:
+        assert np.all(np.isnan(gh.t5_score))
+    assert err["chi2_rz_rel"][0] < 1e-4 and err["chi2_rphi_rel"][0] < 1e-4
+    return reps, orc
+
+
+def test_small_barrel_event_parity(builder_b, geo_b, mdl):
+    for e in range(3):
+        ev = E.make_event(geo_b, E.SMALL_BARREL, (0, e))
+        _say(f"small barrel event {e}: {ev.n} hits")
+        gh = run_gpu(builder_b, ev, with_features=True)
+        reps, orc = check_parity(geo_b, mdl, ev, gh, label=f"C0[{e}]")
+        assert reps[3].n_gpu > 100
+        worst = CMP.feature_errors(gh, orc)
+        assert np.max(worst) < 1e-5, np.argmax(worst)
+
+
+def test_pu200_event_parity_f32(builder_f, geo_f, mdl):
+    ev = E.make_event(geo_f, E.PU200, (1, 0))
+    _say(f"PU200 event: {ev.n} hits")
+    gh = run_gpu(builder_f, ev)
+    reps, _ = check_parity(geo_f, mdl, ev, gh, label="C1 f32")
+    assert reps[0].n_gpu > 30000 and reps[3].n_gpu > 10000
+
+
+def test_pu200_event_parity_bf16_scores(builder_f, geo_f, mdl):
+    ev = E.make_event(geo_f, E.PU200, (1, 1))
+    gh = run_gpu(builder_f, ev, precision=1)
+    check_parity(geo_f, mdl, ev, gh, score_tol=2e-2, label="C1 bf16")
+
+
+def test_pu200_pre_dnn_mode(builder_f, geo_f, mdl):
+    ev = E.make_event(geo_f, E.PU200, (1, 2))
+    gh = run_gpu(builder_f, ev, mode=1)
+    reps, orc = check_parity(geo_f, mdl, ev, gh, mode=1, label="C1 pre-DNN")
+    assert reps[3].n_gpu < len(O.build_objects(O.Geom(geo_f.to_blob()), O.Model(mdl.to_blob()),
+                                               ev.x, ev.y, ev.z, ev.sensor, mode=0).t5)
+
+
+def test_score_min_cut(builder_f, geo_f, mdl):
+    ev = E.make_event(geo_f, E.PU200, (1, 3))
+    gh = run_gpu(builder_f, ev, score_min=0.6)
+    og, om = O.Geom(geo_f.to_blob()), O.Model(mdl.to_blob())
+    orc = O.build_objects(og, om, ev.x, ev.y, ev.z, ev.sensor, mode=0, score_min=0.6)
+    reps = CMP.compare(og, om, ev, gh, orc, 0, 0.6)
+    for r in reps:
+        assert r.violation == 0, r.examples
+    assert np.all(gh.t5_score >= 0.6)
+
+
+def test_deterministic_outputs(builder_f, geo_f):
+    ev = E.make_event(geo_f, E.PU200, (1, 4))
+    a = run_gpu(builder_f, ev)
+    b = run_gpu(builder_f, ev)
+    for f in ("md_hits", "ls_md", "t3_ls", "t5_t3", "t5_score", "t5_chi2_rz"):
+        assert np.array_equal(getattr(a, f), getattr(b, f), equal_nan=True), f
+
+
+def test_batched_equals_single_and_oracle(builder_f, geo_f, mdl):
+    from paper_2403_13166_amd.runtime import Builder
+    rng = E.event_rng(2, 99)
+    evs = [E.make_event(geo_f, E.batch_event_config(rng), (2, 99, i)) for i in range(4)]
+    evs.append(E.make_event(geo_f, E.EventConfig("tiny", 3, 0.1, 1.0, 1.0, 0.0, 20, True), (2, 99, 9)))
+    x, y, z, s, off = E.concat_events(evs)
+    dev = builder_f.device
+    T = lambda a: torch.from_numpy(a).to(dev)
+    out = builder_f.build(T(x), T(y), T(z), T(s), event_offsets=T(off))
+    torch.cuda.synchronize()
+    bh = out.to_host()
+    eo = bh.event_offsets
+    for i, ev in enumerate(evs):
+        sh = run_gpu(builder_f, ev)
+        md = bh.md_hits[eo[0, i]:eo[0, i + 1]] - off[i]
+        assert np.array_equal(md, sh.md_hits), i
+        ls = bh.ls_md[eo[1, i]:eo[1, i + 1]] - eo[0, i]
+        assert np.array_equal(ls, sh.ls_md), i
+        t3 = bh.t3_ls[eo[2, i]:eo[2, i + 1]] - eo[1, i]
+        assert np.array_equal(t3, sh.t3_ls), i
+        t5 = bh.t5_t3[eo[3, i]:eo[3, i + 1]] - eo[2, i]
+        assert np.array_equal(t5, sh.t5_t3), i
+        assert np.array_equal(bh.t5_score[eo[3, i]:eo[3, i + 1]], sh.t5_score), i
+    # sampled events of the batch against the oracle
+    for i in (0, 4):
+        sh = run_gpu(builder_f, evs[i])
+        check_parity(geo_f, mdl, evs[i], sh, label=f"batch[{i}]")
+
+
+def test_standalone_scoring(builder_f, mdl):
+    X = M.make_scoring_inputs(200_000, seed=(3, 0))
+    om = O.Model(M.make_model(standardise=False).to_blob())
+    from paper_2403_13166_amd.runtime import Builder
+    geo = G.make_geometry(False)
+    b = Builder(geo.to_blob(), M.make_model(standardise=False).to_blob(), 0)
+    try:
+        ref = O.mlp(om, X[:20000])
+        Xd = torch.from_numpy(X).to(b.device)
+        s32 = b.score(Xd, precision=0).cpu().numpy()
+        s16 = b.score(Xd, precision=1).cpu().numpy()
+        sb = b.score(Xd.to(torch.bfloat16), precision=1).cpu().numpy()
+        e32 = np.max(np.abs(s32[:20000] - ref))
+        e16 = np.max(np.abs(s16[:20000] - ref))
+        _say(f"scoring: f32 max err {e32:.2e}, bf16-mfma max err {e16:.2e}, mean {np.mean(np.abs(s16[:20000]-ref)):.2e}")
+        assert e32 <= 1e-5
+        assert e16 <= 2e-2
+        # bf16 inputs: same as rounding the inputs first
+        Xr = torch.from_numpy(X[:20000]).to(torch.bfloat16).float().numpy()
+        assert np.max(np.abs(sb[:20000] - O.mlp(om, Xr))) <= 2e-2
+        assert np.all(np.isfinite(s16)) and s16.shape == (200_000,)
+        # ragged tails: n not a multiple of 64 / 256
+        for n in (1, 63, 65, 257, 1000):
+            t = b.score(Xd[:n].contiguous(), precision=1).cpu().numpy()
+            assert np.array_equal(t, s16[:n])
+    finally:
+        b.close()
+
+
+def test_edge_cases(builder_f, geo_f):
+    from paper_2403_13166_amd import binding as B
+    dev = builder_f.device
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    # empty event
+    e = np.zeros(0, np.float32)
+    out = builder_f.build(T(e), T(e), T(e), T(np.zeros(0, np.int32)))
+    assert out.counts() == (0, 0, 0, 0)
+    # a single hit; hits all on one sensor
+    ev = E.make_event(geo_f, E.PU200, (1, 5))
+    one = builder_f.build(T(ev.x[:1]), T(ev.y[:1]), T(ev.z[:1]), T(ev.sensor[:1]))
+    assert one.counts() == (0, 0, 0, 0)
+    s0 = np.full(50, ev.sensor[0], np.int32)
+    out = builder_f.build(T(ev.x[:50]), T(ev.y[:50]), T(ev.z[:50]), T(s0))
+    assert out.counts()[0] == 0
+    # invalid sensor id -> LST_E_INVAL
+    bad = ev.sensor[:100].copy()
+    bad[7] = 2 * geo_f.n_modules + 5
+    with pytest.raises(B.LstError) as ex:
+        builder_f.build(T(ev.x[:100]), T(ev.y[:100]), T(ev.z[:100]), T(bad))
+    assert ex.value.status == B.LST_E_INVAL
+    # too small capacities -> grown and retried transparently, same result
+    from paper_2403_13166_amd.runtime import Builder, Caps
+    ref = run_gpu(builder_f, ev)
+    small = Caps(hits=ev.n, events=1, md=1000, ls=1000, t3=1000, t5=1000, cand=100_000)
+    x, y, z, s = (T(a) for a in (ev.x, ev.y, ev.z, ev.sensor))
+    h = B.LstHits(x.data_ptr(), y.data_ptr(), z.data_ptr(), s.data_ptr(), ev.n)
+    builder_f.caps = None
+    builder_f.reserve(small)
+    st = B.lst_build_objects(builder_f.ctx, h, B.LstOptions(0, 0, float("nan"), 0), small.c(),
+                             builder_f._objects_struct(False), builder_f._ws_ptr(), builder_f.ws_bytes,
+                             torch.cuda.current_stream(dev).cuda_stream, check=False)
+    assert st == B.LST_E_CAPACITY
+    out = builder_f.build(x, y, z, s, caps=small).to_host()
+    assert np.array_equal(out.t5_t3, ref.t5_t3) and np.array_equal(out.md_hits, ref.md_hits)
