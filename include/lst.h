@@ -157,6 +157,16 @@ lst_status lst_build_objects_batched(lst_ctx *ctx, const lst_hits *hits,
 lst_status lst_score(lst_ctx *ctx, const void *X_dev, int32_t x_dtype, int64_t n,
                      float *scores_dev, int32_t precision, void *stream);
 
+/* Stage timing for measurement: while enabled, every build records HIP
+ * events on its stream around the pipeline's stages (also when the build is
+ * captured into a HIP graph). lst_stage_times then returns, for the most
+ * recent completed build, n <= 7 durations in ms: 0 whole build, 1 hit
+ * binning, 2 MD, 3 LS, 4 T3, 5 T5 compaction kernels, 6 T5 features + DNN
+ * scoring. The caller synchronises the stream first; LST_E_STATE if timing
+ * was never enabled. */
+lst_status lst_set_timing(lst_ctx *ctx, int32_t enable);
+lst_status lst_stage_times(lst_ctx *ctx, float *ms, int32_t n);
+
 const char *lst_status_string(lst_status s);
 const char *lst_last_error(const lst_ctx *ctx);
 

@@ -33,7 +33,7 @@ N_FEATURES = 42
 
 EXPORTED = ("lst_create", "lst_destroy", "lst_load_geometry", "lst_load_model", "lst_workspace_size",
             "lst_build_objects", "lst_build_objects_batched", "lst_score", "lst_status_string",
-            "lst_last_error")
+            "lst_last_error", "lst_set_timing", "lst_stage_times")
 
 
 class LstHits(C.Structure):
@@ -95,6 +95,10 @@ def lib():
         L.lst_build_objects_batched.restype = i32
         L.lst_score.argtypes = [vp, vp, i32, i64, vp, i32, vp]
         L.lst_score.restype = i32
+        L.lst_set_timing.argtypes = [vp, i32]
+        L.lst_set_timing.restype = i32
+        L.lst_stage_times.argtypes = [vp, vp, i32]
+        L.lst_stage_times.restype = i32
         L.lst_status_string.argtypes = [i32]
         L.lst_status_string.restype = C.c_char_p
         L.lst_last_error.argtypes = [vp]
@@ -156,6 +160,20 @@ def lst_build_objects_batched(ctx, hits: LstHits, event_offsets_dev: int, n_even
 def lst_score(ctx, X_dev: int, x_dtype: int, n: int, scores_dev: int, precision: int, stream: int) -> None:
     _check(ctx, lib().lst_score(ctx, X_dev, int(x_dtype), int(n), scores_dev, int(precision), stream),
            "lst_score")
+
+
+STAGE_WINDOWS = ("build", "bin", "md", "ls", "t3", "t5", "score")
+
+
+def lst_set_timing(ctx, enable: bool) -> None:
+    _check(ctx, lib().lst_set_timing(ctx, int(bool(enable))), "lst_set_timing")
+
+
+def lst_stage_times(ctx) -> dict:
+    """ms per stage window of the most recent completed build (stream synchronised)."""
+    buf = (C.c_float * len(STAGE_WINDOWS))()
+    _check(ctx, lib().lst_stage_times(ctx, buf, len(STAGE_WINDOWS)), "lst_stage_times")
+    return dict(zip(STAGE_WINDOWS, list(buf)))
 
 
 def lst_status_string(status: int) -> str:

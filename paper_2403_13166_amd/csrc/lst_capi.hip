@@ -27,6 +27,9 @@ struct lst_ctx {
     bool model_loaded = false;
     float *d_model = nullptr;
     ModelDev md{};
+    // stage timing
+    bool timing = false, events_made = false;
+    hipEvent_t tev[kTimingEvents];
 };
 
 static lst_status fail(lst_ctx *c, lst_status s, const char *fmt, ...) {
@@ -88,6 +91,8 @@ void lst_destroy(lst_ctx *c) {
     (void)hipSetDevice(c->device);
     free_geom(c);
     if (c->d_model) (void)hipFree(c->d_model);
+    if (c->events_made)
+        for (int i = 0; i < kTimingEvents; ++i) (void)hipEventDestroy(c->tev[i]);
     delete c;
 }
 
@@ -312,6 +317,7 @@ static lst_status build_common(lst_ctx *c, const lst_hits *h, const int64_t *ev_
     a.ev_off = ev_off; a.n_ev = n_ev;
     a.mode = opt->mode; a.precision = opt->precision; a.score_min = opt->score_min;
     a.ev_obj_off = ev_obj_off;
+    a.timing = c->timing ? c->tev : nullptr;
     Outputs o{};
     o.md_hits = (int2 *)out->md_hits; o.ls_md = (int2 *)out->ls_md; o.t3_ls = (int2 *)out->t3_ls;
     o.t5_t3 = (int2 *)out->t5_t3; o.t5_score = out->t5_score; o.t5_chi2_rphi = out->t5_chi2_rphi;
@@ -340,6 +346,25 @@ lst_status lst_build_objects_batched(lst_ctx *c, const lst_hits *h, const int64_
                                      const lst_options *opt, const lst_caps *k, lst_objects *out,
                                      int64_t *ev_obj_off, void *ws, size_t ws_bytes, void *stream) {
     return build_common(c, h, ev_off, n_ev, opt, k, out, ev_obj_off, ws, ws_bytes, stream, false);
+}
+
+lst_status lst_set_timing(lst_ctx *c, int32_t enable) {
+    if (!c) return LST_E_INVAL;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (enable && !c->events_made) {
+        for (int i = 0; i < kTimingEvents; ++i) HIP_TRY(c, hipEventCreate(&c->tev[i]));
+        c->events_made = true;
+    }
+    c->timing = enable != 0;
+    return LST_OK;
+}
+
+lst_status lst_stage_times(lst_ctx *c, float *ms, int32_t n) {
+    if (!c || !ms || n < 0) return LST_E_INVAL;
+    if (!c->events_made) return fail(c, LST_E_STATE, "timing was never enabled");
+    for (int i = 0; i < n && i < kTimingWindows; ++i)
+        HIP_TRY(c, hipEventElapsedTime(&ms[i], c->tev[2 * i], c->tev[2 * i + 1]));
+    return LST_OK;
 }
 
 lst_status lst_score(lst_ctx *c, const void *X, int32_t x_dtype, int64_t n, float *scores, int32_t precision,

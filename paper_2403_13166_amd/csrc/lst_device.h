@@ -16,7 +16,8 @@ namespace lst {
 constexpr int kNFeat = 42;
 constexpr int kH1 = 32;
 constexpr int kH2 = 32;
-constexpr int kTile = 256;          // candidates per compaction tile (= block size)
+constexpr int kPerThread = 4;       // candidates per thread and tile
+constexpr int kTile = 256 * kPerThread;   // candidates per compaction tile
 
 // ------------------------------------------------------------------ layout
 

@@ -68,7 +68,13 @@ struct RunArgs {
     int32_t mode, precision;
     float score_min;
     int64_t *ev_obj_off;              // device [4][n_ev + 1] or null
+    hipEvent_t *timing;               // null, or kTimingEvents events recorded around the stages
 };
+
+// Timing windows (pairs of events): 0 whole build, 1 binning, 2 MD, 3 LS,
+// 4 T3, 5 T5 compaction kernels, 6 T5 features + DNN scoring.
+constexpr int kTimingWindows = 7;
+constexpr int kTimingEvents = 2 * kTimingWindows;
 
 // Enqueue the whole object-building pipeline on `stream`.
 hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipStream_t stream);

@@ -188,9 +188,11 @@ __global__ __launch_bounds__(kBlock) void k_stage_eval(S st, const int64_t *cand
                                                        unsigned long long *state, int64_t max_tiles,
                                                        uint32_t *ticket, int64_t *out_count,
                                                        int64_t cap_out) {
+    constexpr int kWaves = kBlock / 64;
+    constexpr int kSeg = kPerThread * kWaves;     // output segments, in candidate order
     __shared__ int64_t s_tile, s_base;
     __shared__ int64_t s_alo, s_ahi;
-    __shared__ int s_wcnt[kBlock / 64];
+    __shared__ int s_cnt[kSeg];
     const int64_t na = n_dev ? dev_count(n_dev, n_cap) : n_cap;
     const int64_t total = cand_off[na];
     int64_t ntiles = (total + kTile - 1) / kTile;
@@ -208,55 +210,80 @@ __global__ __launch_bounds__(kBlock) void k_stage_eval(S st, const int64_t *cand
         __syncthreads();
         const int64_t tile = s_tile;
         if (tile >= ntiles) break;
-        const int64_t g = tile * kTile + threadIdx.x;
-        typename S::Rec rec;
-        bool pass = false;
-        if (g < total) {
-            // largest anchor a in [alo, ahi] with cand_off[a] <= g
-            int64_t lo = s_alo, hi = s_ahi + 1;
-            while (hi - lo > 1) {
-                int64_t mid = (lo + hi) >> 1;
-                if (cand_off[mid] <= g) lo = mid; else hi = mid;
-            }
-            pass = st.eval(lo, g - cand_off[lo], rec);
-        }
-        const unsigned long long m = __ballot(pass);
-        const int rank = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) s_wcnt[wv] = __popcll(m);
-        __syncthreads();
-        int woff = 0, tcnt = 0;
+        // candidate g = tile * kTile + i * kBlock + tid: each sub-round i is a
+        // contiguous run of kBlock candidates (coalesced reads)
+        typename S::Rec rec[kPerThread];
+        bool pass[kPerThread];
+        int64_t lo = s_alo;
+        const int64_t ahi = s_ahi;
 #pragma unroll
-        for (int k = 0; k < kBlock / 64; ++k) { if (k < wv) woff += s_wcnt[k]; tcnt += s_wcnt[k]; }
-        if (threadIdx.x == 0) {
-            int64_t excl = 0;
-            if (tile == 0) {
-                __hip_atomic_store(&state[0], kFlagPre | (unsigned long long)tcnt, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                __hip_atomic_store(&state[tile], kFlagAgg | (unsigned long long)tcnt, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                // decoupled look-back: every predecessor tile is held by a
-                // running block that publishes its aggregate before waiting
-                int64_t j = tile - 1;
-                for (;;) {
-                    unsigned long long sv = __hip_atomic_load(&state[j], __ATOMIC_ACQUIRE,
-                                                              __HIP_MEMORY_SCOPE_AGENT);
-                    unsigned long long fl = sv & ~kValMask;
-                    if (fl == 0ull) { __builtin_amdgcn_s_sleep(1); continue; }
-                    excl += (int64_t)(sv & kValMask);
-                    if (fl == kFlagPre) break;
-                    --j;
+        for (int i = 0; i < kPerThread; ++i) {
+            const int64_t g = tile * kTile + i * kBlock + threadIdx.x;
+            pass[i] = false;
+            if (g < total) {
+                // largest anchor a in [lo, ahi] with cand_off[a] <= g (g grows with i)
+                int64_t hi = ahi + 1;
+                while (hi - lo > 1) {
+                    int64_t mid = (lo + hi) >> 1;
+                    if (cand_off[mid] <= g) lo = mid; else hi = mid;
                 }
-                __hip_atomic_store(&state[tile], kFlagPre | (unsigned long long)(excl + tcnt),
-                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                pass[i] = st.eval(lo, g - cand_off[lo], rec[i]);
             }
-            s_base = excl;
-            if (tile == ntiles - 1) *out_count = excl + tcnt;
+        }
+        int rank[kPerThread];
+#pragma unroll
+        for (int i = 0; i < kPerThread; ++i) {
+            const unsigned long long m = __ballot(pass[i]);
+            rank[i] = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) s_cnt[i * kWaves + wv] = __popcll(m);
         }
         __syncthreads();
-        if (pass) {
-            int64_t pos = s_base + woff + rank;
-            if (pos < cap_out) st.write(pos, rec);
+        int tcnt = 0;
+#pragma unroll
+        for (int k = 0; k < kSeg; ++k) tcnt += s_cnt[k];
+        if (wv == 0) {
+            // decoupled look-back, one wavefront probing 64 predecessor tiles
+            // at a time; every predecessor is held by a running block that
+            // publishes its aggregate before it looks back itself
+            int64_t excl = 0;
+            if (lane == 0)
+                __hip_atomic_store(&state[tile], (tile == 0 ? kFlagPre : kFlagAgg) | (unsigned long long)tcnt,
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            int64_t top = tile - 1;
+            while (top >= 0) {
+                const int64_t j = top - lane;
+                unsigned long long sv = kFlagPre;    // before tile 0: prefix 0
+                if (j >= 0) sv = __hip_atomic_load(&state[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long fl = sv & ~kValMask;
+                const unsigned long long pre = __ballot(fl == kFlagPre);
+                const unsigned long long zero = __ballot(fl == 0ull);
+                const int p = pre ? __ffsll((long long)pre) - 1 : 64;   // nearest prefix
+                const unsigned long long upto = p >= 63 ? ~0ull : ((1ull << (p + 1)) - 1ull);
+                if (zero & upto) { __builtin_amdgcn_s_sleep(1); continue; }
+                int64_t v = lane <= p ? (int64_t)(sv & kValMask) : 0;
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+                excl += v;
+                if (p < 64) break;
+                top -= 64;
+            }
+            if (lane == 0) {
+                if (tile > 0)
+                    __hip_atomic_store(&state[tile], kFlagPre | (unsigned long long)(excl + tcnt),
+                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                s_base = excl;
+                if (tile == ntiles - 1) *out_count = excl + tcnt;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kPerThread; ++i) {
+            if (pass[i]) {
+                int off = 0;
+                for (int k = 0; k < i * kWaves + wv; ++k) off += s_cnt[k];
+                const int64_t pos = s_base + off + rank[i];
+                if (pos < cap_out) st.write(pos, rec[i]);
+            }
         }
         __syncthreads();
     }
@@ -268,16 +295,22 @@ struct StageCount {
     __device__ int64_t operator()(int64_t a) const { return s.count(a); }
 };
 
+static inline void mark(hipEvent_t *ev, int k, hipStream_t st) {
+    if (ev) (void)hipEventRecord(ev[k], st);
+}
+
 template <class S>
 static void run_stage(const S &s, const int64_t *n_dev, int64_t n_cap, const Work &w, int64_t *out_count,
-                      int64_t cap_out, int64_t *counts, hipStream_t st) {
+                      int64_t cap_out, int64_t *counts, hipStream_t st, hipEvent_t *ev, int win) {
     scan(StageCount<S>{s}, n_dev, n_cap, w, w.cand_off, w.tile_anchor, st);
     hipLaunchKernelGGL(k_stage_clear, dim3(grid_for(w.max_tiles)), dim3(kBlock), 0, st, w.cand_off,
                        n_dev, n_cap, w.tile_state, w.max_tiles, w.ticket, out_count, counts, w.cap_cand);
     int nb = (int)(w.max_tiles < kEvalBlocks ? w.max_tiles : kEvalBlocks);
     if (nb < 1) nb = 1;
+    mark(ev, 2 * win, st);
     hipLaunchKernelGGL(k_stage_eval<S>, dim3(nb), dim3(kBlock), 0, st, s, w.cand_off, n_dev, n_cap,
                        w.tile_anchor, w.tile_state, w.max_tiles, w.ticket, out_count, cap_out);
+    mark(ev, 2 * win + 1, st);
 }
 
 // ------------------------------------------------------------- binning
@@ -687,8 +720,11 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     const int64_t ngm = (int64_t)a.n_ev * n_mod;
     int64_t *cnt = o.counts;
 
+    hipEvent_t *ev = a.timing;
+    mark(ev, 0, st);
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, cnt, (int64_t)LST_COUNTS_LEN, (int64_t)0);
     // a1: bin hits by (event, sensor)
+    mark(ev, 2, st);
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nbins)), dim3(kBlock), 0, st, w.bin_cnt, nbins, 0);
     hipLaunchKernelGGL(k_bin_count, dim3(grid_for(a.n_hits)), dim3(kBlock), 0, st, a.sensor, a.n_hits, a.ev_off,
                        a.n_ev, n_sens, w.bin_cnt, cnt);
@@ -696,10 +732,11 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(a.n_hits)), dim3(kBlock), 0, st, a.x, a.y, a.z, a.sensor,
                        a.n_hits, a.ev_off, a.n_ev, n_sens, w.bin_off, w.bin_cnt, w.bin_hit);
     hipLaunchKernelGGL(k_bin_sort, dim3(grid_for(nbins)), dim3(kBlock), 0, st, w.bin_off, nbins, w.bin_hit);
+    mark(ev, 3, st);
 
     // a2: mini-doublets, anchored on (event, module)
     MDStage md{w.bin_off, w.bin_hit, a.g.mod, a.p, n_mod, n_sens, o.md_hits, w.md_a, w.md_o};
-    run_stage(md, nullptr, ngm, w, cnt + LST_COUNT_MD, w.cap_md, cnt, st);
+    run_stage(md, nullptr, ngm, w, cnt + LST_COUNT_MD, w.cap_md, cnt, st, ev, 2);
     hipLaunchKernelGGL(k_fill_offsets<GmKey>, dim3(grid_for(w.cap_md)), dim3(kBlock), 0, st, GmKey{w.md_a},
                        cnt + LST_COUNT_MD, w.cap_md, nullptr, ngm, w.md_mod_off);
     hipLaunchKernelGGL(k_ls_prefix, dim3(grid_for(ngm)), dim3(kBlock), 0, st, a.g.map_off, a.g.map_tgt, n_mod,
@@ -708,7 +745,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     // a3: line segments, anchored on the inner MD, over the mapped modules
     LSStage ls{w.md_a, w.md_o, w.md_mod_off, w.rsum, w.rpref, a.g.map_off, a.g.map_tgt, a.g.mod, a.p,
                n_mod, n_map, o.ls_md};
-    run_stage(ls, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st);
+    run_stage(ls, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st, ev, 3);
     hipLaunchKernelGGL(k_fill_offsets<LsInKey>, dim3(grid_for(w.cap_ls)), dim3(kBlock), 0, st, LsInKey{o.ls_md},
                        cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w.ls_off);
     bucket_sort(LsOutKey{o.ls_md}, cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w, w.lsT_off,
@@ -716,7 +753,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
 
     // a4: triplets, anchored on the shared (middle) MD
     T3Stage t3{o.ls_md, w.ls_off, w.lsT_off, w.lsT_idx, w.md_a, w.md_o, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
-    run_stage(t3, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st);
+    run_stage(t3, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st, ev, 4);
     bucket_sort(T3InKey{w.t3_mds}, cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w, w.t3i_off,
                 w.t3i_idx, st);
     bucket_sort(T3OutKey{w.t3_mds}, cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w, w.t3o_off,
@@ -725,23 +762,26 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     // a5: quintuplets, anchored on the shared MD; FP64 fits
     T5Stage t5{w.t3_mds, w.t3o_off, w.t3i_off, w.t3o_idx, w.t3i_idx, w.md_a, a.g.mod, a.p, a.m, n_mod,
                a.mode, a.score_min, o.t5_t3, o.t5_chi2_rphi, o.t5_chi2_rz};
-    run_stage(t5, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st);
+    run_stage(t5, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, ev, 5);
 
     // a6: features and T5-DNN scores (BF16 MFMA runs over the feature rows;
     // a score cut forces the FP32 path, which the T5 stage itself applied)
     bool mfma = a.mode == 0 && a.precision == 1 && !(a.score_min == a.score_min);
     float *feat = o.t5_feat ? o.t5_feat : (mfma ? w.t5_feat : nullptr);
+    mark(ev, 12, st);
     hipLaunchKernelGGL(k_t5_score_f32, dim3(grid_for(w.cap_t5)), dim3(kBlock), 0, st, t5,
                        cnt + LST_COUNT_T5, w.cap_t5, o.t5_score, feat, (int)!mfma);
     if (mfma) {
         hipError_t e = score_rows_dev(a.m, feat, cnt + LST_COUNT_T5, w.cap_t5, o.t5_score, st);
         if (e != hipSuccess) return e;
     }
+    mark(ev, 13, st);
     if (a.ev_obj_off) {
         hipLaunchKernelGGL(k_event_offsets, dim3((a.n_ev + 64) / 64), dim3(64), 0, st, w.md_mod_off, w.ls_off,
                            w.t3_mds, o.t5_t3, cnt, w.cap_md, w.cap_ls, w.cap_t3, w.cap_t5, n_mod, a.n_ev,
                            a.ev_obj_off);
     }
+    mark(ev, 1, st);
     return hipGetLastError();
 }
 

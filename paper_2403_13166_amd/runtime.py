@@ -206,6 +206,41 @@ class Builder:
             return self._slice((out.n_md, out.n_ls, out.n_t3, out.n_t5), with_features, ev)
         raise B.LstError(B.LST_E_CAPACITY, "capacity still exceeded after retries")
 
+    def launch(self, x, y, z, sensor, event_offsets: torch.Tensor | None = None, mode: int = B.LST_MODE_DNN,
+               precision: int = B.LST_PREC_F32, score_min: float = float("nan"),
+               with_features: bool = False) -> None:
+        """Enqueue one build on the current stream with the reserved capacities,
+        without synchronising (LST_ASYNC): safe to capture into a HIP graph.
+        Read the outcome afterwards with device_counts() / view()."""
+        n = int(x.shape[0])
+        n_ev = 1 if event_offsets is None else int(event_offsets.shape[0]) - 1
+        if self.caps is None or self.caps.hits < n or self.caps.events < n_ev:
+            raise ValueError("reserve() capacities for this input first")
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        hits = B.LstHits(_ptr(x), _ptr(y), _ptr(z), _ptr(sensor), n)
+        opts = B.LstOptions(int(mode), int(precision), float(score_min), B.LST_ASYNC)
+        out = self._objects_struct(with_features)
+        if event_offsets is None:
+            B.lst_build_objects(self.ctx, hits, opts, self.caps.c(), out, self._ws_ptr(), self.ws_bytes, stream)
+        else:
+            B.lst_build_objects_batched(self.ctx, hits, _ptr(event_offsets), n_ev, opts, self.caps.c(), out,
+                                        _ptr(self._buf["ev_obj"]), self._ws_ptr(), self.ws_bytes, stream)
+        self._last_n_ev = n_ev
+
+    def device_counts(self) -> list:
+        """Counts of the last launched build (synchronises): md, ls, t3, t5, err, max_cand."""
+        return self._buf["counts"].cpu().tolist()
+
+    def view(self, with_features: bool = False) -> Objects:
+        """Objects of the last launched build (after device_counts() shows no overflow)."""
+        c = self.device_counts()
+        if c[B.LST_COUNT_ERR] or c[0] > self.caps.md or c[1] > self.caps.ls or c[2] > self.caps.t3 \
+                or c[3] > self.caps.t5:
+            raise B.LstError(B.LST_E_CAPACITY, f"last build overflowed or failed: counts {c}")
+        n_ev = getattr(self, "_last_n_ev", 1)
+        ev = self._buf["ev_obj"].view(-1)[:4 * (n_ev + 1)].view(4, n_ev + 1)
+        return self._slice(c[:4], with_features, ev)
+
     def score(self, X: torch.Tensor, precision: int = B.LST_PREC_BF16) -> torch.Tensor:
         """T5-DNN scores of feature rows X [n, 42] (f32 or bf16, device)."""
         if X.dim() != 2 or X.shape[1] != B.N_FEATURES or not X.is_contiguous():
