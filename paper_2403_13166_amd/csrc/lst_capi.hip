@@ -226,7 +226,8 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     const int64_t nsens = 2 * (int64_t)c->n_mod, nmod = c->n_mod;
     const int64_t ev = k->events > 0 ? k->events : 1;
     const int64_t md = k->md > 0 ? k->md : 1;
-    const int64_t max_tiles = (k->cand + kTile - 1) / kTile + 1;
+    // tiles of kMinTile candidates, with room for the largest tile's rounding
+    const int64_t max_tiles = (k->cand + kMinTile - 1) / kMinTile + 8;
     int64_t anchors = ev * nmod;
     if (md > anchors) anchors = md;
     Work x{};
@@ -238,8 +239,10 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     x.cand_off = (int64_t *)take(8 * (anchors + 1));
     x.scan_part = (int64_t *)take(8 * (kScanBlocks + 1));
     x.tile_anchor = (int32_t *)take(4 * (max_tiles + 1));
-    x.tile_state = (unsigned long long *)take(8 * max_tiles);
-    x.ticket = (uint32_t *)take(32);
+    x.tile_cnt = (int32_t *)take(4 * max_tiles);
+    x.tile_pre = (int64_t *)take(8 * (max_tiles + 1));
+    x.ntiles = (int64_t *)take(8);
+    x.rec_scratch = (void *)take((size_t)kMaxRecBytes * kMinTile * max_tiles);
     x.md_a = (float4 *)take(16 * md);
     x.md_o = (float2 *)take(8 * md);
     x.md_mod_off = (int64_t *)take(8 * (ev * nmod + 1));

@@ -16,8 +16,7 @@ namespace lst {
 constexpr int kNFeat = 42;
 constexpr int kH1 = 32;
 constexpr int kH2 = 32;
-constexpr int kPerThread = 4;       // candidates per thread and tile
-constexpr int kTile = 256 * kPerThread;   // candidates per compaction tile
+constexpr int kMinTile = 256;       // smallest compaction tile (candidates)
 
 // ------------------------------------------------------------------ layout
 

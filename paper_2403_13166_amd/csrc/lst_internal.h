@@ -14,6 +14,7 @@ constexpr int kBlock = 256;
 constexpr int kScanBlocks = 1024;
 constexpr int kEvalBlocks = 4096;     // persistent compaction blocks (256 CUs x 16)
 constexpr int kMaxStride = 8192;      // grid cap of grid-stride kernels
+constexpr int kMaxRecBytes = 32;      // largest per-candidate record a stage compacts
 
 struct Work {
     // capacities
@@ -27,8 +28,10 @@ struct Work {
     int64_t *cand_off;                // [n_anchor_cap + 1]
     int64_t *scan_part;               // [kScanBlocks + 1]
     int32_t *tile_anchor;             // [max_tiles + 1]
-    unsigned long long *tile_state;   // [max_tiles]
-    uint32_t *ticket;                 // [8]
+    int32_t *tile_cnt;                // [max_tiles] survivors per tile
+    int64_t *tile_pre;                // [max_tiles + 1] their exclusive scan
+    int64_t *ntiles;                  // [1] tiles of the current stage
+    void *rec_scratch;                // [max_tiles * kMinTile] records of kMaxRecBytes
     // MD
     float4 *md_a;                     // [cap_md] anchor x, y, z, global module (bits)
     float2 *md_o;                     // [cap_md] other hit x, y

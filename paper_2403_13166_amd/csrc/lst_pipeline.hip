@@ -3,15 +3,19 @@
 // compaction kernel over its candidate pairs.
 //
 // Every stage has the same shape:
-//   * anchors (a module for MD, an MD for LS / T3 / T5) own a contiguous range
-//     of candidate pairs (left x right lists); a device-wide exclusive scan of
-//     the per-anchor counts gives the ranges and, for every 256-candidate tile,
-//     the anchor its first candidate belongs to;
-//   * a persistent kernel takes tiles in order from a ticket counter, each
-//     thread decodes one candidate and applies the cuts, the block compacts the
-//     survivors with a wavefront ballot + LDS scan, and tiles chain their
-//     output offsets with a decoupled look-back, so the output is in candidate
-//     order (deterministic) without per-object global atomics;
+//   * anchors (a module for MD and LS, an MD for T3 and T5) own a contiguous
+//     range of candidate pairs (left list x right list); a device-wide
+//     exclusive scan of the per-anchor counts gives the ranges and, for every
+//     tile of candidates, the anchor its first candidate belongs to;
+//   * an eval kernel walks the tiles (grid-stride). The block first stages the
+//     tile's window of anchor offsets and per-anchor list bases in LDS (for
+//     LS also the module-map tables of those modules), so decoding a
+//     candidate into its (left, right) pair is LDS work; each thread then
+//     applies the cuts to S::kPer candidates and the block compacts the
+//     survivors with wavefront ballots into the tile's scratch slot. No block
+//     ever waits for another: a scan of the tile counts and a copy kernel
+//     place the survivors. Output is in candidate order (deterministic)
+//     without per-object global atomics;
 //   * CSR offsets the next stage needs are filled from the sorted outputs.
 // Grid shapes depend only on capacities, never on data, so a whole build can be
 // captured into a HIP graph.
@@ -89,7 +93,7 @@ __device__ __forceinline__ int64_t block_incl_scan(int64_t v, int64_t *tot) {
 // ------------------------------------------------------------------ scan
 // Exclusive scan of count(i), i < n (n from device or host), into out[0..n],
 // out[n] = total. With tile_anchor != null also records, for every tile of
-// kTile scanned positions, the index i whose range holds the tile's start.
+// `tile` scanned positions, the index i whose range holds the tile's start.
 
 template <class F>
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(F f, const int64_t *n_dev, int64_t n_cap,
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(1024) void k_scan_partials(int64_t *part, int nb) {
 template <class F>
 __global__ __launch_bounds__(kBlock) void k_scan_down(F f, const int64_t *n_dev, int64_t n_cap,
                                                       const int64_t *part, int64_t *out,
-                                                      int32_t *tile_anchor, int64_t max_tiles) {
+                                                      int32_t *tile_anchor, int64_t max_tiles, int tile) {
     int64_t n = n_dev ? dev_count(n_dev, n_cap) : n_cap;
     int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(F f, const int64_t *n_dev,
         if (i < b1) {
             out[i] = o;
             if (tile_anchor && c > 0) {
-                int64_t t0 = (o + kTile - 1) / kTile, t1 = (o + c - 1) / kTile;
+                int64_t t0 = (o + tile - 1) / tile, t1 = (o + c - 1) / tile;
                 for (int64_t t = t0; t <= t1 && t < max_tiles; ++t) tile_anchor[t] = (int32_t)i;
             }
         }
@@ -147,145 +151,155 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(F f, const int64_t *n_dev,
 
 template <class F>
 static void scan(F f, const int64_t *n_dev, int64_t n_cap, const Work &w, int64_t *out,
-                 int32_t *tile_anchor, hipStream_t st) {
+                 int32_t *tile_anchor, hipStream_t st, int tile = 256) {
     int nb = (int)((n_cap + kBlock - 1) / kBlock);
     if (nb < 1) nb = 1;
     if (nb > kScanBlocks) nb = kScanBlocks;
     hipLaunchKernelGGL(k_scan_reduce<F>, dim3(nb), dim3(kBlock), 0, st, f, n_dev, n_cap, w.scan_part);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, w.scan_part, nb);
     hipLaunchKernelGGL(k_scan_down<F>, dim3(nb), dim3(kBlock), 0, st, f, n_dev, n_cap, w.scan_part,
-                       out, tile_anchor, w.max_tiles);
+                       out, tile_anchor, w.max_tiles, tile);
 }
 
 // ------------------------------------------------ compaction (one stage)
 
-// Reset the look-back state for the tiles of this stage and record the
-// candidate total (error bit 1 if it exceeds the candidate capacity).
-__global__ void k_stage_clear(const int64_t *cand_off, const int64_t *n_dev, int64_t n_cap,
-                              unsigned long long *state, int64_t max_tiles, uint32_t *ticket,
-                              int64_t *out_count, int64_t *counts, int64_t cap_cand) {
-    int64_t na = n_dev ? dev_count(n_dev, n_cap) : n_cap;
-    int64_t total = cand_off[na];
-    int64_t nt = (total + kTile - 1) / kTile;
-    if (nt > max_tiles) nt = max_tiles;
-    for (int64_t i = grid_tid(); i < nt; i += grid_stride()) state[i] = 0ull;
-    if (grid_tid() == 0) {
-        *ticket = 0u;
-        *out_count = 0;
-        atomicMax((unsigned long long *)&counts[LST_COUNT_MAXCAND], (unsigned long long)total);
-        if (total > cap_cand) atomicOr((unsigned long long *)&counts[LST_COUNT_ERR], 2ull);
-    }
-}
+struct CntF {
+    const int32_t *c;
+    __device__ int64_t operator()(int64_t i) const { return c[i]; }
+};
 
-constexpr unsigned long long kFlagAgg = 1ull << 62;
-constexpr unsigned long long kFlagPre = 2ull << 62;
-constexpr unsigned long long kValMask = (1ull << 62) - 1;
+constexpr int kWin = 512;   // anchors of one tile staged in LDS
 
+// LDS of one tile: the anchor offsets and per-anchor list bases of the tile's
+// window, and (LS only) the module-map tables of the window's modules.
+template <int kEnt>
+struct TileLds {
+    int64_t off[kWin + 1];
+    int32_t info[kWin][4];
+    int32_t ebase[kEnt > 0 ? kWin : 1];   // first table entry of each window anchor
+    int32_t ek0[kEnt > 0 ? kWin : 1];     // its first module-map entry
+    int32_t ent_rp[kEnt > 0 ? kEnt : 1];
+    int32_t ent_md[kEnt > 0 ? kEnt : 1];
+    int32_t ent_mod[kEnt > 0 ? kEnt : 1];
+};
+
+// Compaction of one stage in three steps, none of which waits on another
+// block: (1) the eval kernel takes tiles of kBlock * S::kPer candidates
+// (grid-stride), stages the tile's anchor window in LDS, applies the cuts and
+// compacts each tile's survivors, in candidate order, into that tile's slot of
+// a scratch buffer, with the tile's count; (2) an exclusive scan of the tile
+// counts gives every tile its output offset; (3) a copy kernel moves each
+// tile's survivors to their final position. Output order = candidate order.
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_stage_eval(S st, const int64_t *cand_off,
                                                        const int64_t *n_dev, int64_t n_cap,
-                                                       const int32_t *tile_anchor,
-                                                       unsigned long long *state, int64_t max_tiles,
-                                                       uint32_t *ticket, int64_t *out_count,
-                                                       int64_t cap_out) {
+                                                       const int32_t *tile_anchor, int64_t max_tiles,
+                                                       int32_t *tile_cnt, typename S::Rec *scratch,
+                                                       int64_t *ntiles_out, int64_t *counts, int64_t cap_cand) {
     constexpr int kWaves = kBlock / 64;
-    constexpr int kSeg = kPerThread * kWaves;     // output segments, in candidate order
-    __shared__ int64_t s_tile, s_base;
-    __shared__ int64_t s_alo, s_ahi;
+    constexpr int kPer = S::kPer;
+    constexpr int kTileC = kBlock * kPer;
+    constexpr int kSeg = kPer * kWaves;     // output segments, in candidate order
+    __shared__ TileLds<S::kEnt> L;
     __shared__ int s_cnt[kSeg];
     const int64_t na = n_dev ? dev_count(n_dev, n_cap) : n_cap;
     const int64_t total = cand_off[na];
-    int64_t ntiles = (total + kTile - 1) / kTile;
-    if (ntiles > max_tiles) ntiles = max_tiles;
+    int64_t ntiles = (total + kTileC - 1) / kTileC;
+    // max_tiles counts tiles of kMinTile candidates (the scratch size)
+    const int64_t max_t = max_tiles * kMinTile / kTileC;
+    if (ntiles > max_t) ntiles = max_t;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *ntiles_out = ntiles;
+        atomicMax((unsigned long long *)&counts[LST_COUNT_MAXCAND], (unsigned long long)total);
+        if (total > cap_cand) atomicOr((unsigned long long *)&counts[LST_COUNT_ERR], 2ull);
+    }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            int64_t t = (int64_t)atomicAdd(ticket, 1u);
-            s_tile = t;
-            if (t < ntiles) {
-                s_alo = tile_anchor[t];
-                s_ahi = (t + 1 < ntiles) ? (int64_t)tile_anchor[t + 1] : na - 1;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t alo = tile_anchor[tile];
+        const int64_t ahi = (tile + 1 < ntiles) ? (int64_t)tile_anchor[tile + 1] : na - 1;
+        const int nw = (int)(ahi - alo + 1 < (int64_t)kWin + 1 ? ahi - alo + 1 : (int64_t)kWin + 1);
+        const bool staged = nw <= kWin;
+        if (staged) {
+            for (int i = threadIdx.x; i <= nw; i += kBlock) {
+                L.off[i] = cand_off[alo + i];
+                if (i < nw) st.info(alo + i, L.info[i]);
             }
+            __syncthreads();
+            st.prepare(L, alo, nw);
         }
-        __syncthreads();
-        const int64_t tile = s_tile;
-        if (tile >= ntiles) break;
-        // candidate g = tile * kTile + i * kBlock + tid: each sub-round i is a
+        // candidate g = tile * kTileC + i * kBlock + tid: each sub-round i is a
         // contiguous run of kBlock candidates (coalesced reads)
-        typename S::Rec rec[kPerThread];
-        bool pass[kPerThread];
-        int64_t lo = s_alo;
-        const int64_t ahi = s_ahi;
+        typename S::Rec rec[kPer];
+        bool pass[kPer];
+        int wlo = 0;                 // window index (staged)
+        int64_t glo = alo;           // anchor index (global search)
 #pragma unroll
-        for (int i = 0; i < kPerThread; ++i) {
-            const int64_t g = tile * kTile + i * kBlock + threadIdx.x;
+        for (int i = 0; i < kPer; ++i) {
+            const int64_t g = tile * kTileC + i * kBlock + threadIdx.x;
             pass[i] = false;
             if (g < total) {
-                // largest anchor a in [lo, ahi] with cand_off[a] <= g (g grows with i)
-                int64_t hi = ahi + 1;
-                while (hi - lo > 1) {
-                    int64_t mid = (lo + hi) >> 1;
-                    if (cand_off[mid] <= g) lo = mid; else hi = mid;
+                if (staged) {
+                    int hi = nw;      // largest w in [wlo, nw) with off[w] <= g
+                    while (hi - wlo > 1) {
+                        int mid = (wlo + hi) >> 1;
+                        if (L.off[mid] <= g) wlo = mid; else hi = mid;
+                    }
+                    pass[i] = st.eval(alo + wlo, (int32_t)(g - L.off[wlo]), L.info[wlo], L, rec[i]);
+                } else {
+                    int64_t hi = ahi + 1;
+                    while (hi - glo > 1) {
+                        int64_t mid = (glo + hi) >> 1;
+                        if (cand_off[mid] <= g) glo = mid; else hi = mid;
+                    }
+                    int32_t f[4];
+                    st.info(glo, f);
+                    f[2] = S::kEnt > 0 ? -1 : f[2];
+                    pass[i] = st.eval(glo, (int32_t)(g - cand_off[glo]), f, L, rec[i]);
                 }
-                pass[i] = st.eval(lo, g - cand_off[lo], rec[i]);
             }
         }
-        int rank[kPerThread];
+        int rank[kPer];
 #pragma unroll
-        for (int i = 0; i < kPerThread; ++i) {
+        for (int i = 0; i < kPer; ++i) {
             const unsigned long long m = __ballot(pass[i]);
             rank[i] = __popcll(m & ((1ull << lane) - 1ull));
             if (lane == 0) s_cnt[i * kWaves + wv] = __popcll(m);
         }
         __syncthreads();
-        int tcnt = 0;
+        typename S::Rec *slot = scratch + tile * kTileC;
 #pragma unroll
-        for (int k = 0; k < kSeg; ++k) tcnt += s_cnt[k];
-        if (wv == 0) {
-            // decoupled look-back, one wavefront probing 64 predecessor tiles
-            // at a time; every predecessor is held by a running block that
-            // publishes its aggregate before it looks back itself
-            int64_t excl = 0;
-            if (lane == 0)
-                __hip_atomic_store(&state[tile], (tile == 0 ? kFlagPre : kFlagAgg) | (unsigned long long)tcnt,
-                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            int64_t top = tile - 1;
-            while (top >= 0) {
-                const int64_t j = top - lane;
-                unsigned long long sv = kFlagPre;    // before tile 0: prefix 0
-                if (j >= 0) sv = __hip_atomic_load(&state[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned long long fl = sv & ~kValMask;
-                const unsigned long long pre = __ballot(fl == kFlagPre);
-                const unsigned long long zero = __ballot(fl == 0ull);
-                const int p = pre ? __ffsll((long long)pre) - 1 : 64;   // nearest prefix
-                const unsigned long long upto = p >= 63 ? ~0ull : ((1ull << (p + 1)) - 1ull);
-                if (zero & upto) { __builtin_amdgcn_s_sleep(1); continue; }
-                int64_t v = lane <= p ? (int64_t)(sv & kValMask) : 0;
-#pragma unroll
-                for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-                excl += v;
-                if (p < 64) break;
-                top -= 64;
-            }
-            if (lane == 0) {
-                if (tile > 0)
-                    __hip_atomic_store(&state[tile], kFlagPre | (unsigned long long)(excl + tcnt),
-                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                s_base = excl;
-                if (tile == ntiles - 1) *out_count = excl + tcnt;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < kPerThread; ++i) {
+        for (int i = 0; i < kPer; ++i) {
             if (pass[i]) {
                 int off = 0;
                 for (int k = 0; k < i * kWaves + wv; ++k) off += s_cnt[k];
-                const int64_t pos = s_base + off + rank[i];
-                if (pos < cap_out) st.write(pos, rec[i]);
+                slot[off + rank[i]] = rec[i];
             }
         }
+        if (threadIdx.x == 0) {
+            int tcnt = 0;
+            for (int k = 0; k < kSeg; ++k) tcnt += s_cnt[k];
+            tile_cnt[tile] = tcnt;
+        }
         __syncthreads();
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_stage_copy(S st, const typename S::Rec *scratch,
+                                                       const int32_t *tile_cnt, const int64_t *tile_pre,
+                                                       const int64_t *ntiles_dev, int64_t *out_count,
+                                                       int64_t cap_out) {
+    constexpr int kTileC = kBlock * S::kPer;
+    const int64_t ntiles = *ntiles_dev;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *out_count = tile_pre[ntiles];
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int n = tile_cnt[tile];
+        const int64_t base = tile_pre[tile];
+        const typename S::Rec *slot = scratch + tile * kTileC;
+        for (int i = threadIdx.x; i < n; i += kBlock) {
+            const int64_t pos = base + i;
+            if (pos < cap_out) st.write(pos, slot[i]);
+        }
     }
 }
 
@@ -302,15 +316,19 @@ static inline void mark(hipEvent_t *ev, int k, hipStream_t st) {
 template <class S>
 static void run_stage(const S &s, const int64_t *n_dev, int64_t n_cap, const Work &w, int64_t *out_count,
                       int64_t cap_out, int64_t *counts, hipStream_t st, hipEvent_t *ev, int win) {
-    scan(StageCount<S>{s}, n_dev, n_cap, w, w.cand_off, w.tile_anchor, st);
-    hipLaunchKernelGGL(k_stage_clear, dim3(grid_for(w.max_tiles)), dim3(kBlock), 0, st, w.cand_off,
-                       n_dev, n_cap, w.tile_state, w.max_tiles, w.ticket, out_count, counts, w.cap_cand);
+    static_assert(sizeof(typename S::Rec) <= kMaxRecBytes, "scratch record too large");
+    const int tile = kBlock * S::kPer;
+    scan(StageCount<S>{s}, n_dev, n_cap, w, w.cand_off, w.tile_anchor, st, tile);
     int nb = (int)(w.max_tiles < kEvalBlocks ? w.max_tiles : kEvalBlocks);
     if (nb < 1) nb = 1;
+    typename S::Rec *scratch = (typename S::Rec *)w.rec_scratch;
     mark(ev, 2 * win, st);
     hipLaunchKernelGGL(k_stage_eval<S>, dim3(nb), dim3(kBlock), 0, st, s, w.cand_off, n_dev, n_cap,
-                       w.tile_anchor, w.tile_state, w.max_tiles, w.ticket, out_count, cap_out);
+                       w.tile_anchor, w.max_tiles, w.tile_cnt, scratch, w.ntiles, counts, w.cap_cand);
     mark(ev, 2 * win + 1, st);
+    scan(CntF{w.tile_cnt}, w.ntiles, w.max_tiles, w, w.tile_pre, nullptr, st);
+    hipLaunchKernelGGL(k_stage_copy<S>, dim3(nb), dim3(kBlock), 0, st, s, scratch, w.tile_cnt, w.tile_pre,
+                       w.ntiles, out_count, cap_out);
 }
 
 // ------------------------------------------------------------- binning
@@ -361,6 +379,8 @@ __global__ void k_bin_sort(const int64_t *off, int64_t nbins, float4 *hit) {
 }
 
 // ------------------------------------------------------------ MD stage
+// Anchor: (event, module). Left = hits on the anchor sensor, right = hits on
+// the other sensor. info = {first left hit, n left, n right, module}.
 
 struct MDStage {
     const int64_t *bin_off;
@@ -371,21 +391,30 @@ struct MDStage {
     int2 *md_hits;
     float4 *md_a;
     float2 *md_o;
-    struct Rec { int hl, hu; float4 a; float2 o; };
+    static constexpr int kEnt = 0;
+    static constexpr int kPer = 4;
+    struct Rec { float4 a; float2 o; int hl, hu; };
 
     __device__ int64_t count(int64_t gm) const {
         int64_t e = gm / n_mod, m = gm - e * n_mod;
         int64_t b = e * n_sens + 2 * m;
         return (bin_off[b + 1] - bin_off[b]) * (bin_off[b + 2] - bin_off[b + 1]);
     }
-    __device__ bool eval(int64_t gm, int64_t local, Rec &r) const {
+    __device__ void info(int64_t gm, int32_t *f) const {
         int64_t e = gm / n_mod, m = gm - e * n_mod;
         int64_t b = e * n_sens + 2 * m;
-        int nR = (int)(bin_off[b + 2] - bin_off[b + 1]);
-        int l = (int)local / nR, rr = (int)local - l * nR;
-        float4 hi = bin_hit[bin_off[b] + l];
-        float4 hj = bin_hit[bin_off[b + 1] + rr];
-        bool ok = md_pass(mod[m], p, P3{hi.x, hi.y, hi.z}, P3{hj.x, hj.y, hj.z});
+        int64_t b0 = bin_off[b], b1 = bin_off[b + 1], b2 = bin_off[b + 2];
+        f[0] = (int32_t)b0; f[1] = (int32_t)(b1 - b0); f[2] = (int32_t)(b2 - b1); f[3] = (int32_t)m;
+    }
+    template <class LDS>
+    __device__ void prepare(LDS &, int64_t, int) const {}
+    template <class LDS>
+    __device__ bool eval(int64_t gm, int32_t local, const int32_t *f, const LDS &, Rec &r) const {
+        const int nR = f[2];
+        const int l = local / nR, rr = local - l * nR;
+        float4 hi = bin_hit[f[0] + l];
+        float4 hj = bin_hit[f[0] + f[1] + rr];
+        bool ok = md_pass(mod[f[3]], p, P3{hi.x, hi.y, hi.z}, P3{hj.x, hj.y, hj.z});
         r.hl = __float_as_int(hi.w); r.hu = __float_as_int(hj.w);
         r.a = make_float4(hi.x, hi.y, hi.z, __int_as_float((int)gm));
         r.o = make_float2(hj.x, hj.y);
@@ -431,6 +460,9 @@ __global__ void k_ls_prefix(const int32_t *map_off, const int32_t *map_tgt, int3
 }
 
 // ------------------------------------------------------------ LS stage
+// Anchor: (event, module). Left = the module's MDs, right = the MDs of every
+// module in its map entry list, concatenated in map order. info = {first left
+// MD, n right, LDS base of the map-entry table (-1: not staged), n entries}.
 
 struct LSStage {
     const float4 *md_a;
@@ -442,24 +474,87 @@ struct LSStage {
     CutParams p;
     int32_t n_mod, n_map;
     int2 *ls_md;
+    static constexpr int kEnt = 1536;
+    static constexpr int kPer = 4;
     struct Rec { int a, b; };
 
-    __device__ int64_t count(int64_t a) const { return rsum[__float_as_int(md_a[a].w)]; }
-    __device__ bool eval(int64_t a, int64_t local, Rec &r) const {
-        float4 A = md_a[a];
-        int gm = __float_as_int(A.w);
-        int e = gm / n_mod, m = gm - e * n_mod;
-        const int32_t *rp = rpref + (int64_t)e * n_map;
-        int lo = map_off[m], hi = map_off[m + 1];   // largest k with rp[k] <= local
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (rp[mid] <= local) lo = mid; else hi = mid;
+    __device__ int64_t count(int64_t gm) const {
+        return (md_mod_off[gm + 1] - md_mod_off[gm]) * (int64_t)rsum[gm];
+    }
+    __device__ void info(int64_t gm, int32_t *f) const {
+        int64_t e = gm / n_mod, m = gm - e * n_mod;
+        f[0] = (int32_t)md_mod_off[gm];
+        f[1] = rsum[gm];
+        f[2] = -1;
+        f[3] = map_off[m + 1] - map_off[m];
+    }
+    // stage the map-entry tables of the window's non-empty modules: one entry
+    // per thread, so the dependent loads of all entries overlap
+    template <class LDS>
+    __device__ void prepare(LDS &L, int64_t alo, int nw) const {
+        // thread t owns window anchors 2t and 2t+1 (nw <= 2 * kBlock)
+        const int i0 = 2 * threadIdx.x, i1 = i0 + 1;
+        const int d0 = (i0 < nw && L.off[i0 + 1] > L.off[i0]) ? L.info[i0][3] : 0;
+        const int d1 = (i1 < nw && L.off[i1 + 1] > L.off[i1]) ? L.info[i1][3] : 0;
+        int64_t tot;
+        const int64_t inc = block_incl_scan((int64_t)(d0 + d1), &tot);
+        const int base0 = (int)(inc - d0 - d1), base1 = base0 + d0;
+        const bool fits = tot <= kEnt;
+        if (fits) {
+            if (i0 < nw) { L.ebase[i0] = base0; L.ek0[i0] = d0 ? map_off[(alo + i0) % n_mod] : 0; }
+            if (i1 < nw) { L.ebase[i1] = base1; L.ek0[i1] = d1 ? map_off[(alo + i1) % n_mod] : 0; }
+            if (d0) L.info[i0][2] = base0;
+            if (d1) L.info[i1][2] = base1;
         }
-        int mb = map_tgt[lo];
-        int64_t b = md_mod_off[(int64_t)e * n_mod + mb] + (local - rp[lo]);
-        float4 B = md_a[b];
+        __syncthreads();
+        if (fits) {
+            for (int q = threadIdx.x; q < (int)tot; q += kBlock) {
+                int lo = 0, hi = nw;      // window anchor owning entry q
+                while (hi - lo > 1) {
+                    int mid = (lo + hi) >> 1;
+                    if (L.ebase[mid] <= q) lo = mid; else hi = mid;
+                }
+                const int64_t gm = alo + lo;
+                const int64_t e = gm / n_mod;
+                const int32_t k = L.ek0[lo] + (q - L.ebase[lo]);
+                const int32_t tg = map_tgt[k];
+                L.ent_rp[q] = rpref[e * n_map + k];
+                L.ent_md[q] = (int32_t)md_mod_off[e * n_mod + tg];
+                L.ent_mod[q] = tg;
+            }
+        }
+        __syncthreads();
+    }
+    template <class LDS>
+    __device__ bool eval(int64_t gm, int32_t local, const int32_t *f, const LDS &L, Rec &r) const {
+        const int nR = f[1];
+        const int l = local / nR, rr = local - l * nR;
+        const int64_t a = f[0] + l;
+        int64_t b;
+        int mb;
+        if (f[2] >= 0) {
+            int lo = f[2], hi = f[2] + f[3];   // largest entry with ent_rp <= rr
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (L.ent_rp[mid] <= rr) lo = mid; else hi = mid;
+            }
+            b = L.ent_md[lo] + (rr - L.ent_rp[lo]);
+            mb = L.ent_mod[lo];
+        } else {
+            const int64_t e = gm / n_mod, m = gm - e * n_mod;
+            const int32_t *rp = rpref + e * n_map;
+            int lo = map_off[m], hi = map_off[m + 1];
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (rp[mid] <= rr) lo = mid; else hi = mid;
+            }
+            mb = map_tgt[lo];
+            b = md_mod_off[e * n_mod + mb] + (rr - rp[lo]);
+        }
+        const int ma = (int)(gm % n_mod);
+        float4 A = md_a[a], B = md_a[b];
         r.a = (int)a; r.b = (int)b;
-        bool eA = mod[m].kind != 0, eB = mod[mb].kind != 0;
+        bool eA = mod[ma].kind != 0, eB = mod[mb].kind != 0;
         float c, sg;
         if (!pair_pass(p, P3{A.x, A.y, A.z}, eA, P3{B.x, B.y, B.z}, eB, c, sg)) return false;
         float cp = fminf(c, p.cmax);
@@ -503,10 +598,6 @@ __global__ void k_bucket_sort(const int64_t *off, const int64_t *K_dev, int64_t 
     }
 }
 
-struct CntF {
-    const int32_t *c;
-    __device__ int64_t operator()(int64_t i) const { return c[i]; }
-};
 
 template <class KF>
 static void bucket_sort(KF key, const int64_t *n_dev, int64_t n_cap, const int64_t *K_dev, int64_t K_cap,
@@ -522,6 +613,8 @@ static void bucket_sort(KF key, const int64_t *n_dev, int64_t n_cap, const int64
 }
 
 // ------------------------------------------------------------ T3 stage
+// Anchor: the shared MD B. Left = LS ending at B, right = LS starting at B.
+// info = {first left entry in lsT_idx, n left, first right LS, n right}.
 
 struct T3Stage {
     const int2 *ls_md;
@@ -534,17 +627,27 @@ struct T3Stage {
     int32_t n_mod;
     int2 *t3_ls;
     int4 *t3_mds;
+    static constexpr int kEnt = 0;
+    static constexpr int kPer = 2;
     struct Rec { int li, lo, A, B, C; };
 
     __device__ int64_t count(int64_t B) const {
         return (lsT_off[B + 1] - lsT_off[B]) * (ls_off[B + 1] - ls_off[B]);
     }
-    __device__ bool eval(int64_t B, int64_t local, Rec &r) const {
-        int nR = (int)(ls_off[B + 1] - ls_off[B]);
-        int l = (int)local / nR, rr = (int)local - l * nR;
-        int li = lsT_idx[lsT_off[B] + l];
-        int lo = (int)(ls_off[B] + rr);
-        int A = ls_md[li].x, C = ls_md[lo].y;
+    __device__ void info(int64_t B, int32_t *f) const {
+        int64_t t0 = lsT_off[B], l0 = ls_off[B];
+        f[0] = (int32_t)t0; f[1] = (int32_t)(lsT_off[B + 1] - t0);
+        f[2] = (int32_t)l0; f[3] = (int32_t)(ls_off[B + 1] - l0);
+    }
+    template <class LDS>
+    __device__ void prepare(LDS &, int64_t, int) const {}
+    template <class LDS>
+    __device__ bool eval(int64_t B, int32_t local, const int32_t *f, const LDS &, Rec &r) const {
+        const int nR = f[3];
+        const int l = local / nR, rr = local - l * nR;
+        const int li = lsT_idx[f[0] + l];
+        const int lo = f[2] + rr;
+        const int A = ls_md[li].x, C = ls_md[lo].y;
         r.li = li; r.lo = lo; r.A = A; r.B = (int)B; r.C = C;
         float4 a = md_a[A], b = md_a[B], c = md_a[C];
         int ma = __float_as_int(a.w) % n_mod, mb = __float_as_int(b.w) % n_mod, mc = __float_as_int(c.w) % n_mod;
@@ -564,7 +667,11 @@ struct T3Stage {
 };
 
 // ------------------------------------------------------------ T5 stage
+// Anchor: the shared MD C. Left = T3 ending at C, right = T3 starting at C.
+// info = {first left entry in t3o_idx, n left, first right entry in t3i_idx,
+// n right}. kScoreCut adds the optional T5-DNN score cut (FP32 VALU).
 
+template <bool kScoreCut>
 struct T5Stage {
     const int4 *t3_mds;
     const int64_t *t3o_off, *t3i_off;
@@ -577,19 +684,29 @@ struct T5Stage {
     float score_min;
     int2 *t5_t3;
     float *chi2_rphi, *chi2_rz;
+    static constexpr int kEnt = 0;
+    static constexpr int kPer = 1;
     struct Rec { int u, v; float cr, cz; };
 
     __device__ int64_t count(int64_t C) const {
         return (t3o_off[C + 1] - t3o_off[C]) * (t3i_off[C + 1] - t3i_off[C]);
     }
-    __device__ bool eval(int64_t C, int64_t local, Rec &r) const {
-        int nR = (int)(t3i_off[C + 1] - t3i_off[C]);
-        int l = (int)local / nR, rr = (int)local - l * nR;
-        int u = t3o_idx[t3o_off[C] + l];
-        int v = t3i_idx[t3i_off[C] + rr];
-        int4 m1 = t3_mds[u], m2 = t3_mds[v];
+    __device__ void info(int64_t C, int32_t *f) const {
+        int64_t o0 = t3o_off[C], i0 = t3i_off[C];
+        f[0] = (int32_t)o0; f[1] = (int32_t)(t3o_off[C + 1] - o0);
+        f[2] = (int32_t)i0; f[3] = (int32_t)(t3i_off[C + 1] - i0);
+    }
+    template <class LDS>
+    __device__ void prepare(LDS &, int64_t, int) const {}
+    template <class LDS>
+    __device__ bool eval(int64_t, int32_t local, const int32_t *f, const LDS &, Rec &r) const {
+        const int nR = f[3];
+        const int l = local / nR, rr = local - l * nR;
+        const int u = t3o_idx[f[0] + l];
+        const int v = t3i_idx[f[2] + rr];
+        const int4 m1 = t3_mds[u], m2 = t3_mds[v];
         r.u = u; r.v = v; r.cr = 0.f; r.cz = 0.f;
-        int ids[5] = {m1.x, m1.y, m1.z, m2.y, m2.z};
+        const int ids[5] = {m1.x, m1.y, m1.z, m2.y, m2.z};
         float4 an[5];
         bool endc[5];
         int lay[5];
@@ -606,14 +723,14 @@ struct T5Stage {
         double x[5], y[5], z[5];
 #pragma unroll
         for (int i = 0; i < 5; ++i) { x[i] = an[i].x; y[i] = an[i].y; z[i] = an[i].z; }
-        Fit5 f;
-        t5_fit(p, x, y, z, endc, f);
-        r.cr = (float)f.chi2_rphi; r.cz = (float)f.chi2_rz;
-        if (!(f.chi2_rz <= (double)p.chi2rz)) return false;
-        if (mode == 1 && !(f.chi2_rphi <= (double)p.chi2rphi)) return false;
-        if (mode == 0 && score_min == score_min) {
+        Fit5 fit;
+        t5_fit(p, x, y, z, endc, fit);
+        r.cr = (float)fit.chi2_rphi; r.cz = (float)fit.chi2_rz;
+        if (!(fit.chi2_rz <= (double)p.chi2rz)) return false;
+        if (mode == 1 && !(fit.chi2_rphi <= (double)p.chi2rphi)) return false;
+        if (kScoreCut) {
             float ft[kNFeat];
-            t5_features(p, x, y, z, lay, endc, f, ft);
+            t5_features(p, x, y, z, lay, endc, fit, ft);
             if (!(score_min <= mlp_f32(mdl, ft))) return false;
         }
         return true;
@@ -626,7 +743,7 @@ struct T5Stage {
 };
 
 // T5 features and T5-DNN score, one thread per T5 (FP32 vector ALU).
-__global__ __launch_bounds__(kBlock) void k_t5_score_f32(T5Stage s, const int64_t *n_dev, int64_t cap,
+__global__ __launch_bounds__(kBlock) void k_t5_score_f32(T5Stage<false> s, const int64_t *n_dev, int64_t cap,
                                                          float *score, float *feat, int do_mlp) {
     int64_t n = dev_count(n_dev, cap);
     for (int64_t i = grid_tid(); i < n; i += grid_stride()) {
@@ -742,10 +859,11 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     hipLaunchKernelGGL(k_ls_prefix, dim3(grid_for(ngm)), dim3(kBlock), 0, st, a.g.map_off, a.g.map_tgt, n_mod,
                        n_map, a.n_ev, w.md_mod_off, w.rsum, w.rpref);
 
-    // a3: line segments, anchored on the inner MD, over the mapped modules
+    // a3: line segments, anchored on (event, module): the module's MDs against
+    // the MDs of its mapped modules
     LSStage ls{w.md_a, w.md_o, w.md_mod_off, w.rsum, w.rpref, a.g.map_off, a.g.map_tgt, a.g.mod, a.p,
                n_mod, n_map, o.ls_md};
-    run_stage(ls, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st, ev, 3);
+    run_stage(ls, nullptr, ngm, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st, ev, 3);
     hipLaunchKernelGGL(k_fill_offsets<LsInKey>, dim3(grid_for(w.cap_ls)), dim3(kBlock), 0, st, LsInKey{o.ls_md},
                        cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w.ls_off);
     bucket_sort(LsOutKey{o.ls_md}, cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w, w.lsT_off,
@@ -760,13 +878,20 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
                 w.t3o_idx, st);
 
     // a5: quintuplets, anchored on the shared MD; FP64 fits
-    T5Stage t5{w.t3_mds, w.t3o_off, w.t3i_off, w.t3o_idx, w.t3i_idx, w.md_a, a.g.mod, a.p, a.m, n_mod,
-               a.mode, a.score_min, o.t5_t3, o.t5_chi2_rphi, o.t5_chi2_rz};
-    run_stage(t5, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, ev, 5);
+    const bool score_cut = a.mode == 0 && a.score_min == a.score_min;
+    T5Stage<false> t5{w.t3_mds, w.t3o_off, w.t3i_off, w.t3o_idx, w.t3i_idx, w.md_a, a.g.mod, a.p, a.m, n_mod,
+                      a.mode, a.score_min, o.t5_t3, o.t5_chi2_rphi, o.t5_chi2_rz};
+    if (score_cut) {
+        T5Stage<true> t5c{w.t3_mds, w.t3o_off, w.t3i_off, w.t3o_idx, w.t3i_idx, w.md_a, a.g.mod, a.p, a.m, n_mod,
+                          a.mode, a.score_min, o.t5_t3, o.t5_chi2_rphi, o.t5_chi2_rz};
+        run_stage(t5c, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, ev, 5);
+    } else {
+        run_stage(t5, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, ev, 5);
+    }
 
     // a6: features and T5-DNN scores (BF16 MFMA runs over the feature rows;
     // a score cut forces the FP32 path, which the T5 stage itself applied)
-    bool mfma = a.mode == 0 && a.precision == 1 && !(a.score_min == a.score_min);
+    bool mfma = a.mode == 0 && a.precision == 1 && !score_cut;
     float *feat = o.t5_feat ? o.t5_feat : (mfma ? w.t5_feat : nullptr);
     mark(ev, 12, st);
     hipLaunchKernelGGL(k_t5_score_f32, dim3(grid_for(w.cap_t5)), dim3(kBlock), 0, st, t5,

@@ -32,21 +32,22 @@ class Caps:
         n = max(int(n_hits), 1)
         e = max(int(n_events), 1)
         return Caps(hits=n, events=e, md=n // 2 + 4096 * e, ls=n + 8192 * e, t3=2 * n + 8192 * e,
-                    t5=n + 8192 * e, cand=48 * n + (1 << 20))
+                    t5=n + 8192 * e, cand=12 * n + (1 << 20))
 
     def grown(self, counts) -> "Caps":
         """Capacities that hold the required counts of a failed call, with headroom.
         A stage that overflowed fed only part of its objects to the later
         stages, whose reported counts are then underestimates: those are
-        scaled up by the square of the truncation ratio."""
+        scaled by the truncation ratio (bounded), and later calls grow again
+        if that was not enough."""
         caps = [self.md, self.ls, self.t3, self.t5]
         out, factor = [], 1.0
         for cur, need in zip(caps, counts[:4]):
             need_eff = need * factor
             out.append(max(cur, int(math.ceil(need_eff * 1.25)) + 1024))
             if need > cur:
-                factor *= (need / max(cur, 1)) ** 2
-        cand = max(self.cand, int(math.ceil(counts[5] * factor * 1.25)) + 4096)
+                factor = min(8.0, factor * need / max(cur, 1))
+        cand = max(self.cand, int(math.ceil(counts[5] * min(factor, 4.0) * 1.25)) + 4096)
         return Caps(self.hits, self.events, *out, cand)
 
     def c(self) -> B.LstCaps:
