@@ -60,6 +60,7 @@ typedef int32_t lst_status;
 #define LST_COUNT_T5 3
 #define LST_COUNT_ERR 4      /* bit 0 bad sensor id, bit 1 candidate cap, bit 2 object cap */
 #define LST_COUNT_MAXCAND 5  /* largest candidate count of any stage (required cand cap) */
+#define LST_COUNT_T5PRE 6    /* T3 pairs passing the quintuplet's FP32 cuts (bounded by cand cap) */
 #define LST_COUNTS_LEN 8
 
 #define LST_N_FEATURES 42

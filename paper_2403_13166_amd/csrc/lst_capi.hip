@@ -228,8 +228,10 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     const int64_t md = k->md > 0 ? k->md : 1;
     // tiles of kMinTile candidates, with room for the largest tile's rounding
     const int64_t max_tiles = (k->cand + kMinTile - 1) / kMinTile + 8;
+    // anchors: modules (MD, LS), LS (T3), T3 (T5 pre-cuts), pre-candidates (T5 fits)
     int64_t anchors = ev * nmod;
-    if (md > anchors) anchors = md;
+    for (int64_t v : {md, k->ls, k->t3, k->cand})
+        if (v > anchors) anchors = v;
     Work x{};
     x.cap_hits = k->hits; x.cap_ev = ev; x.cap_md = md; x.cap_ls = k->ls; x.cap_t3 = k->t3;
     x.cap_t5 = k->t5; x.cap_cand = k->cand; x.max_tiles = max_tiles; x.n_anchor_cap = anchors;
@@ -249,14 +251,10 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     x.rsum = (int32_t *)take(4 * ev * nmod);
     x.rpref = (int32_t *)take(4 * ev * (c->n_map > 0 ? c->n_map : 1));
     x.ls_off = (int64_t *)take(8 * (md + 1));
-    x.lsT_off = (int64_t *)take(8 * (md + 1));
-    x.lsT_idx = (int32_t *)take(4 * (k->ls > 0 ? k->ls : 1));
-    x.bucket_cnt = (int32_t *)take(4 * md);
     x.t3_mds = (int4 *)take(16 * (k->t3 > 0 ? k->t3 : 1));
     x.t3i_off = (int64_t *)take(8 * (md + 1));
-    x.t3i_idx = (int32_t *)take(4 * (k->t3 > 0 ? k->t3 : 1));
-    x.t3o_off = (int64_t *)take(8 * (md + 1));
-    x.t3o_idx = (int32_t *)take(4 * (k->t3 > 0 ? k->t3 : 1));
+    x.cap_t5pre = k->cand;
+    x.t5_pre = (int2 *)take(8 * (k->cand > 0 ? k->cand : 1));
     x.t5_feat = (float *)take(4 * kNFeat * (k->t5 > 0 ? k->t5 : 1));
     x.ev_off = (int64_t *)take(16);
     if (w) *w = x;
@@ -332,7 +330,8 @@ static lst_status build_common(lst_ctx *c, const lst_hits *h, const int64_t *ev_
     HIP_TRY(c, hipStreamSynchronize(st));
     out->n_md = cnt[0]; out->n_ls = cnt[1]; out->n_t3 = cnt[2]; out->n_t5 = cnt[3];
     if (cnt[LST_COUNT_ERR] & 1) return fail(c, LST_E_INVAL, "sensor id out of range in the hits");
-    if ((cnt[LST_COUNT_ERR] & 2) || cnt[0] > k->md || cnt[1] > k->ls || cnt[2] > k->t3 || cnt[3] > k->t5)
+    if ((cnt[LST_COUNT_ERR] & 2) || cnt[0] > k->md || cnt[1] > k->ls || cnt[2] > k->t3 || cnt[3] > k->t5 ||
+        cnt[LST_COUNT_T5PRE] > k->cand)
         return fail(c, LST_E_CAPACITY, "capacity exceeded: md %lld/%lld ls %lld/%lld t3 %lld/%lld t5 %lld/%lld cand %lld/%lld",
                     (long long)cnt[0], (long long)k->md, (long long)cnt[1], (long long)k->ls, (long long)cnt[2],
                     (long long)k->t3, (long long)cnt[3], (long long)k->t5, (long long)cnt[LST_COUNT_MAXCAND],

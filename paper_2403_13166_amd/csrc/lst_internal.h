@@ -40,15 +40,12 @@ struct Work {
     int32_t *rpref;                   // [cap_ev * n_map] exclusive prefix over map entries
     // LS
     int64_t *ls_off;                  // [cap_md + 1] CSR by inner MD
-    int64_t *lsT_off;                 // [cap_md + 1] CSR by outer MD
-    int32_t *lsT_idx;                 // [cap_ls]
-    int32_t *bucket_cnt;              // [cap_md]
     // T3
     int4 *t3_mds;                     // [cap_t3] MDs (A, B, C)
-    int64_t *t3i_off;                 // [cap_md + 1] T3 by inner MD
-    int32_t *t3i_idx;                 // [cap_t3]
-    int64_t *t3o_off;                 // [cap_md + 1] T3 by outer MD
-    int32_t *t3o_idx;                 // [cap_t3]
+    int64_t *t3i_off;                 // [cap_md + 1] T3 by inner MD (they are sorted by it)
+    // T5
+    int64_t cap_t5pre;
+    int2 *t5_pre;                     // [cap_t5pre] T3 pairs passing the FP32 cuts
     float *t5_feat;                   // [cap_t5][42] feature rows for the MFMA scorer
     int64_t *ev_off;                  // [2] event offsets of a single-event call
 };

@@ -565,61 +565,15 @@ struct LSStage {
     __device__ void write(int64_t pos, const Rec &r) const { ls_md[pos] = make_int2(r.a, r.b); }
 };
 
-// ---------------------------------------------------------- bucket sorts
-// Deterministic counting sort of item ids by key (ids ascending in a bucket).
-
-template <class KF>
-__global__ void k_bucket_count(KF key, const int64_t *n_dev, int64_t n_cap, int32_t *cnt) {
-    int64_t n = dev_count(n_dev, n_cap);
-    for (int64_t i = grid_tid(); i < n; i += grid_stride()) atomicAdd(&cnt[key(i)], 1);
-}
-
-template <class KF>
-__global__ void k_bucket_scatter(KF key, const int64_t *n_dev, int64_t n_cap, const int64_t *off,
-                                 int32_t *cnt, int32_t *idx) {
-    int64_t n = dev_count(n_dev, n_cap);
-    for (int64_t i = grid_tid(); i < n; i += grid_stride()) {
-        int k = key(i);
-        int64_t pos = off[k] + (int64_t)atomicSub(&cnt[k], 1) - 1;
-        idx[pos] = (int32_t)i;
-    }
-}
-
-__global__ void k_bucket_sort(const int64_t *off, const int64_t *K_dev, int64_t K_cap, int32_t *idx) {
-    int64_t K = dev_count(K_dev, K_cap);
-    for (int64_t b = grid_tid(); b < K; b += grid_stride()) {
-        int64_t s = off[b], e = off[b + 1];
-        for (int64_t i = s + 1; i < e; ++i) {
-            int32_t v = idx[i];
-            int64_t j = i - 1;
-            while (j >= s && idx[j] > v) { idx[j + 1] = idx[j]; --j; }
-            idx[j + 1] = v;
-        }
-    }
-}
-
-
-template <class KF>
-static void bucket_sort(KF key, const int64_t *n_dev, int64_t n_cap, const int64_t *K_dev, int64_t K_cap,
-                        const Work &w, int64_t *off, int32_t *idx, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill_i32_dev, dim3(grid_for(K_cap)), dim3(kBlock), 0, st, w.bucket_cnt, K_dev,
-                       K_cap, 0);
-    hipLaunchKernelGGL(k_bucket_count<KF>, dim3(grid_for(n_cap)), dim3(kBlock), 0, st, key, n_dev, n_cap,
-                       w.bucket_cnt);
-    scan(CntF{w.bucket_cnt}, K_dev, K_cap, w, off, nullptr, st);
-    hipLaunchKernelGGL(k_bucket_scatter<KF>, dim3(grid_for(n_cap)), dim3(kBlock), 0, st, key, n_dev, n_cap,
-                       off, w.bucket_cnt, idx);
-    hipLaunchKernelGGL(k_bucket_sort, dim3(grid_for(K_cap)), dim3(kBlock), 0, st, off, K_dev, K_cap, idx);
-}
-
 // ------------------------------------------------------------ T3 stage
-// Anchor: the shared MD B. Left = LS ending at B, right = LS starting at B.
-// info = {first left entry in lsT_idx, n left, first right LS, n right}.
+// Anchor: the inner LS (A, B); candidates: every LS starting at B, which the
+// LS output (sorted by inner MD) holds contiguously. T3 come out sorted by
+// inner LS, hence by inner MD A: the next stage reads T3 starting at an MD
+// as one contiguous range. info = {first outer LS, n outer LS, A, B}.
 
 struct T3Stage {
     const int2 *ls_md;
-    const int64_t *ls_off, *lsT_off;
-    const int32_t *lsT_idx;
+    const int64_t *ls_off;
     const float4 *md_a;
     const float2 *md_o;
     const ModConst *mod;
@@ -631,24 +585,23 @@ struct T3Stage {
     static constexpr int kPer = 2;
     struct Rec { int li, lo, A, B, C; };
 
-    __device__ int64_t count(int64_t B) const {
-        return (lsT_off[B + 1] - lsT_off[B]) * (ls_off[B + 1] - ls_off[B]);
+    __device__ int64_t count(int64_t l1) const {
+        const int B = ls_md[l1].y;
+        return ls_off[B + 1] - ls_off[B];
     }
-    __device__ void info(int64_t B, int32_t *f) const {
-        int64_t t0 = lsT_off[B], l0 = ls_off[B];
-        f[0] = (int32_t)t0; f[1] = (int32_t)(lsT_off[B + 1] - t0);
-        f[2] = (int32_t)l0; f[3] = (int32_t)(ls_off[B + 1] - l0);
+    __device__ void info(int64_t l1, int32_t *f) const {
+        const int2 lm = ls_md[l1];
+        const int64_t o0 = ls_off[lm.y];
+        f[0] = (int32_t)o0; f[1] = (int32_t)(ls_off[lm.y + 1] - o0); f[2] = lm.x; f[3] = lm.y;
     }
     template <class LDS>
     __device__ void prepare(LDS &, int64_t, int) const {}
     template <class LDS>
-    __device__ bool eval(int64_t B, int32_t local, const int32_t *f, const LDS &, Rec &r) const {
-        const int nR = f[3];
-        const int l = local / nR, rr = local - l * nR;
-        const int li = lsT_idx[f[0] + l];
-        const int lo = f[2] + rr;
-        const int A = ls_md[li].x, C = ls_md[lo].y;
-        r.li = li; r.lo = lo; r.A = A; r.B = (int)B; r.C = C;
+    __device__ bool eval(int64_t l1, int32_t local, const int32_t *f, const LDS &, Rec &r) const {
+        const int lo = f[0] + local;
+        const int A = f[2], B = f[3];
+        const int C = ls_md[lo].y;
+        r.li = (int)l1; r.lo = lo; r.A = A; r.B = B; r.C = C;
         float4 a = md_a[A], b = md_a[B], c = md_a[C];
         int ma = __float_as_int(a.w) % n_mod, mb = __float_as_int(b.w) % n_mod, mc = __float_as_int(c.w) % n_mod;
         float cv, sg;
@@ -667,15 +620,72 @@ struct T3Stage {
 };
 
 // ------------------------------------------------------------ T5 stage
-// Anchor: the shared MD C. Left = T3 ending at C, right = T3 starting at C.
-// info = {first left entry in t3o_idx, n left, first right entry in t3i_idx,
-// n right}. kScoreCut adds the optional T5-DNN score cut (FP32 VALU).
+// In two passes so that the FP64 fits run on dense lanes:
+//  (a) anchor: the inner T3 (A, B, C); candidates: every T3 starting at C
+//      (contiguous in the T3 output); the FP32 beam-line cuts on (A, E)
+//      select pre-candidates (T3 pairs) in candidate order;
+//  (b) anchor: one pre-candidate each; both fits, the chi2 cuts and, with a
+//      score threshold, the T5-DNN cut. T5 come out sorted by inner T3.
+
+struct T5PreStage {
+    const int4 *t3_mds;
+    const int64_t *t3i_off;
+    const float4 *md_a;
+    const ModConst *mod;
+    CutParams p;
+    int32_t n_mod;
+    int2 *pre;
+    static constexpr int kEnt = 0;
+    static constexpr int kPer = 2;
+    struct Rec { int u, v; };
+
+    __device__ int64_t count(int64_t u) const {
+        const int C = t3_mds[u].z;
+        return t3i_off[C + 1] - t3i_off[C];
+    }
+    __device__ void info(int64_t u, int32_t *f) const {
+        const int4 m1 = t3_mds[u];
+        const int64_t o0 = t3i_off[m1.z];
+        f[0] = (int32_t)o0; f[1] = (int32_t)(t3i_off[m1.z + 1] - o0); f[2] = m1.x; f[3] = 0;
+    }
+    template <class LDS>
+    __device__ void prepare(LDS &, int64_t, int) const {}
+    template <class LDS>
+    __device__ bool eval(int64_t u, int32_t local, const int32_t *f, const LDS &, Rec &r) const {
+        const int v = f[0] + local;
+        r.u = (int)u; r.v = v;
+        const int E = t3_mds[v].z;
+        const float4 a = md_a[f[2]], e = md_a[E];
+        float cv, sg;
+        return pair_pass(p, P3{a.x, a.y, a.z}, mod[__float_as_int(a.w) % n_mod].kind != 0, P3{e.x, e.y, e.z},
+                         mod[__float_as_int(e.w) % n_mod].kind != 0, cv, sg);
+    }
+    __device__ void write(int64_t pos, const Rec &r) const { pre[pos] = make_int2(r.u, r.v); }
+};
+
+// anchors of a T5 candidate, FP64, with module kinds and layers
+struct T5Anchors {
+    double x[5], y[5], z[5];
+    bool endc[5];
+    int lay[5];
+};
+
+__device__ __forceinline__ void load_t5_anchors(const int4 *t3_mds, const float4 *md_a, const ModConst *mod,
+                                                int32_t n_mod, int u, int v, T5Anchors &t) {
+    const int4 m1 = t3_mds[u], m2 = t3_mds[v];
+    const int ids[5] = {m1.x, m1.y, m1.z, m2.y, m2.z};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const float4 a = md_a[ids[k]];
+        const ModConst &mc = mod[__float_as_int(a.w) % n_mod];
+        t.x[k] = a.x; t.y[k] = a.y; t.z[k] = a.z; t.endc[k] = mc.kind != 0; t.lay[k] = mc.layer;
+    }
+}
 
 template <bool kScoreCut>
-struct T5Stage {
+struct T5FitStage {
+    const int2 *pre;
     const int4 *t3_mds;
-    const int64_t *t3o_off, *t3i_off;
-    const int32_t *t3o_idx, *t3i_idx;
     const float4 *md_a;
     const ModConst *mod;
     CutParams p;
@@ -688,49 +698,24 @@ struct T5Stage {
     static constexpr int kPer = 1;
     struct Rec { int u, v; float cr, cz; };
 
-    __device__ int64_t count(int64_t C) const {
-        return (t3o_off[C + 1] - t3o_off[C]) * (t3i_off[C + 1] - t3i_off[C]);
-    }
-    __device__ void info(int64_t C, int32_t *f) const {
-        int64_t o0 = t3o_off[C], i0 = t3i_off[C];
-        f[0] = (int32_t)o0; f[1] = (int32_t)(t3o_off[C + 1] - o0);
-        f[2] = (int32_t)i0; f[3] = (int32_t)(t3i_off[C + 1] - i0);
-    }
+    __device__ int64_t count(int64_t) const { return 1; }
+    __device__ void info(int64_t, int32_t *f) const { f[0] = f[1] = f[2] = f[3] = 0; }
     template <class LDS>
     __device__ void prepare(LDS &, int64_t, int) const {}
     template <class LDS>
-    __device__ bool eval(int64_t, int32_t local, const int32_t *f, const LDS &, Rec &r) const {
-        const int nR = f[3];
-        const int l = local / nR, rr = local - l * nR;
-        const int u = t3o_idx[f[0] + l];
-        const int v = t3i_idx[f[2] + rr];
-        const int4 m1 = t3_mds[u], m2 = t3_mds[v];
-        r.u = u; r.v = v; r.cr = 0.f; r.cz = 0.f;
-        const int ids[5] = {m1.x, m1.y, m1.z, m2.y, m2.z};
-        float4 an[5];
-        bool endc[5];
-        int lay[5];
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            an[i] = md_a[ids[i]];
-            const ModConst &mc = mod[__float_as_int(an[i].w) % n_mod];
-            endc[i] = mc.kind != 0;
-            lay[i] = mc.layer;
-        }
-        float cv, sg;
-        if (!pair_pass(p, P3{an[0].x, an[0].y, an[0].z}, endc[0], P3{an[4].x, an[4].y, an[4].z}, endc[4], cv, sg))
-            return false;
-        double x[5], y[5], z[5];
-#pragma unroll
-        for (int i = 0; i < 5; ++i) { x[i] = an[i].x; y[i] = an[i].y; z[i] = an[i].z; }
+    __device__ bool eval(int64_t q, int32_t, const int32_t *, const LDS &, Rec &r) const {
+        const int2 uv = pre[q];
+        r.u = uv.x; r.v = uv.y;
+        T5Anchors t;
+        load_t5_anchors(t3_mds, md_a, mod, n_mod, uv.x, uv.y, t);
         Fit5 fit;
-        t5_fit(p, x, y, z, endc, fit);
+        t5_fit(p, t.x, t.y, t.z, t.endc, fit);
         r.cr = (float)fit.chi2_rphi; r.cz = (float)fit.chi2_rz;
         if (!(fit.chi2_rz <= (double)p.chi2rz)) return false;
         if (mode == 1 && !(fit.chi2_rphi <= (double)p.chi2rphi)) return false;
         if (kScoreCut) {
             float ft[kNFeat];
-            t5_features(p, x, y, z, lay, endc, fit, ft);
+            t5_features(p, t.x, t.y, t.z, t.lay, t.endc, fit, ft);
             if (!(score_min <= mlp_f32(mdl, ft))) return false;
         }
         return true;
@@ -743,26 +728,17 @@ struct T5Stage {
 };
 
 // T5 features and T5-DNN score, one thread per T5 (FP32 vector ALU).
-__global__ __launch_bounds__(kBlock) void k_t5_score_f32(T5Stage<false> s, const int64_t *n_dev, int64_t cap,
+__global__ __launch_bounds__(kBlock) void k_t5_score_f32(T5FitStage<false> s, const int64_t *n_dev, int64_t cap,
                                                          float *score, float *feat, int do_mlp) {
     int64_t n = dev_count(n_dev, cap);
     for (int64_t i = grid_tid(); i < n; i += grid_stride()) {
-        int2 uv = s.t5_t3[i];
-        int4 m1 = s.t3_mds[uv.x], m2 = s.t3_mds[uv.y];
-        int ids[5] = {m1.x, m1.y, m1.z, m2.y, m2.z};
-        double x[5], y[5], z[5];
-        bool endc[5];
-        int lay[5];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            float4 a = s.md_a[ids[k]];
-            const ModConst &mc = s.mod[__float_as_int(a.w) % s.n_mod];
-            x[k] = a.x; y[k] = a.y; z[k] = a.z; endc[k] = mc.kind != 0; lay[k] = mc.layer;
-        }
+        const int2 uv = s.t5_t3[i];
+        T5Anchors t;
+        load_t5_anchors(s.t3_mds, s.md_a, s.mod, s.n_mod, uv.x, uv.y, t);
         Fit5 f;
-        t5_fit(s.p, x, y, z, endc, f);
+        t5_fit(s.p, t.x, t.y, t.z, t.endc, f);
         float ft[kNFeat];
-        t5_features(s.p, x, y, z, lay, endc, f, ft);
+        t5_features(s.p, t.x, t.y, t.z, t.lay, t.endc, f, ft);
         if (feat) {
 #pragma unroll
             for (int k = 0; k < kNFeat; ++k) feat[i * kNFeat + k] = ft[k];
@@ -788,14 +764,14 @@ __global__ void k_event_offsets(const int64_t *md_mod_off, const int64_t *ls_off
     int64_t md0 = md_mod_off[(int64_t)e * n_mod];
     if (md0 > nmd) md0 = nmd;
     int64_t ls0 = ls_off[md0];
-    // T3 are sorted by middle MD, T5 by their shared MD: first with MD >= md0
+    // T3 and T5 are sorted by their inner MD: first one with inner MD >= md0
     int64_t lo = 0, hi = nt3;
-    while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (t3_mds[mid].y < md0) lo = mid + 1; else hi = mid; }
+    while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (t3_mds[mid].x < md0) lo = mid + 1; else hi = mid; }
     int64_t t30 = lo;
     lo = 0; hi = nt5;
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
-        if (t3_mds[t5_t3[mid].x].z < md0) lo = mid + 1; else hi = mid;
+        if (t3_mds[t5_t3[mid].x].x < md0) lo = mid + 1; else hi = mid;
     }
     out[0 * (n_ev + 1) + e] = md0;
     out[1 * (n_ev + 1) + e] = e == n_ev ? nls : ls0;
@@ -813,17 +789,9 @@ struct LsInKey {
     const int2 *ls;
     __device__ int operator()(int64_t i) const { return ls[i].x; }
 };
-struct LsOutKey {
-    const int2 *ls;
-    __device__ int operator()(int64_t i) const { return ls[i].y; }
-};
 struct T3InKey {
     const int4 *t;
     __device__ int operator()(int64_t i) const { return t[i].x; }
-};
-struct T3OutKey {
-    const int4 *t;
-    __device__ int operator()(int64_t i) const { return t[i].z; }
 };
 
 hipError_t set_single_event(int64_t *ev_off, int64_t n, hipStream_t st) {
@@ -866,28 +834,29 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     run_stage(ls, nullptr, ngm, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st, ev, 3);
     hipLaunchKernelGGL(k_fill_offsets<LsInKey>, dim3(grid_for(w.cap_ls)), dim3(kBlock), 0, st, LsInKey{o.ls_md},
                        cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w.ls_off);
-    bucket_sort(LsOutKey{o.ls_md}, cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w, w.lsT_off,
-                w.lsT_idx, st);
 
-    // a4: triplets, anchored on the shared (middle) MD
-    T3Stage t3{o.ls_md, w.ls_off, w.lsT_off, w.lsT_idx, w.md_a, w.md_o, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
-    run_stage(t3, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st, ev, 4);
-    bucket_sort(T3InKey{w.t3_mds}, cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w, w.t3i_off,
-                w.t3i_idx, st);
-    bucket_sort(T3OutKey{w.t3_mds}, cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w, w.t3o_off,
-                w.t3o_idx, st);
+    // a4: triplets, anchored on the inner LS
+    T3Stage t3{o.ls_md, w.ls_off, w.md_a, w.md_o, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
+    run_stage(t3, cnt + LST_COUNT_LS, w.cap_ls, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st, ev, 4);
+    hipLaunchKernelGGL(k_fill_offsets<T3InKey>, dim3(grid_for(w.cap_t3)), dim3(kBlock), 0, st, T3InKey{w.t3_mds},
+                       cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w.t3i_off);
 
-    // a5: quintuplets, anchored on the shared MD; FP64 fits
+    // a5: quintuplets, anchored on the inner T3: FP32 beam-line cuts, then the
+    // FP64 fits on the dense list of pre-candidates
     const bool score_cut = a.mode == 0 && a.score_min == a.score_min;
-    T5Stage<false> t5{w.t3_mds, w.t3o_off, w.t3i_off, w.t3o_idx, w.t3i_idx, w.md_a, a.g.mod, a.p, a.m, n_mod,
-                      a.mode, a.score_min, o.t5_t3, o.t5_chi2_rphi, o.t5_chi2_rz};
+    T5PreStage t5p{w.t3_mds, w.t3i_off, w.md_a, a.g.mod, a.p, n_mod, w.t5_pre};
+    mark(ev, 10, st);
+    run_stage(t5p, cnt + LST_COUNT_T3, w.cap_t3, w, cnt + LST_COUNT_T5PRE, w.cap_t5pre, cnt, st, nullptr, 0);
+    T5FitStage<false> t5{w.t5_pre, w.t3_mds, w.md_a, a.g.mod, a.p, a.m, n_mod, a.mode, a.score_min, o.t5_t3,
+                         o.t5_chi2_rphi, o.t5_chi2_rz};
     if (score_cut) {
-        T5Stage<true> t5c{w.t3_mds, w.t3o_off, w.t3i_off, w.t3o_idx, w.t3i_idx, w.md_a, a.g.mod, a.p, a.m, n_mod,
-                          a.mode, a.score_min, o.t5_t3, o.t5_chi2_rphi, o.t5_chi2_rz};
-        run_stage(t5c, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, ev, 5);
+        T5FitStage<true> t5c{w.t5_pre, w.t3_mds, w.md_a, a.g.mod, a.p, a.m, n_mod, a.mode, a.score_min, o.t5_t3,
+                             o.t5_chi2_rphi, o.t5_chi2_rz};
+        run_stage(t5c, cnt + LST_COUNT_T5PRE, w.cap_t5pre, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, nullptr, 0);
     } else {
-        run_stage(t5, cnt + LST_COUNT_MD, w.cap_md, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, ev, 5);
+        run_stage(t5, cnt + LST_COUNT_T5PRE, w.cap_t5pre, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, nullptr, 0);
     }
+    mark(ev, 11, st);
 
     // a6: features and T5-DNN scores (BF16 MFMA runs over the feature rows;
     // a score cut forces the FP32 path, which the T5 stage itself applied)
