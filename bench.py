@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--precision", choices=("bf16", "f32"), default="bf16")
     ap.add_argument("--mode", choices=("dnn", "pre_dnn"), default="dnn")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help='fixed launch shapes as JSON {"bin_split", "tile_per": [5], "eval_blocks"} (no autotuning)')
     ap.add_argument("--plain-events", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
@@ -125,10 +128,19 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     run = lambda: b.launch(dx, dy, dz, ds, event_offsets=doff, mode=mode, precision=prec)
     graph = None
+    tuned, tune_table = B.lst_get_tuning(b.ctx), []
     with torch.cuda.stream(stream):
         for _ in range(max(1, a.warmup)):
             run()
         stream.synchronize()
+        if a.tuning:
+            B.lst_set_tuning(b.ctx, json.loads(a.tuning))
+            tuned = B.lst_get_tuning(b.ctx)
+        elif not a.no_autotune:
+            # untimed: pick launch shapes for this workload on this GPU
+            from paper_2403_13166_amd.autotune import autotune
+            tuned, tune_table = autotune(b, run, stream.synchronize, reps=5,
+                                         log=lambda m: print(m, file=sys.stderr, flush=True))
         if not a.no_graph:
             graph = torch.cuda.CUDAGraph()
             with torch.cuda.graph(graph, stream=stream, capture_error_mode="relaxed"):
@@ -239,6 +251,7 @@ def main():
         "objects_per_event": {"md": per_ev[0], "ls": per_ev[1], "t3": per_ev[2], "t5": per_ev[3]},
         "max_candidates_per_stage": int(final[5]),
         "input_generation_s": t_gen, "stage_timing": timing_src,
+        "tuning": tuned, "autotune": tune_table,
     }
     print(json.dumps(out), flush=True)
     b.close()

@@ -168,6 +168,28 @@ lst_status lst_score(lst_ctx *ctx, const void *X_dev, int32_t x_dtype, int64_t n
 lst_status lst_set_timing(lst_ctx *ctx, int32_t enable);
 lst_status lst_stage_times(lst_ctx *ctx, float *ms, int32_t n);
 
+/* Launch shapes of the build kernels. They never change results: every stage
+ * writes its objects in candidate order whatever the tiling, so a tuning only
+ * changes speed (the autotuner in the Python package times them).
+ *   bin_split    blocks per event in hit binning, each histogramming one range
+ *                of sensor ids in LDS (1..64; raised at launch until one
+ *                range's histogram fits in 64 KiB of LDS);
+ *   tile_per[s]  candidates per thread of a 256-thread compaction tile, for
+ *                stage s = 0 MD {2,4,8}, 1 LS {2,4,8}, 2 T3 {1,2,4},
+ *                3 T5 FP32 pre-cuts {1,2,4}, 4 T5 FP64 fits {1,2};
+ *   eval_blocks  persistent blocks of the compaction kernels (256..8192).
+ * Defaults: {4, {4, 4, 2, 2, 1}, 4096}. lst_set_tuning(ctx, NULL) restores
+ * them; an unsupported value gives LST_E_INVAL and leaves the tuning as it
+ * was. The tuning in force when a build is enqueued (or captured) is used. */
+typedef struct {
+    int32_t bin_split;
+    int32_t tile_per[5];
+    int32_t eval_blocks;
+} lst_tuning;
+
+lst_status lst_get_tuning(const lst_ctx *ctx, lst_tuning *out);
+lst_status lst_set_tuning(lst_ctx *ctx, const lst_tuning *tuning);
+
 const char *lst_status_string(lst_status s);
 const char *lst_last_error(const lst_ctx *ctx);
 

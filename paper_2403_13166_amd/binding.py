@@ -33,7 +33,7 @@ N_FEATURES = 42
 
 EXPORTED = ("lst_create", "lst_destroy", "lst_load_geometry", "lst_load_model", "lst_workspace_size",
             "lst_build_objects", "lst_build_objects_batched", "lst_score", "lst_status_string",
-            "lst_last_error", "lst_set_timing", "lst_stage_times")
+            "lst_last_error", "lst_set_timing", "lst_stage_times", "lst_get_tuning", "lst_set_tuning")
 
 
 class LstHits(C.Structure):
@@ -56,6 +56,22 @@ class LstObjects(C.Structure):
 class LstOptions(C.Structure):
     _fields_ = [("mode", C.c_int32), ("precision", C.c_int32), ("score_min", C.c_float),
                 ("flags", C.c_int32)]
+
+
+class LstTuning(C.Structure):
+    _fields_ = [("bin_split", C.c_int32), ("tile_per", C.c_int32 * 5), ("eval_blocks", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"bin_split": self.bin_split, "tile_per": list(self.tile_per), "eval_blocks": self.eval_blocks}
+
+    @staticmethod
+    def from_dict(d: dict) -> "LstTuning":
+        t = LstTuning()
+        t.bin_split = int(d["bin_split"])
+        for i, v in enumerate(d["tile_per"]):
+            t.tile_per[i] = int(v)
+        t.eval_blocks = int(d["eval_blocks"])
+        return t
 
 
 class LstError(RuntimeError):
@@ -99,6 +115,10 @@ def lib():
         L.lst_set_timing.restype = i32
         L.lst_stage_times.argtypes = [vp, vp, i32]
         L.lst_stage_times.restype = i32
+        L.lst_get_tuning.argtypes = [vp, C.POINTER(LstTuning)]
+        L.lst_get_tuning.restype = i32
+        L.lst_set_tuning.argtypes = [vp, C.POINTER(LstTuning)]
+        L.lst_set_tuning.restype = i32
         L.lst_status_string.argtypes = [i32]
         L.lst_status_string.restype = C.c_char_p
         L.lst_last_error.argtypes = [vp]
@@ -174,6 +194,25 @@ def lst_stage_times(ctx) -> dict:
     buf = (C.c_float * len(STAGE_WINDOWS))()
     _check(ctx, lib().lst_stage_times(ctx, buf, len(STAGE_WINDOWS)), "lst_stage_times")
     return dict(zip(STAGE_WINDOWS, list(buf)))
+
+
+# tile sizes each stage is compiled for (candidates per thread): MD, LS, T3, T5 pre, T5 fit
+TILE_CHOICES = ((2, 4, 8), (2, 4, 8), (1, 2, 4), (1, 2, 4), (1, 2))
+
+
+def lst_get_tuning(ctx) -> dict:
+    t = LstTuning()
+    _check(ctx, lib().lst_get_tuning(ctx, C.byref(t)), "lst_get_tuning")
+    return t.as_dict()
+
+
+def lst_set_tuning(ctx, tuning: dict | None) -> None:
+    """Set launch shapes ({"bin_split", "tile_per": [5], "eval_blocks"}); None restores the defaults."""
+    if tuning is None:
+        _check(ctx, lib().lst_set_tuning(ctx, None), "lst_set_tuning")
+    else:
+        t = LstTuning.from_dict(tuning)
+        _check(ctx, lib().lst_set_tuning(ctx, C.byref(t)), "lst_set_tuning")
 
 
 def lst_status_string(status: int) -> str:

@@ -30,6 +30,8 @@ struct lst_ctx {
     // stage timing
     bool timing = false, events_made = false;
     hipEvent_t tev[kTimingEvents];
+    // launch shapes
+    Tuning tune = kDefaultTuning;
 };
 
 static lst_status fail(lst_ctx *c, lst_status s, const char *fmt, ...) {
@@ -235,7 +237,6 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     Work x{};
     x.cap_hits = k->hits; x.cap_ev = ev; x.cap_md = md; x.cap_ls = k->ls; x.cap_t3 = k->t3;
     x.cap_t5 = k->t5; x.cap_cand = k->cand; x.max_tiles = max_tiles; x.n_anchor_cap = anchors;
-    x.bin_cnt = (int32_t *)take(4 * ev * nsens);
     x.bin_off = (int64_t *)take(8 * (ev * nsens + 1));
     x.bin_hit = (float4 *)take(16 * (k->hits > 0 ? k->hits : 1));
     x.cand_off = (int64_t *)take(8 * (anchors + 1));
@@ -319,6 +320,7 @@ static lst_status build_common(lst_ctx *c, const lst_hits *h, const int64_t *ev_
     a.mode = opt->mode; a.precision = opt->precision; a.score_min = opt->score_min;
     a.ev_obj_off = ev_obj_off;
     a.timing = c->timing ? c->tev : nullptr;
+    a.tune = c->tune;
     Outputs o{};
     o.md_hits = (int2 *)out->md_hits; o.ls_md = (int2 *)out->ls_md; o.t3_ls = (int2 *)out->t3_ls;
     o.t5_t3 = (int2 *)out->t5_t3; o.t5_score = out->t5_score; o.t5_chi2_rphi = out->t5_chi2_rphi;
@@ -366,6 +368,29 @@ lst_status lst_stage_times(lst_ctx *c, float *ms, int32_t n) {
     if (!c->events_made) return fail(c, LST_E_STATE, "timing was never enabled");
     for (int i = 0; i < n && i < kTimingWindows; ++i)
         HIP_TRY(c, hipEventElapsedTime(&ms[i], c->tev[2 * i], c->tev[2 * i + 1]));
+    return LST_OK;
+}
+
+lst_status lst_get_tuning(const lst_ctx *c, lst_tuning *t) {
+    if (!c || !t) return LST_E_INVAL;
+    t->bin_split = c->tune.bin_split;
+    for (int i = 0; i < kStages; ++i) t->tile_per[i] = c->tune.per[i];
+    t->eval_blocks = c->tune.eval_blocks;
+    return LST_OK;
+}
+
+lst_status lst_set_tuning(lst_ctx *c, const lst_tuning *t) {
+    if (!c) return LST_E_INVAL;
+    Tuning n = kDefaultTuning;
+    if (t) {
+        n.bin_split = t->bin_split;
+        for (int i = 0; i < kStages; ++i) n.per[i] = t->tile_per[i];
+        n.eval_blocks = t->eval_blocks;
+    }
+    if (!tuning_valid(n))
+        return fail(c, LST_E_INVAL, "unsupported tuning (bin_split %d, tiles %d %d %d %d %d, eval_blocks %d)",
+                    n.bin_split, n.per[0], n.per[1], n.per[2], n.per[3], n.per[4], n.eval_blocks);
+    c->tune = n;
     return LST_OK;
 }
 

@@ -15,13 +15,35 @@ constexpr int kScanBlocks = 1024;
 constexpr int kEvalBlocks = 4096;     // persistent compaction blocks (256 CUs x 16)
 constexpr int kMaxStride = 8192;      // grid cap of grid-stride kernels
 constexpr int kMaxRecBytes = 32;      // largest per-candidate record a stage compacts
+constexpr int kBinLdsMax = 65536;     // LDS bytes of one binning block's histogram, at most
+
+// Launch shapes (never change results: outputs are in candidate order for any
+// tiling). Stage order: MD, LS, T3, T5 pre-cuts, T5 fit.
+constexpr int kStages = 5;
+// candidates per thread in a 256-thread tile that each stage is compiled for
+// (bit v set = value v allowed; values are powers of two)
+constexpr int kPerMask[kStages] = {2 | 4 | 8, 2 | 4 | 8, 1 | 2 | 4, 1 | 2 | 4, 1 | 2};
+struct Tuning {
+    int32_t bin_split;                // sensor ranges (blocks) per event in hit binning, 1..64
+    int32_t per[kStages];
+    int32_t eval_blocks;              // persistent blocks of the compaction kernels
+};
+constexpr Tuning kDefaultTuning = {4, {4, 4, 2, 2, 1}, kEvalBlocks};
+inline bool tuning_valid(const Tuning &t) {
+    if (t.bin_split < 1 || t.bin_split > 64) return false;
+    if (t.eval_blocks < 256 || t.eval_blocks > kMaxStride) return false;
+    for (int i = 0; i < kStages; ++i) {
+        const int v = t.per[i];
+        if (v < 1 || v > 8 || (v & (v - 1)) || !(kPerMask[i] & v)) return false;
+    }
+    return true;
+}
 
 struct Work {
     // capacities
     int64_t cap_hits, cap_ev, cap_md, cap_ls, cap_t3, cap_t5, cap_cand, max_tiles;
     int64_t n_anchor_cap;             // largest anchor count of any stage + 1
     // hits binned by (event, sensor)
-    int32_t *bin_cnt;                 // [cap_ev * n_sens]
     int64_t *bin_off;                 // [cap_ev * n_sens + 1]
     float4 *bin_hit;                  // [cap_hits] x, y, z, input index (bits)
     // per-stage scratch
@@ -69,6 +91,7 @@ struct RunArgs {
     float score_min;
     int64_t *ev_obj_off;              // device [4][n_ev + 1] or null
     hipEvent_t *timing;               // null, or kTimingEvents events recorded around the stages
+    Tuning tune;
 };
 
 // Timing windows (pairs of events): 0 whole build, 1 binning, 2 MD, 3 LS,

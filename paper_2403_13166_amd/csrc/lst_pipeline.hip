@@ -3,7 +3,8 @@
 // compaction kernel over its candidate pairs.
 //
 // Every stage has the same shape:
-//   * anchors (a module for MD and LS, an MD for T3 and T5) own a contiguous
+//   * anchors (a module for MD and LS, the inner LS for T3, the inner T3 for
+//     T5) own a contiguous
 //     range of candidate pairs (left list x right list); a device-wide
 //     exclusive scan of the per-anchor counts gives the ranges and, for every
 //     tile of candidates, the anchor its first candidate belongs to;
@@ -11,7 +12,7 @@
 //     tile's window of anchor offsets and per-anchor list bases in LDS (for
 //     LS also the module-map tables of those modules), so decoding a
 //     candidate into its (left, right) pair is LDS work; each thread then
-//     applies the cuts to S::kPer candidates and the block compacts the
+//     applies the cuts to kPer candidates and the block compacts the
 //     survivors with wavefront ballots into the tile's scratch slot. No block
 //     ever waits for another: a scan of the tile counts and a copy kernel
 //     place the survivors. Output is in candidate order (deterministic)
@@ -42,10 +43,6 @@ static inline int grid_for(int64_t n) {
     if (g < 1) g = 1;
     if (g > kMaxStride) g = kMaxStride;
     return (int)g;
-}
-
-__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
-    for (int64_t i = grid_tid(); i < n; i += grid_stride()) p[i] = v;
 }
 
 __global__ void k_fill_i32_dev(int32_t *p, const int64_t *n_dev, int64_t cap, int32_t v) {
@@ -184,20 +181,19 @@ struct TileLds {
 };
 
 // Compaction of one stage in three steps, none of which waits on another
-// block: (1) the eval kernel takes tiles of kBlock * S::kPer candidates
+// block: (1) the eval kernel takes tiles of kBlock * kPer candidates
 // (grid-stride), stages the tile's anchor window in LDS, applies the cuts and
 // compacts each tile's survivors, in candidate order, into that tile's slot of
 // a scratch buffer, with the tile's count; (2) an exclusive scan of the tile
 // counts gives every tile its output offset; (3) a copy kernel moves each
 // tile's survivors to their final position. Output order = candidate order.
-template <class S>
+template <class S, int kPer>
 __global__ __launch_bounds__(kBlock) void k_stage_eval(S st, const int64_t *cand_off,
                                                        const int64_t *n_dev, int64_t n_cap,
                                                        const int32_t *tile_anchor, int64_t max_tiles,
                                                        int32_t *tile_cnt, typename S::Rec *scratch,
                                                        int64_t *ntiles_out, int64_t *counts, int64_t cap_cand) {
     constexpr int kWaves = kBlock / 64;
-    constexpr int kPer = S::kPer;
     constexpr int kTileC = kBlock * kPer;
     constexpr int kSeg = kPer * kWaves;     // output segments, in candidate order
     __shared__ TileLds<S::kEnt> L;
@@ -284,12 +280,12 @@ __global__ __launch_bounds__(kBlock) void k_stage_eval(S st, const int64_t *cand
     }
 }
 
-template <class S>
+template <class S, int kPer>
 __global__ __launch_bounds__(kBlock) void k_stage_copy(S st, const typename S::Rec *scratch,
                                                        const int32_t *tile_cnt, const int64_t *tile_pre,
                                                        const int64_t *ntiles_dev, int64_t *out_count,
                                                        int64_t cap_out) {
-    constexpr int kTileC = kBlock * S::kPer;
+    constexpr int kTileC = kBlock * kPer;
     const int64_t ntiles = *ntiles_dev;
     if (blockIdx.x == 0 && threadIdx.x == 0) *out_count = tile_pre[ntiles];
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -313,67 +309,126 @@ static inline void mark(hipEvent_t *ev, int k, hipStream_t st) {
     if (ev) (void)hipEventRecord(ev[k], st);
 }
 
-template <class S>
-static void run_stage(const S &s, const int64_t *n_dev, int64_t n_cap, const Work &w, int64_t *out_count,
-                      int64_t cap_out, int64_t *counts, hipStream_t st, hipEvent_t *ev, int win) {
+template <class S, int kPer>
+static void run_stage_p(const S &s, const int64_t *n_dev, int64_t n_cap, const Work &w, int64_t *out_count,
+                        int64_t cap_out, int64_t *counts, hipStream_t st, hipEvent_t *ev, int win,
+                        int eval_blocks) {
     static_assert(sizeof(typename S::Rec) <= kMaxRecBytes, "scratch record too large");
-    const int tile = kBlock * S::kPer;
+    static_assert((kPerMask[S::kStage] & kPer) != 0, "tile size not offered for this stage");
+    const int tile = kBlock * kPer;
     scan(StageCount<S>{s}, n_dev, n_cap, w, w.cand_off, w.tile_anchor, st, tile);
-    int nb = (int)(w.max_tiles < kEvalBlocks ? w.max_tiles : kEvalBlocks);
+    int nb = (int)(w.max_tiles < eval_blocks ? w.max_tiles : eval_blocks);
     if (nb < 1) nb = 1;
     typename S::Rec *scratch = (typename S::Rec *)w.rec_scratch;
     mark(ev, 2 * win, st);
-    hipLaunchKernelGGL(k_stage_eval<S>, dim3(nb), dim3(kBlock), 0, st, s, w.cand_off, n_dev, n_cap,
+    hipLaunchKernelGGL((k_stage_eval<S, kPer>), dim3(nb), dim3(kBlock), 0, st, s, w.cand_off, n_dev, n_cap,
                        w.tile_anchor, w.max_tiles, w.tile_cnt, scratch, w.ntiles, counts, w.cap_cand);
     mark(ev, 2 * win + 1, st);
     scan(CntF{w.tile_cnt}, w.ntiles, w.max_tiles, w, w.tile_pre, nullptr, st);
-    hipLaunchKernelGGL(k_stage_copy<S>, dim3(nb), dim3(kBlock), 0, st, s, scratch, w.tile_cnt, w.tile_pre,
+    hipLaunchKernelGGL((k_stage_copy<S, kPer>), dim3(nb), dim3(kBlock), 0, st, s, scratch, w.tile_cnt, w.tile_pre,
                        w.ntiles, out_count, cap_out);
 }
 
+// Run a stage with the tile size chosen at run time among those compiled for
+// it (the host validated `per` against kPerMask).
+template <class S>
+static void run_stage(const S &s, const int64_t *n_dev, int64_t n_cap, const Work &w, int64_t *out_count,
+                      int64_t cap_out, int64_t *counts, hipStream_t st, hipEvent_t *ev, int win,
+                      const Tuning &tn) {
+    constexpr int m = kPerMask[S::kStage];
+    const int per = tn.per[S::kStage], nb = tn.eval_blocks;
+    if constexpr ((m & 1) != 0) if (per == 1) return run_stage_p<S, 1>(s, n_dev, n_cap, w, out_count, cap_out, counts, st, ev, win, nb);
+    if constexpr ((m & 2) != 0) if (per == 2) return run_stage_p<S, 2>(s, n_dev, n_cap, w, out_count, cap_out, counts, st, ev, win, nb);
+    if constexpr ((m & 4) != 0) if (per == 4) return run_stage_p<S, 4>(s, n_dev, n_cap, w, out_count, cap_out, counts, st, ev, win, nb);
+    if constexpr ((m & 8) != 0) if (per == 8) return run_stage_p<S, 8>(s, n_dev, n_cap, w, out_count, cap_out, counts, st, ev, win, nb);
+}
+
 // ------------------------------------------------------------- binning
+// Counting sort of the hits by (event, sensor) without device-wide atomics:
+// block (e, r) owns sensor range r of event e. It histograms its range with
+// LDS atomics while counting the event's hits on lower sensors (its base),
+// scans the histogram in LDS, writes the bin offsets, scatters its hits with
+// LDS cursors and finally orders each of its (small) bins by input index, so
+// the binned layout is deterministic. Hits with an out-of-range sensor id set
+// error bit 0 and are dropped.
 
-__device__ __forceinline__ int event_of(const int64_t *ev_off, int n_ev, int64_t h) {
-    int lo = 0, hi = n_ev;   // largest e with ev_off[e] <= h
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (ev_off[mid] <= h) lo = mid; else hi = mid;
+constexpr int kBinThreads = 1024;
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_event(const float *x, const float *y, const float *z,
+                                                           const int32_t *sensor, const int64_t *ev_off,
+                                                           int n_ev, int n_sens, int split, int64_t *bin_off,
+                                                           float4 *bin_hit, int64_t *counts) {
+    extern __shared__ int32_t s_hist[];          // [range + 1]
+    __shared__ int64_t s_red[kBinThreads / 64];
+    __shared__ int64_t s_base;
+    const int e = blockIdx.x / split, r = blockIdx.x - e * split;
+    const int range = (n_sens + split - 1) / split;
+    // ranges past the last sensor are empty (nb = 0), never negative
+    const int lo = r * range < n_sens ? r * range : n_sens;
+    const int hi = lo + range < n_sens ? lo + range : n_sens;
+    const int nb = hi - lo;
+    const int64_t h0 = ev_off[e], h1 = ev_off[e + 1];
+    for (int i = threadIdx.x; i <= nb; i += kBinThreads) s_hist[i] = 0;
+    __syncthreads();
+    int64_t below = 0;
+    bool bad = false;
+    for (int64_t h = h0 + threadIdx.x; h < h1; h += kBinThreads) {
+        const int sv = sensor[h];
+        if (sv < 0 || sv >= n_sens) { bad = true; continue; }
+        if (sv < lo) ++below;
+        else if (sv < hi) atomicAdd(&s_hist[sv - lo], 1);
     }
-    return lo;
-}
-
-__global__ void k_bin_count(const int32_t *sensor, int64_t n, const int64_t *ev_off, int n_ev, int n_sens,
-                            int32_t *cnt, int64_t *counts) {
-    for (int64_t h = grid_tid(); h < n; h += grid_stride()) {
-        int s = sensor[h];
-        if (s < 0 || s >= n_sens) { atomicOr((unsigned long long *)&counts[LST_COUNT_ERR], 1ull); continue; }
-        int e = event_of(ev_off, n_ev, h);
-        atomicAdd(&cnt[(int64_t)e * n_sens + s], 1);
+    if (bad && r == 0) atomicOr((unsigned long long *)&counts[LST_COUNT_ERR], 1ull);
+    // block reduction of `below`
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) below += __shfl_xor(below, d, 64);
+    if (lane == 0) s_red[wv] = below;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t b = 0;
+        for (int k = 0; k < kBinThreads / 64; ++k) b += s_red[k];
+        s_base = h0 + b;
     }
-}
-
-__global__ void k_bin_scatter(const float *x, const float *y, const float *z, const int32_t *sensor,
-                              int64_t n, const int64_t *ev_off, int n_ev, int n_sens,
-                              const int64_t *off, int32_t *cnt, float4 *out) {
-    for (int64_t h = grid_tid(); h < n; h += grid_stride()) {
-        int s = sensor[h];
-        if (s < 0 || s >= n_sens) continue;
-        int64_t key = (int64_t)event_of(ev_off, n_ev, h) * n_sens + s;
-        int64_t pos = off[key] + (int64_t)atomicSub(&cnt[key], 1) - 1;
-        out[pos] = make_float4(x[h], y[h], z[h], __int_as_float((int)h));
+    __syncthreads();
+    // exclusive scan of the histogram: thread t owns a contiguous run
+    const int per = (nb + kBinThreads - 1) / kBinThreads;
+    const int a0 = threadIdx.x * per, a1 = a0 + per < nb ? a0 + per : nb;
+    int64_t run = 0;
+    for (int i = a0; i < a1; ++i) run += s_hist[i];
+    int64_t inc = wave_incl_scan(run);
+    if (lane == 63) s_red[wv] = inc;
+    __syncthreads();
+    int64_t woff = 0, tot = 0;
+    for (int k = 0; k < kBinThreads / 64; ++k) { if (k < wv) woff += s_red[k]; tot += s_red[k]; }
+    int64_t acc = woff + inc - run;
+    const int64_t base = s_base;
+    __syncthreads();
+    for (int i = a0; i < a1; ++i) {
+        const int c = s_hist[i];
+        s_hist[i] = (int32_t)acc;                 // exclusive offset, then cursor
+        bin_off[(int64_t)e * n_sens + lo + i] = base + acc;
+        acc += c;
     }
-}
-
-// order each bin by input index so that every later stage is deterministic
-__global__ void k_bin_sort(const int64_t *off, int64_t nbins, float4 *hit) {
-    for (int64_t b = grid_tid(); b < nbins; b += grid_stride()) {
-        int64_t s = off[b], e = off[b + 1];
-        for (int64_t i = s + 1; i < e; ++i) {
-            float4 v = hit[i];
-            int key = __float_as_int(v.w);
-            int64_t j = i - 1;
-            while (j >= s && __float_as_int(hit[j].w) > key) { hit[j + 1] = hit[j]; --j; }
-            hit[j + 1] = v;
+    if (e == n_ev - 1 && r == split - 1 && threadIdx.x == 0) bin_off[(int64_t)n_ev * n_sens] = base + tot;
+    if (threadIdx.x == 0) s_hist[nb] = (int32_t)tot;
+    __syncthreads();
+    for (int64_t h = h0 + threadIdx.x; h < h1; h += kBinThreads) {
+        const int sv = sensor[h];
+        if (sv < lo || sv >= hi) continue;
+        const int64_t pos = base + atomicAdd(&s_hist[sv - lo], 1);
+        bin_hit[pos] = make_float4(x[h], y[h], z[h], __int_as_float((int)h));
+    }
+    __syncthreads();
+    // each cursor now holds the end of its bin (the next bin's start)
+    for (int i = threadIdx.x; i < nb; i += kBinThreads) {
+        const int64_t bs = base + (i == 0 ? 0 : s_hist[i - 1]), be = base + s_hist[i];
+        for (int64_t k = bs + 1; k < be; ++k) {
+            const float4 v = bin_hit[k];
+            const int key = __float_as_int(v.w);
+            int64_t j = k - 1;
+            while (j >= bs && __float_as_int(bin_hit[j].w) > key) { bin_hit[j + 1] = bin_hit[j]; --j; }
+            bin_hit[j + 1] = v;
         }
     }
 }
@@ -392,7 +447,7 @@ struct MDStage {
     float4 *md_a;
     float2 *md_o;
     static constexpr int kEnt = 0;
-    static constexpr int kPer = 4;
+    static constexpr int kStage = 0;
     struct Rec { float4 a; float2 o; int hl, hu; };
 
     __device__ int64_t count(int64_t gm) const {
@@ -475,7 +530,7 @@ struct LSStage {
     int32_t n_mod, n_map;
     int2 *ls_md;
     static constexpr int kEnt = 1536;
-    static constexpr int kPer = 4;
+    static constexpr int kStage = 1;
     struct Rec { int a, b; };
 
     __device__ int64_t count(int64_t gm) const {
@@ -582,7 +637,7 @@ struct T3Stage {
     int2 *t3_ls;
     int4 *t3_mds;
     static constexpr int kEnt = 0;
-    static constexpr int kPer = 2;
+    static constexpr int kStage = 2;
     struct Rec { int li, lo, A, B, C; };
 
     __device__ int64_t count(int64_t l1) const {
@@ -636,7 +691,7 @@ struct T5PreStage {
     int32_t n_mod;
     int2 *pre;
     static constexpr int kEnt = 0;
-    static constexpr int kPer = 2;
+    static constexpr int kStage = 3;
     struct Rec { int u, v; };
 
     __device__ int64_t count(int64_t u) const {
@@ -695,7 +750,7 @@ struct T5FitStage {
     int2 *t5_t3;
     float *chi2_rphi, *chi2_rz;
     static constexpr int kEnt = 0;
-    static constexpr int kPer = 1;
+    static constexpr int kStage = 4;
     struct Rec { int u, v; float cr, cz; };
 
     __device__ int64_t count(int64_t) const { return 1; }
@@ -801,7 +856,6 @@ hipError_t set_single_event(int64_t *ev_off, int64_t n, hipStream_t st) {
 
 hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipStream_t st) {
     const int32_t n_mod = a.g.n_mod, n_sens = a.g.n_sens, n_map = a.g.n_map;
-    const int64_t nbins = (int64_t)a.n_ev * n_sens;
     const int64_t ngm = (int64_t)a.n_ev * n_mod;
     int64_t *cnt = o.counts;
 
@@ -810,18 +864,19 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, cnt, (int64_t)LST_COUNTS_LEN, (int64_t)0);
     // a1: bin hits by (event, sensor)
     mark(ev, 2, st);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nbins)), dim3(kBlock), 0, st, w.bin_cnt, nbins, 0);
-    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(a.n_hits)), dim3(kBlock), 0, st, a.sensor, a.n_hits, a.ev_off,
-                       a.n_ev, n_sens, w.bin_cnt, cnt);
-    scan(CntF{w.bin_cnt}, nullptr, nbins, w, w.bin_off, nullptr, st);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(a.n_hits)), dim3(kBlock), 0, st, a.x, a.y, a.z, a.sensor,
-                       a.n_hits, a.ev_off, a.n_ev, n_sens, w.bin_off, w.bin_cnt, w.bin_hit);
-    hipLaunchKernelGGL(k_bin_sort, dim3(grid_for(nbins)), dim3(kBlock), 0, st, w.bin_off, nbins, w.bin_hit);
+    {
+        // the requested split, raised until one range's histogram fits the LDS limit
+        int split = a.tune.bin_split;
+        while ((int64_t)((n_sens + split - 1) / split + 1) * 4 > kBinLdsMax) ++split;
+        const int range = (n_sens + split - 1) / split;
+        hipLaunchKernelGGL(k_bin_event, dim3(a.n_ev * split), dim3(kBinThreads), (size_t)(range + 1) * 4, st,
+                           a.x, a.y, a.z, a.sensor, a.ev_off, a.n_ev, n_sens, split, w.bin_off, w.bin_hit, cnt);
+    }
     mark(ev, 3, st);
 
     // a2: mini-doublets, anchored on (event, module)
     MDStage md{w.bin_off, w.bin_hit, a.g.mod, a.p, n_mod, n_sens, o.md_hits, w.md_a, w.md_o};
-    run_stage(md, nullptr, ngm, w, cnt + LST_COUNT_MD, w.cap_md, cnt, st, ev, 2);
+    run_stage(md, nullptr, ngm, w, cnt + LST_COUNT_MD, w.cap_md, cnt, st, ev, 2, a.tune);
     hipLaunchKernelGGL(k_fill_offsets<GmKey>, dim3(grid_for(w.cap_md)), dim3(kBlock), 0, st, GmKey{w.md_a},
                        cnt + LST_COUNT_MD, w.cap_md, nullptr, ngm, w.md_mod_off);
     hipLaunchKernelGGL(k_ls_prefix, dim3(grid_for(ngm)), dim3(kBlock), 0, st, a.g.map_off, a.g.map_tgt, n_mod,
@@ -831,13 +886,13 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     // the MDs of its mapped modules
     LSStage ls{w.md_a, w.md_o, w.md_mod_off, w.rsum, w.rpref, a.g.map_off, a.g.map_tgt, a.g.mod, a.p,
                n_mod, n_map, o.ls_md};
-    run_stage(ls, nullptr, ngm, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st, ev, 3);
+    run_stage(ls, nullptr, ngm, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st, ev, 3, a.tune);
     hipLaunchKernelGGL(k_fill_offsets<LsInKey>, dim3(grid_for(w.cap_ls)), dim3(kBlock), 0, st, LsInKey{o.ls_md},
                        cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w.ls_off);
 
     // a4: triplets, anchored on the inner LS
     T3Stage t3{o.ls_md, w.ls_off, w.md_a, w.md_o, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
-    run_stage(t3, cnt + LST_COUNT_LS, w.cap_ls, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st, ev, 4);
+    run_stage(t3, cnt + LST_COUNT_LS, w.cap_ls, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st, ev, 4, a.tune);
     hipLaunchKernelGGL(k_fill_offsets<T3InKey>, dim3(grid_for(w.cap_t3)), dim3(kBlock), 0, st, T3InKey{w.t3_mds},
                        cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w.t3i_off);
 
@@ -846,15 +901,15 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     const bool score_cut = a.mode == 0 && a.score_min == a.score_min;
     T5PreStage t5p{w.t3_mds, w.t3i_off, w.md_a, a.g.mod, a.p, n_mod, w.t5_pre};
     mark(ev, 10, st);
-    run_stage(t5p, cnt + LST_COUNT_T3, w.cap_t3, w, cnt + LST_COUNT_T5PRE, w.cap_t5pre, cnt, st, nullptr, 0);
+    run_stage(t5p, cnt + LST_COUNT_T3, w.cap_t3, w, cnt + LST_COUNT_T5PRE, w.cap_t5pre, cnt, st, nullptr, 0, a.tune);
     T5FitStage<false> t5{w.t5_pre, w.t3_mds, w.md_a, a.g.mod, a.p, a.m, n_mod, a.mode, a.score_min, o.t5_t3,
                          o.t5_chi2_rphi, o.t5_chi2_rz};
     if (score_cut) {
         T5FitStage<true> t5c{w.t5_pre, w.t3_mds, w.md_a, a.g.mod, a.p, a.m, n_mod, a.mode, a.score_min, o.t5_t3,
                              o.t5_chi2_rphi, o.t5_chi2_rz};
-        run_stage(t5c, cnt + LST_COUNT_T5PRE, w.cap_t5pre, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, nullptr, 0);
+        run_stage(t5c, cnt + LST_COUNT_T5PRE, w.cap_t5pre, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, nullptr, 0, a.tune);
     } else {
-        run_stage(t5, cnt + LST_COUNT_T5PRE, w.cap_t5pre, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, nullptr, 0);
+        run_stage(t5, cnt + LST_COUNT_T5PRE, w.cap_t5pre, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, nullptr, 0, a.tune);
     }
     mark(ev, 11, st);
 

@@ -227,3 +227,57 @@ def test_edge_cases(builder_f, geo_f):
     assert st == B.LST_E_CAPACITY
     out = builder_f.build(x, y, z, s, caps=small).to_host()
     assert np.array_equal(out.t5_t3, ref.t5_t3) and np.array_equal(out.md_hits, ref.md_hits)
+
+
+def test_tunings_change_nothing_but_speed(builder_f, geo_f):
+    from paper_2403_13166_amd import binding as B
+    ev = E.make_event(geo_f, E.PU200, (1, 1))
+    ref = run_gpu(builder_f, ev, precision=B.LST_PREC_BF16)
+    default = B.lst_get_tuning(builder_f.ctx)
+    variants = [
+        {"bin_split": 1, "tile_per": [2, 2, 1, 1, 1], "eval_blocks": 256},
+        {"bin_split": 32, "tile_per": [8, 8, 4, 4, 2], "eval_blocks": 8192},
+        {"bin_split": 8, "tile_per": [2, 8, 4, 1, 2], "eval_blocks": 1024},
+    ]
+    try:
+        for t in variants:
+            _say("tuning", t)
+            B.lst_set_tuning(builder_f.ctx, t)
+            assert B.lst_get_tuning(builder_f.ctx) == t
+            got = run_gpu(builder_f, ev, precision=B.LST_PREC_BF16)
+            for k in ("md_hits", "ls_md", "t3_ls", "t5_t3", "t5_score", "t5_chi2_rphi", "t5_chi2_rz"):
+                assert np.array_equal(getattr(got, k), getattr(ref, k)), (t, k)
+        for bad in ({"bin_split": 0, "tile_per": [4, 4, 2, 2, 1], "eval_blocks": 4096},
+                    {"bin_split": 4, "tile_per": [1, 4, 2, 2, 1], "eval_blocks": 4096},
+                    {"bin_split": 4, "tile_per": [4, 4, 2, 2, 4], "eval_blocks": 4096},
+                    {"bin_split": 4, "tile_per": [4, 3, 2, 2, 1], "eval_blocks": 4096},
+                    {"bin_split": 4, "tile_per": [4, 4, 2, 2, 1], "eval_blocks": 100}):
+            before = B.lst_get_tuning(builder_f.ctx)
+            with pytest.raises(B.LstError) as ei:
+                B.lst_set_tuning(builder_f.ctx, bad)
+            assert ei.value.status == B.LST_E_INVAL
+            assert B.lst_get_tuning(builder_f.ctx) == before
+    finally:
+        B.lst_set_tuning(builder_f.ctx, None)
+    assert B.lst_get_tuning(builder_f.ctx) == default
+
+
+def test_autotune_keeps_results(geo_f, mdl):
+    from paper_2403_13166_amd import binding as B
+    from paper_2403_13166_amd.autotune import autotune
+    from paper_2403_13166_amd.runtime import Builder
+    rng = E.event_rng(2, 5)
+    evs = [E.make_event(geo_f, E.batch_event_config(rng), (2, 5, i)) for i in range(3)]
+    x, y, z, s, off = E.concat_events(evs)
+    b = Builder(geo_f.to_blob(), mdl.to_blob(), 0)
+    T = lambda a: torch.from_numpy(a).to(b.device)
+    dx, dy, dz, ds, doff = T(x), T(y), T(z), T(s), T(off)
+    ref = b.build(dx, dy, dz, ds, event_offsets=doff).to_host()
+    run = lambda: b.launch(dx, dy, dz, ds, event_offsets=doff)
+    best, table = autotune(b, run, torch.cuda.synchronize, reps=1, log=_say)
+    assert len(table) == 7
+    B.lst_set_tuning(b.ctx, best)
+    got = b.build(dx, dy, dz, ds, event_offsets=doff).to_host()
+    for k in ("md_hits", "ls_md", "t3_ls", "t5_t3", "t5_score"):
+        assert np.array_equal(getattr(got, k), getattr(ref, k)), k
+    b.close()
