@@ -212,9 +212,11 @@ def main():
         pb.close()
 
     if a.copy_calibration_mb > 0:
-        src = torch.empty(a.copy_calibration_mb << 20, dtype=torch.uint8, device=dev)
+        # one plain elementwise kernel that reads and writes exactly this many
+        # bytes: the scale of the HBM byte counters
+        src = torch.ones((a.copy_calibration_mb << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
 
     # ---------------- roofline of the dominant kernel

@@ -168,6 +168,35 @@ lst_status lst_score(lst_ctx *ctx, const void *X_dev, int32_t x_dtype, int64_t n
 lst_status lst_set_timing(lst_ctx *ctx, int32_t enable);
 lst_status lst_stage_times(lst_ctx *ctx, float *ms, int32_t n);
 
+/* Edge classifier on a graph of LST objects (the GNN proposed in Sec. 4:
+ * nodes are lower-level objects, e.g. line segments, and edges the
+ * higher-level objects joining two of them, e.g. triplets). The paper gives no
+ * architecture; the library runs an interaction network: node encoder
+ * 7 -> 64 -> 64, edge init 128 -> 64, two message-passing steps (residual edge
+ * update 192 -> 64 -> 64 on [h_src, h_dst, e]; sum of the states of the edges
+ * entering each node; residual node update 128 -> 64 -> 64 on [h, m]), and an
+ * edge head 64 -> 32 -> 1 with a sigmoid; ReLU on every hidden layer. Dense
+ * layers use BF16 MFMA with FP32 accumulation; states are FP32.
+ * lst_load_gnn takes the "LSTE" blob v1 (host memory, copied): header
+ * {"LSTE", 1, 7, 64, 32, 2} then, per layer in the order enc1, enc2, einit,
+ * then per step edge_a, edge_b, node_a, node_b, then head1, head2, an FP32
+ * weight [out][in] followed by its bias [out]. LST_E_INVAL on any other shape. */
+lst_status lst_load_gnn(lst_ctx *ctx, const void *blob, size_t nbytes);
+
+/* Device workspace bytes for a graph of this size (256-byte aligned base). */
+lst_status lst_gnn_workspace_size(const lst_ctx *ctx, int64_t n_nodes, int64_t n_edges, size_t *bytes);
+
+/* Score every edge: x_dev [n_nodes][7] FP32 node features, src_dev / dst_dev
+ * int32 [n_edges] node ids with dst_dev sorted ascending (edges entering a
+ * node are contiguous), scores_dev FP32 [n_edges] receives the sigmoid
+ * outputs. All device pointers, caller-owned. Unless flags has LST_ASYNC the
+ * call synchronises and returns LST_E_INVAL if an id is out of range or dst
+ * is not sorted (scores are then unspecified; the kernels never access memory
+ * outside the arrays). */
+lst_status lst_gnn_score(lst_ctx *ctx, const float *x_dev, int64_t n_nodes, const int32_t *src_dev,
+                         const int32_t *dst_dev, int64_t n_edges, float *scores_dev, void *workspace,
+                         size_t ws_bytes, int32_t flags, void *stream);
+
 /* Launch shapes of the build kernels. They never change results: every stage
  * writes its objects in candidate order whatever the tiling, so a tuning only
  * changes speed (the autotuner in the Python package times them).

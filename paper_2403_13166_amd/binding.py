@@ -33,7 +33,8 @@ N_FEATURES = 42
 
 EXPORTED = ("lst_create", "lst_destroy", "lst_load_geometry", "lst_load_model", "lst_workspace_size",
             "lst_build_objects", "lst_build_objects_batched", "lst_score", "lst_status_string",
-            "lst_last_error", "lst_set_timing", "lst_stage_times", "lst_get_tuning", "lst_set_tuning")
+            "lst_last_error", "lst_set_timing", "lst_stage_times", "lst_get_tuning", "lst_set_tuning",
+            "lst_load_gnn", "lst_gnn_workspace_size", "lst_gnn_score")
 
 
 class LstHits(C.Structure):
@@ -115,6 +116,12 @@ def lib():
         L.lst_set_timing.restype = i32
         L.lst_stage_times.argtypes = [vp, vp, i32]
         L.lst_stage_times.restype = i32
+        L.lst_load_gnn.argtypes = [vp, C.c_char_p, C.c_size_t]
+        L.lst_load_gnn.restype = i32
+        L.lst_gnn_workspace_size.argtypes = [vp, i64, i64, C.POINTER(C.c_size_t)]
+        L.lst_gnn_workspace_size.restype = i32
+        L.lst_gnn_score.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, C.c_size_t, i32, vp]
+        L.lst_gnn_score.restype = i32
         L.lst_get_tuning.argtypes = [vp, C.POINTER(LstTuning)]
         L.lst_get_tuning.restype = i32
         L.lst_set_tuning.argtypes = [vp, C.POINTER(LstTuning)]
@@ -194,6 +201,25 @@ def lst_stage_times(ctx) -> dict:
     buf = (C.c_float * len(STAGE_WINDOWS))()
     _check(ctx, lib().lst_stage_times(ctx, buf, len(STAGE_WINDOWS)), "lst_stage_times")
     return dict(zip(STAGE_WINDOWS, list(buf)))
+
+
+def lst_load_gnn(ctx, blob: bytes) -> None:
+    _check(ctx, lib().lst_load_gnn(ctx, blob, len(blob)), "lst_load_gnn")
+
+
+def lst_gnn_workspace_size(ctx, n_nodes: int, n_edges: int) -> int:
+    n = C.c_size_t()
+    _check(ctx, lib().lst_gnn_workspace_size(ctx, int(n_nodes), int(n_edges), C.byref(n)), "lst_gnn_workspace_size")
+    return int(n.value)
+
+
+def lst_gnn_score(ctx, x_dev: int, n_nodes: int, src_dev: int, dst_dev: int, n_edges: int, scores_dev: int,
+                  ws: int, ws_bytes: int, flags: int, stream: int, check: bool = True) -> int:
+    st = lib().lst_gnn_score(ctx, x_dev, int(n_nodes), src_dev, dst_dev, int(n_edges), scores_dev, ws, ws_bytes,
+                             int(flags), stream)
+    if check:
+        _check(ctx, st, "lst_gnn_score")
+    return st
 
 
 # tile sizes each stage is compiled for (candidates per thread): MD, LS, T3, T5 pre, T5 fit

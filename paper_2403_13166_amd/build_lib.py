@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblst.so")
-SOURCES = ["lst_capi.hip", "lst_pipeline.hip", "lst_score.hip"]
+SOURCES = ["lst_capi.hip", "lst_pipeline.hip", "lst_score.hip", "lst_gnn.hip"]
 ARCH = os.environ.get("LST_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

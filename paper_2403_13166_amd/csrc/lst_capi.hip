@@ -32,6 +32,10 @@ struct lst_ctx {
     hipEvent_t tev[kTimingEvents];
     // launch shapes
     Tuning tune = kDefaultTuning;
+    // edge classifier
+    bool gnn_loaded = false;
+    void *d_gnn = nullptr;
+    GnnDev gnn{};
 };
 
 static lst_status fail(lst_ctx *c, lst_status s, const char *fmt, ...) {
@@ -93,6 +97,7 @@ void lst_destroy(lst_ctx *c) {
     (void)hipSetDevice(c->device);
     free_geom(c);
     if (c->d_model) (void)hipFree(c->d_model);
+    if (c->d_gnn) (void)hipFree(c->d_gnn);
     if (c->events_made)
         for (int i = 0; i < kTimingEvents; ++i) (void)hipEventDestroy(c->tev[i]);
     delete c;
@@ -368,6 +373,136 @@ lst_status lst_stage_times(lst_ctx *c, float *ms, int32_t n) {
     if (!c->events_made) return fail(c, LST_E_STATE, "timing was never enabled");
     for (int i = 0; i < n && i < kTimingWindows; ++i)
         HIP_TRY(c, hipEventElapsedTime(&ms[i], c->tev[2 * i], c->tev[2 * i + 1]));
+    return LST_OK;
+}
+
+// ------------------------------------------------------ edge classifier
+
+namespace {
+
+struct GLayer { int out, in; };
+// layer shapes in blob order (index = GnnLayer)
+constexpr GLayer kGShape[kGnnLayers] = {{64, 7},   {64, 64},  {64, 128}, {64, 192}, {64, 64}, {64, 128}, {64, 64},
+                                        {64, 192}, {64, 64},  {64, 128}, {64, 64},  {32, 64}, {1, 32}};
+
+uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// K index carried by slot i of lane group g in K chunk ks: 64-wide inputs use
+// the accumulator-compatible order of the kernels, the 7-wide input is padded
+int gnn_kidx(int in, int ks, int g, int i) {
+    if (in % 64 != 0) return 8 * g + i < in ? 8 * g + i : -1;
+    const int seg = ks / 2, ksl = ks % 2;
+    return seg * 64 + 32 * ksl + 16 * (i >> 2) + 4 * g + (i & 3);
+}
+
+}  // namespace
+
+lst_status lst_load_gnn(lst_ctx *c, const void *blob, size_t nbytes) {
+    if (!c || !blob) return LST_E_INVAL;
+    const unsigned char *b = (const unsigned char *)blob;
+    if (nbytes < 24 || memcmp(b, "LSTE", 4) != 0 || rd32(b + 4) != 1)
+        return fail(c, LST_E_INVAL, "edge-classifier blob: bad magic or version");
+    if (rd32(b + 8) != 7 || rd32(b + 12) != 64 || rd32(b + 16) != 32 || rd32(b + 20) != 2)
+        return fail(c, LST_E_INVAL, "edge-classifier blob: expected 7 inputs, hidden 64, head 32, 2 steps");
+    size_t nf = 0;
+    for (int l = 0; l < kGnnLayers; ++l) nf += (size_t)kGShape[l].out * kGShape[l].in + kGShape[l].out;
+    if (nbytes != 24 + 4 * nf) return fail(c, LST_E_INVAL, "edge-classifier blob: size %zu", nbytes);
+    std::vector<float> w(nf);
+    memcpy(w.data(), b + 24, 4 * nf);
+    // fragments (A operand order) for the MFMA layers, biases for all
+    std::vector<uint16_t> frag;
+    std::vector<float> bias;
+    GnnDev g{};
+    size_t at = 0;
+    const float *wh2 = nullptr;
+    float bh2 = 0.0f;
+    for (int l = 0; l < kGnnLayers; ++l) {
+        const int O = kGShape[l].out, I = kGShape[l].in;
+        const float *W = w.data() + at;
+        const float *B = W + (size_t)O * I;
+        at += (size_t)O * I + O;
+        g.boff[l] = (int64_t)bias.size();
+        bias.insert(bias.end(), B, B + O);
+        g.foff[l] = (int64_t)(frag.size() / 8);
+        if (l == kGHead2) { wh2 = W; bh2 = B[0]; continue; }
+        // K chunks of 32: the 7-wide input is one padded chunk
+        const int MB = O / 16, ks_n = I % 64 == 0 ? I / 32 : 1;
+        for (int mb = 0; mb < MB; ++mb)
+            for (int ks = 0; ks < ks_n; ++ks)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int gg = lane >> 4, cc = lane & 15;
+                    for (int i = 0; i < 8; ++i) {
+                        const int k = gnn_kidx(I, ks, gg, i);
+                        frag.push_back(f32_to_bf16_rne(k >= 0 ? W[(size_t)(mb * 16 + cc) * I + k] : 0.0f));
+                    }
+                }
+    }
+    bias.insert(bias.end(), wh2, wh2 + 32);      // head output weights after the biases
+    const size_t fbytes = frag.size() * 2, bbytes = bias.size() * 4;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (c->d_gnn) { (void)hipFree(c->d_gnn); c->d_gnn = nullptr; c->gnn_loaded = false; }
+    if (hipMalloc(&c->d_gnn, fbytes + bbytes) != hipSuccess) return fail(c, LST_E_NOMEM, "edge classifier");
+    HIP_TRY(c, hipMemcpy(c->d_gnn, frag.data(), fbytes, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy((char *)c->d_gnn + fbytes, bias.data(), bbytes, hipMemcpyHostToDevice));
+    g.frag = (const uint4 *)c->d_gnn;
+    g.bias = (const float *)((char *)c->d_gnn + fbytes);
+    g.wh2 = g.bias + (bias.size() - 32);
+    g.bh2 = bh2;
+    c->gnn = g;
+    c->gnn_loaded = true;
+    return LST_OK;
+}
+
+static size_t gnn_layout(int64_t n_nodes, int64_t n_edges, char *base, GnnWork *w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    char *h0 = take((size_t)n_nodes * 64 * 4), *h1 = take((size_t)n_nodes * 64 * 4);
+    char *e1 = take((size_t)n_edges * 64 * 4), *io = take((size_t)(n_nodes + 1) * 8), *er = take(8);
+    if (w) {
+        w->h0 = (float *)h0; w->h1 = (float *)h1; w->e1 = (float *)e1;
+        w->in_off = (int64_t *)io; w->err = (int64_t *)er;
+    }
+    return off;
+}
+
+lst_status lst_gnn_workspace_size(const lst_ctx *c, int64_t n_nodes, int64_t n_edges, size_t *bytes) {
+    if (!c || !bytes || n_nodes < 0 || n_edges < 0 || n_nodes > INT32_MAX) return LST_E_INVAL;
+    *bytes = gnn_layout(n_nodes, n_edges, nullptr, nullptr);
+    return LST_OK;
+}
+
+lst_status lst_gnn_score(lst_ctx *c, const float *x, int64_t n_nodes, const int32_t *src, const int32_t *dst,
+                         int64_t n_edges, float *scores, void *ws, size_t ws_bytes, int32_t flags, void *stream) {
+    if (!c) return LST_E_INVAL;
+    if (!c->gnn_loaded) return fail(c, LST_E_STATE, "load an edge classifier first");
+    if (n_nodes < 0 || n_edges < 0 || n_nodes > INT32_MAX) return fail(c, LST_E_INVAL, "bad graph size");
+    if (n_edges > 0 && n_nodes == 0) return fail(c, LST_E_INVAL, "edges without nodes");
+    if ((n_nodes > 0 && !x) || (n_edges > 0 && (!src || !dst || !scores)) || !ws)
+        return fail(c, LST_E_INVAL, "null argument");
+    if (((uintptr_t)ws & 255) != 0) return fail(c, LST_E_INVAL, "workspace must be 256-byte aligned");
+    const size_t need = gnn_layout(n_nodes, n_edges, nullptr, nullptr);
+    if (ws_bytes < need) return fail(c, LST_E_INVAL, "workspace %zu bytes, need %zu", ws_bytes, need);
+    if (n_nodes == 0) return LST_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    GnnWork w{};
+    gnn_layout(n_nodes, n_edges, (char *)ws, &w);
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, run_gnn(c->gnn, x, n_nodes, src, dst, n_edges, scores, w, st));
+    if (flags & LST_ASYNC) return LST_OK;
+    int64_t err = 0;
+    HIP_TRY(c, hipMemcpyAsync(&err, w.err, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (err & 1) return fail(c, LST_E_INVAL, "graph: node id out of range or edges not sorted by dst");
     return LST_OK;
 }
 

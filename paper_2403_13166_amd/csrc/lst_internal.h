@@ -99,6 +99,29 @@ struct RunArgs {
 constexpr int kTimingWindows = 7;
 constexpr int kTimingEvents = 2 * kTimingWindows;
 
+// Edge classifier: layers in model-blob order; all but the last are run on
+// MFMA from fragments in A-operand order (see lst_gnn.hip).
+enum GnnLayer {
+    kGEnc1, kGEnc2, kGInit, kGEdgeA0, kGEdgeB0, kGNodeA0, kGNodeB0, kGEdgeA1, kGEdgeB1, kGNodeA1, kGNodeB1,
+    kGHead1, kGHead2, kGnnLayers
+};
+struct GnnDev {
+    const uint4 *frag;                // BF16 fragments of every MFMA layer
+    int64_t foff[kGnnLayers];         // first fragment of each layer
+    const float *bias;                // FP32 biases of every layer
+    int64_t boff[kGnnLayers];
+    const float *wh2;                 // head output weights [32] (vector ALU)
+    float bh2;
+};
+struct GnnWork {
+    float *h0, *h1;                   // [n_nodes][64] node states
+    float *e1;                        // [n_edges][64] edge states after step 0
+    int64_t *in_off;                  // [n_nodes + 1] incoming-edge ranges
+    int64_t *err;                     // [1] bit 0: invalid graph
+};
+hipError_t run_gnn(const GnnDev &m, const float *x, int64_t n_nodes, const int32_t *src, const int32_t *dst,
+                   int64_t n_edges, float *score, const GnnWork &w, hipStream_t stream);
+
 // Enqueue the whole object-building pipeline on `stream`.
 hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipStream_t stream);
 // Enqueue standalone scoring of n rows (f32 or bf16 input).

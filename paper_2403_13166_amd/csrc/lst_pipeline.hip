@@ -350,9 +350,16 @@ static void run_stage(const S &s, const int64_t *n_dev, int64_t n_cap, const Wor
 // scans the histogram in LDS, writes the bin offsets, scatters its hits with
 // LDS cursors and finally orders each of its (small) bins by input index, so
 // the binned layout is deterministic. Hits with an out-of-range sensor id set
-// error bit 0 and are dropped.
+// error bit 0 and are dropped. Every pass over the event's hits keeps kBinU
+// independent loads in flight per thread (the passes are latency bound).
 
 constexpr int kBinThreads = 1024;
+constexpr int kBinU = 8;          // hits per thread per round
+constexpr int kBinSortReg = 8;    // bins up to this size are ordered in registers
+
+__device__ __forceinline__ void cswap_key(float4 &a, float4 &b) {
+    if (__float_as_int(a.w) > __float_as_int(b.w)) { const float4 t = a; a = b; b = t; }
+}
 
 __global__ __launch_bounds__(kBinThreads) void k_bin_event(const float *x, const float *y, const float *z,
                                                            const int32_t *sensor, const int64_t *ev_off,
@@ -368,15 +375,27 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_event(const float *x, const
     const int hi = lo + range < n_sens ? lo + range : n_sens;
     const int nb = hi - lo;
     const int64_t h0 = ev_off[e], h1 = ev_off[e + 1];
+    constexpr int64_t kRound = (int64_t)kBinThreads * kBinU;
     for (int i = threadIdx.x; i <= nb; i += kBinThreads) s_hist[i] = 0;
     __syncthreads();
     int64_t below = 0;
     bool bad = false;
-    for (int64_t h = h0 + threadIdx.x; h < h1; h += kBinThreads) {
-        const int sv = sensor[h];
-        if (sv < 0 || sv >= n_sens) { bad = true; continue; }
-        if (sv < lo) ++below;
-        else if (sv < hi) atomicAdd(&s_hist[sv - lo], 1);
+    for (int64_t hb = h0 + threadIdx.x; hb < h1; hb += kRound) {
+        int sv[kBinU];
+#pragma unroll
+        for (int u = 0; u < kBinU; ++u) {
+            const int64_t h = hb + (int64_t)u * kBinThreads;
+            sv[u] = h < h1 ? sensor[h] : lo - 1;
+        }
+#pragma unroll
+        for (int u = 0; u < kBinU; ++u) {
+            const int64_t h = hb + (int64_t)u * kBinThreads;
+            if (h >= h1) continue;
+            const int v = sv[u];
+            if (v < 0 || v >= n_sens) { bad = true; continue; }
+            if (v < lo) ++below;
+            else if (v < hi) atomicAdd(&s_hist[v - lo], 1);
+        }
     }
     if (bad && r == 0) atomicOr((unsigned long long *)&counts[LST_COUNT_ERR], 1ull);
     // block reduction of `below`
@@ -393,7 +412,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_event(const float *x, const
     __syncthreads();
     // exclusive scan of the histogram: thread t owns a contiguous run
     const int per = (nb + kBinThreads - 1) / kBinThreads;
-    const int a0 = threadIdx.x * per, a1 = a0 + per < nb ? a0 + per : nb;
+    const int a0 = threadIdx.x * per < nb ? threadIdx.x * per : nb;
+    const int a1 = a0 + per < nb ? a0 + per : nb;
     int64_t run = 0;
     for (int i = a0; i < a1; ++i) run += s_hist[i];
     int64_t inc = wave_incl_scan(run);
@@ -413,22 +433,53 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_event(const float *x, const
     if (e == n_ev - 1 && r == split - 1 && threadIdx.x == 0) bin_off[(int64_t)n_ev * n_sens] = base + tot;
     if (threadIdx.x == 0) s_hist[nb] = (int32_t)tot;
     __syncthreads();
-    for (int64_t h = h0 + threadIdx.x; h < h1; h += kBinThreads) {
-        const int sv = sensor[h];
-        if (sv < lo || sv >= hi) continue;
-        const int64_t pos = base + atomicAdd(&s_hist[sv - lo], 1);
-        bin_hit[pos] = make_float4(x[h], y[h], z[h], __int_as_float((int)h));
+    for (int64_t hb = h0 + threadIdx.x; hb < h1; hb += kRound) {
+        int sv[kBinU];
+#pragma unroll
+        for (int u = 0; u < kBinU; ++u) {
+            const int64_t h = hb + (int64_t)u * kBinThreads;
+            sv[u] = h < h1 ? sensor[h] : -1;
+        }
+        int pos[kBinU];
+#pragma unroll
+        for (int u = 0; u < kBinU; ++u)
+            pos[u] = (sv[u] >= lo && sv[u] < hi) ? atomicAdd(&s_hist[sv[u] - lo], 1) : -1;
+#pragma unroll
+        for (int u = 0; u < kBinU; ++u) {
+            if (pos[u] < 0) continue;
+            const int64_t h = hb + (int64_t)u * kBinThreads;
+            bin_hit[base + pos[u]] = make_float4(x[h], y[h], z[h], __int_as_float((int)h));
+        }
     }
     __syncthreads();
-    // each cursor now holds the end of its bin (the next bin's start)
+    // each cursor now holds the end of its bin (the next bin's start); order
+    // every bin by input index: small bins with a sorting network in
+    // registers, larger ones (rare) by insertion in place
     for (int i = threadIdx.x; i < nb; i += kBinThreads) {
         const int64_t bs = base + (i == 0 ? 0 : s_hist[i - 1]), be = base + s_hist[i];
-        for (int64_t k = bs + 1; k < be; ++k) {
-            const float4 v = bin_hit[k];
-            const int key = __float_as_int(v.w);
-            int64_t j = k - 1;
-            while (j >= bs && __float_as_int(bin_hit[j].w) > key) { bin_hit[j + 1] = bin_hit[j]; --j; }
-            bin_hit[j + 1] = v;
+        const int n = (int)(be - bs);
+        if (n <= 1) continue;
+        if (n <= kBinSortReg) {
+            float4 v[kBinSortReg];
+#pragma unroll
+            for (int k = 0; k < kBinSortReg; ++k)
+                v[k] = k < n ? bin_hit[bs + k] : make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fffffff));
+#pragma unroll
+            for (int p = 0; p < kBinSortReg; ++p) {
+#pragma unroll
+                for (int k = p & 1; k + 1 < kBinSortReg; k += 2) cswap_key(v[k], v[k + 1]);
+            }
+#pragma unroll
+            for (int k = 0; k < kBinSortReg; ++k)
+                if (k < n) bin_hit[bs + k] = v[k];
+        } else {
+            for (int64_t k = bs + 1; k < be; ++k) {
+                const float4 v = bin_hit[k];
+                const int key = __float_as_int(v.w);
+                int64_t j = k - 1;
+                while (j >= bs && __float_as_int(bin_hit[j].w) > key) { bin_hit[j + 1] = bin_hit[j]; --j; }
+                bin_hit[j + 1] = v;
+            }
         }
     }
 }
@@ -484,33 +535,57 @@ struct MDStage {
 
 // CSR offsets from a sorted key column: off[k] = first i with key(i) >= k,
 // for k in [0, K]; every entry written exactly once.
+// off[k] = first i < n with key(i) >= k (n if none), for k = 0..K, over keys
+// sorted ascending: one lower-bound search per k, so empty key ranges of any
+// length (modules without MDs, events without hits) cost nothing extra.
 template <class KF>
 __global__ void k_fill_offsets(KF key, const int64_t *n_dev, int64_t n_cap, const int64_t *K_dev,
                                int64_t K_cap, int64_t *off) {
-    int64_t n = n_dev ? dev_count(n_dev, n_cap) : n_cap;
-    int64_t K = K_dev ? dev_count(K_dev, K_cap) : K_cap;
-    for (int64_t i = grid_tid(); i <= n; i += grid_stride()) {
-        int64_t kc = i < n ? (int64_t)key(i) : K;
-        int64_t kp = i > 0 ? (int64_t)key(i - 1) : -1;
-        if (kc > K) kc = K;
-        for (int64_t k = kp + 1; k <= kc; ++k) off[k] = i;
+    const int64_t n = n_dev ? dev_count(n_dev, n_cap) : n_cap;
+    const int64_t K = K_dev ? dev_count(K_dev, K_cap) : K_cap;
+    for (int64_t k = grid_tid(); k <= K; k += grid_stride()) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)key(mid) < k) lo = mid + 1; else hi = mid;
+        }
+        off[k] = lo;
     }
 }
 
-// MDs available to the LS stage from every module: rsum[gm] and the
-// exclusive prefix over the module-map entries (per event).
-__global__ void k_ls_prefix(const int32_t *map_off, const int32_t *map_tgt, int32_t n_mod, int32_t n_map,
-                            int32_t n_ev, const int64_t *md_mod_off, int32_t *rsum, int32_t *rpref) {
-    int64_t N = (int64_t)n_ev * n_mod;
-    for (int64_t gm = grid_tid(); gm < N; gm += grid_stride()) {
-        int64_t e = gm / n_mod, m = gm - e * n_mod;
+// Per (event, module): rsum = MDs in the module's mapped modules, and for each
+// map entry the exclusive prefix of those counts along the module's row. One
+// 16-lane segment per (event, module) takes the row 16 entries at a time with
+// a segmented scan, so the row's reads and writes are coalesced.
+constexpr int kPrefSeg = 16;
+
+__global__ __launch_bounds__(kBlock) void k_ls_prefix(const int32_t *map_off, const int32_t *map_tgt,
+                                                      int32_t n_mod, int32_t n_map, int32_t n_ev,
+                                                      const int64_t *md_mod_off, int32_t *rsum, int32_t *rpref) {
+    const int64_t N = (int64_t)n_ev * n_mod;
+    const int sl = threadIdx.x & (kPrefSeg - 1);
+    const int64_t nseg = grid_stride() / kPrefSeg;
+    for (int64_t gm = grid_tid() / kPrefSeg; gm < N; gm += nseg) {
+        const int64_t e = gm / n_mod, m = gm - e * n_mod;
+        const int32_t k0 = map_off[m], k1 = map_off[m + 1];
         int32_t acc = 0;
-        for (int32_t k = map_off[m]; k < map_off[m + 1]; ++k) {
-            rpref[e * n_map + k] = acc;
-            int64_t t = e * n_mod + map_tgt[k];
-            acc += (int32_t)(md_mod_off[t + 1] - md_mod_off[t]);
+        for (int32_t kb = k0; kb < k1; kb += kPrefSeg) {
+            const int32_t k = kb + sl;
+            int32_t c = 0;
+            if (k < k1) {
+                const int64_t t = e * n_mod + map_tgt[k];
+                c = (int32_t)(md_mod_off[t + 1] - md_mod_off[t]);
+            }
+            int32_t v = c;
+#pragma unroll
+            for (int d = 1; d < kPrefSeg; d <<= 1) {
+                const int32_t o = __shfl_up(v, d, kPrefSeg);
+                if (sl >= d) v += o;
+            }
+            if (k < k1) rpref[e * n_map + k] = acc + v - c;
+            acc += __shfl(v, kPrefSeg - 1, kPrefSeg);
         }
-        rsum[gm] = acc;
+        if (sl == 0) rsum[gm] = acc;
     }
 }
 
@@ -877,9 +952,9 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     // a2: mini-doublets, anchored on (event, module)
     MDStage md{w.bin_off, w.bin_hit, a.g.mod, a.p, n_mod, n_sens, o.md_hits, w.md_a, w.md_o};
     run_stage(md, nullptr, ngm, w, cnt + LST_COUNT_MD, w.cap_md, cnt, st, ev, 2, a.tune);
-    hipLaunchKernelGGL(k_fill_offsets<GmKey>, dim3(grid_for(w.cap_md)), dim3(kBlock), 0, st, GmKey{w.md_a},
+    hipLaunchKernelGGL(k_fill_offsets<GmKey>, dim3(grid_for(ngm + 1)), dim3(kBlock), 0, st, GmKey{w.md_a},
                        cnt + LST_COUNT_MD, w.cap_md, nullptr, ngm, w.md_mod_off);
-    hipLaunchKernelGGL(k_ls_prefix, dim3(grid_for(ngm)), dim3(kBlock), 0, st, a.g.map_off, a.g.map_tgt, n_mod,
+    hipLaunchKernelGGL(k_ls_prefix, dim3(grid_for(ngm * kPrefSeg)), dim3(kBlock), 0, st, a.g.map_off, a.g.map_tgt, n_mod,
                        n_map, a.n_ev, w.md_mod_off, w.rsum, w.rpref);
 
     // a3: line segments, anchored on (event, module): the module's MDs against
@@ -887,13 +962,13 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     LSStage ls{w.md_a, w.md_o, w.md_mod_off, w.rsum, w.rpref, a.g.map_off, a.g.map_tgt, a.g.mod, a.p,
                n_mod, n_map, o.ls_md};
     run_stage(ls, nullptr, ngm, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st, ev, 3, a.tune);
-    hipLaunchKernelGGL(k_fill_offsets<LsInKey>, dim3(grid_for(w.cap_ls)), dim3(kBlock), 0, st, LsInKey{o.ls_md},
+    hipLaunchKernelGGL(k_fill_offsets<LsInKey>, dim3(grid_for(w.cap_md + 1)), dim3(kBlock), 0, st, LsInKey{o.ls_md},
                        cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w.ls_off);
 
     // a4: triplets, anchored on the inner LS
     T3Stage t3{o.ls_md, w.ls_off, w.md_a, w.md_o, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
     run_stage(t3, cnt + LST_COUNT_LS, w.cap_ls, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st, ev, 4, a.tune);
-    hipLaunchKernelGGL(k_fill_offsets<T3InKey>, dim3(grid_for(w.cap_t3)), dim3(kBlock), 0, st, T3InKey{w.t3_mds},
+    hipLaunchKernelGGL(k_fill_offsets<T3InKey>, dim3(grid_for(w.cap_md + 1)), dim3(kBlock), 0, st, T3InKey{w.t3_mds},
                        cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w.t3i_off);
 
     // a5: quintuplets, anchored on the inner T3: FP32 beam-line cuts, then the

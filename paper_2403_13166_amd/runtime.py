@@ -253,6 +253,55 @@ class Builder:
         return out
 
 
+class EdgeClassifier:
+    """Edge scores of an LST object graph (own device context; see lst_gnn_score)."""
+
+    def __init__(self, gnn_blob: bytes, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the edge classifier needs a ROCm GPU (torch.cuda is not available)")
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        self.ctx = B.lst_create(device)
+        B.lst_load_gnn(self.ctx, gnn_blob)
+        self._ws = None
+        self._ws_bytes = 0
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            B.lst_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, n_nodes: int, n_edges: int):
+        need = B.lst_gnn_workspace_size(self.ctx, n_nodes, n_edges)
+        if self._ws is None or need > self._ws_bytes:
+            self._ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+            self._ws_bytes = need
+
+    def score(self, x: torch.Tensor, src: torch.Tensor, dst: torch.Tensor, out: torch.Tensor | None = None,
+              asynchronous: bool = False) -> torch.Tensor:
+        """x [N, 7] f32, src/dst [E] int32 with dst sorted; returns scores [E] f32."""
+        if x.dim() != 2 or x.shape[1] != 7 or x.dtype != torch.float32 or not x.is_contiguous():
+            raise ValueError("x must be a contiguous [N, 7] float32 tensor")
+        for t in (src, dst):
+            if t.dtype != torch.int32 or not t.is_contiguous() or t.shape != src.shape:
+                raise ValueError("src and dst must be contiguous int32 tensors of one length")
+        n, e = int(x.shape[0]), int(src.shape[0])
+        self.reserve(n, e)
+        if out is None:
+            out = torch.empty(e, dtype=torch.float32, device=x.device)
+        ws = (self._ws.data_ptr() + 255) & ~255
+        B.lst_gnn_score(self.ctx, x.data_ptr(), n, src.data_ptr(), dst.data_ptr(), e, out.data_ptr(), ws,
+                        self._ws_bytes, B.LST_ASYNC if asynchronous else 0,
+                        torch.cuda.current_stream(x.device).cuda_stream)
+        return out
+
+
 def to_device(ev, device) -> tuple:
     """Event arrays (numpy) -> device tensors (x, y, z, sensor)."""
     d = torch.device(device)
