@@ -30,6 +30,28 @@ sys.path.insert(0, ROOT)
 METRIC = "events/s at PU200-like occupancy (served+batched vs plain); p99 latency"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE, each scaled by the counts of a plain 512 MiB
+# elementwise kernel), kept with the hash of the kernel sources they were
+# taken on: a changed kernel reports null until it is measured again.
+MEASURED_TRAFFIC = {
+    ("ls stage", 8): {"bytes": 323844325.9, "source_sha1": "ae3e279a05877fe055a7ea70374f6dfb06dbcd95"},
+}
+KERNEL_SOURCES = ("paper_2403_13166_amd/csrc/lst_pipeline.hip", "paper_2403_13166_amd/csrc/lst_device.h",
+                  "paper_2403_13166_amd/csrc/lst_internal.h")
+
+
+def measured_traffic(kernel: str, tile: int):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get((kernel, tile))
+    if rec is None:
+        return None
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return rec["bytes"] if h.hexdigest() == rec["source_sha1"] else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -47,6 +69,12 @@ def parse():
     ap.add_argument("--plain-events", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-events", type=int, default=2000,
+                    help="events per served stream (0: skip the serving measurement)")
+    ap.add_argument("--serve-rates", default="500,20000",
+                    help="Poisson arrival rates (events/s) of the served streams; the largest saturates the GPU")
+    ap.add_argument("--skip-extras", action="store_true",
+                    help="skip the standalone scoring, edge-classifier and pre-DNN measurements")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device copy of this size after the timed region (HBM counter scale)")
     return ap.parse_args()
@@ -73,6 +101,64 @@ def stage_bytes(c, n_hits, n_ev, n_mod, n_map, precision):
         "t5": 24 * t3 + 40 * md + 16 * t5,
         "score": score,
     }
+
+
+def _time_ms(fn, stream, reps=10):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    stream.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        stream.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def measure_extras(b, dx, dy, dz, ds, doff, stream, prec):
+    """Standalone T5-DNN scoring of 1M feature rows (BF16 MFMA and FP32), the
+    edge classifier on a 200k-node / 1M-edge LST-like graph, and the T5 stage
+    of the same batch in pre-DNN mode (circle-fit chi2 cut, no DNN)."""
+    import torch
+    from paper_2403_13166_amd import binding as B
+    from paper_2403_13166_amd.runtime import EdgeClassifier
+    from paper_2403_13166_amd.synth import gnn as SG, model as M
+    dev = dx.device
+    out = {}
+    with torch.cuda.stream(stream):
+        X = torch.from_numpy(M.make_scoring_inputs(1_000_000)).to(dev)
+        for name, p_ in (("bf16_mfma", B.LST_PREC_BF16), ("f32_valu", B.LST_PREC_F32)):
+            ms = _time_ms(lambda: b.score(X, precision=p_), stream)
+            out[f"score_1M_{name}"] = {"ms": ms, "gb_per_s": (168 + 4) * 1e6 / (ms * 1e-3) / 1e9,
+                                       "rows_per_s": 1e6 / (ms * 1e-3)}
+        g = SG.make_graph()
+        clf = EdgeClassifier(SG.make_gnn_model().to_blob(), dev.index or 0)
+        gx, gs, gd = (torch.from_numpy(v).to(dev) for v in (g.x, g.src, g.dst))
+        sc = torch.empty(g.n_edges, dtype=torch.float32, device=dev)
+        ms = _time_ms(lambda: clf.score(gx, gs, gd, out=sc, asynchronous=True), stream)
+        macs = g.n_nodes * (7 * 64 + 64 * 64 + 128 * 64 + 64 * 64) + g.n_edges * (
+            128 * 64 + 2 * (192 * 64 + 64 * 64) + 64 * 32 + 32)
+        out["edge_classifier_200k_1M"] = {"ms": ms, "tflop_per_s": 2 * macs / (ms * 1e-3) / 1e12,
+                                          "edges_per_s": g.n_edges / (ms * 1e-3)}
+        clf.close()
+        # T5 stage in both modes on the batch (paper Table 2 analogue)
+        t5 = {}
+        B.lst_set_timing(b.ctx, True)
+        for mname, mode in (("dnn", B.LST_MODE_DNN), ("pre_dnn", B.LST_MODE_PRE_DNN)):
+            vals = []
+            for _ in range(5):
+                b.launch(dx, dy, dz, ds, event_offsets=doff, mode=mode, precision=prec)
+                stream.synchronize()
+                st_ = B.lst_stage_times(b.ctx)
+                vals.append((st_["t5"], st_["score"], st_["build"]))
+            v = np.median(np.array(vals), axis=0)
+            t5[mname] = {"t5_ms": float(v[0]), "dnn_ms": float(v[1]), "build_ms": float(v[2])}
+        B.lst_set_timing(b.ctx, False)
+        out["t5_stage_by_mode"] = t5
+    return out
 
 
 def cpu_baseline(geo, evs, seconds):
@@ -211,6 +297,27 @@ def main():
         plain_rate = n_plain / (time.perf_counter() - tp0)
         pb.close()
 
+    # ---------------- other rows of the path, each timed with HIP events on its stream
+    extras = None
+    if not a.skip_extras:
+        extras = measure_extras(b, dx, dy, dz, ds, doff, stream, prec)
+
+    # ---------------- served path: Poisson streams of PU-varying events with
+    # continuous batching over HBM-budgeted slots (latency = arrival -> objects on host)
+    served = None
+    if a.serve_events > 0:
+        from paper_2403_13166_amd import serve as S
+        sgeo, pool = S.make_pool(32)
+        served = {"pool": "32 events, PU ~ U[50, 200], 30 tracks + 500 noise hits per unit PU",
+                  "slots": 3, "events_cap": 16, "budget_gib": 64, "streams": []}
+        for rate in [float(r) for r in a.serve_rates.split(",")]:
+            st = S.serve_stream(sgeo, pool, rate, a.serve_events, 3, 1_600_000, 16, 64 << 30, mode=mode,
+                                precision=prec)
+            served["streams"].append({k: st[k] for k in ("rate", "events", "events_per_s", "p50_ms", "p99_ms",
+                                                         "mean_batch", "max_batch", "max_inflight")})
+            print(f"served stream at {rate:.0f} ev/s: {st['events_per_s']:.1f} ev/s, p50 {st['p50_ms']:.2f} ms, "
+                  f"p99 {st['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+
     if a.copy_calibration_mb > 0:
         # one plain elementwise kernel that reads and writes exactly this many
         # bytes: the scale of the HBM byte counters
@@ -225,8 +332,10 @@ def main():
     dom = max(kern, key=kern.get)
     sb = stage_bytes(final, len(x), a.events, geo.n_modules, int(geo.map_tgt.shape[0]), a.precision)
     achieved = sb[dom] / (avg[dom] * 1e-3) / 1e9
+    stage_idx = {"md": 0, "ls": 1, "t3": 2, "t5": 4}
+    tile = tuned["tile_per"][stage_idx[dom]] if dom in stage_idx else None
     roofline = {"bound": "hbm", "kernel": f"{dom} stage", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"{dom} stage", tile),
                 "algorithmic_bytes_per_launch": sb[dom], "avg_launch_ms": avg[dom]}
     stage_gbs = {k: sb[k] / (avg[k] * 1e-3) / 1e9 for k in kern}
 
@@ -251,7 +360,8 @@ def main():
         "speedup_batched_vs_plain": value / plain_rate,
         "stage_ms": avg, "stage_gbs": stage_gbs,
         "objects_per_event": {"md": per_ev[0], "ls": per_ev[1], "t3": per_ev[2], "t5": per_ev[3]},
-        "max_candidates_per_stage": int(final[5]),
+        "max_candidates_per_stage": int(final[5]), "t5_pre_candidates": int(final[6]),
+        "served": served, "extras": extras,
         "input_generation_s": t_gen, "stage_timing": timing_src,
         "tuning": tuned, "autotune": tune_table,
     }

@@ -14,8 +14,13 @@ LIB = os.path.join(HERE, "liblst.so")
 SOURCES = ["lst_capi.hip", "lst_pipeline.hip", "lst_score.hip", "lst_gnn.hip"]
 ARCH = os.environ.get("LST_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# FP32 division and square root use the hardware's 1-ulp sequences instead of
+# correctly rounded emulation: every cut compares against its threshold far
+# outside that error (results within 1e-5 relative of a threshold are the
+# documented marginal band), and NaN still fails every "v <= t" test.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 

@@ -298,9 +298,41 @@ __device__ __forceinline__ double clamp_log(double v) {
 
 // The 42 DNN inputs (Sec. 2 list plus this project's additions), FP64 -> FP32,
 // before standardisation.
-__device__ inline void t5_features(const CutParams &p, const double *x, const double *y,
-                                   const double *z, const int *layer, const bool *endc,
-                                   const Fit5 &f, float *ft) {
+// What the feature row needs from the fits, kept as FP32 by the fit stage:
+// R, tan(lambda), z0, |d0| and the (unnormalised) direction at the point of
+// closest approach, oriented toward the first anchor.
+constexpr int kNFitOut = 6;
+__device__ inline void t5_fit_outputs(const double *x, const double *y, const Fit5 &f, float *fo) {
+    double u0 = -f.xm, v0 = -f.ym;
+    double d0 = circle_distance(f.A, f.B, f.C, f.D, u0, v0);
+    double gx = 2.0 * f.A * u0 + f.B, gy = 2.0 * f.A * v0 + f.C;
+    double dx = -gy, dy = gx;
+    if (x[0] * dx + y[0] * dy < 0) { dx = -dx; dy = -dy; }
+    fo[0] = (float)f.R;
+    fo[1] = (float)f.t;
+    fo[2] = (float)f.z0;
+    fo[3] = (float)fabs(d0);
+    fo[4] = (float)dx;
+    fo[5] = (float)dy;
+}
+
+// The seven features that come from the fits (indices 34, 35, 36, 38, 39, 40,
+// 41 of the feature row), from the fit outputs and the two chi2 values.
+constexpr int kNFitFeat = 7;
+__device__ inline void t5_fit_features_from(const CutParams &p, const float *fo, double chi2_rphi,
+                                            double chi2_rz, float *ff) {
+    ff[0] = (float)clamp_log(p.kb_d * (double)fo[0]);
+    ff[1] = (float)asinh((double)fo[1]);
+    ff[2] = (float)atan2((double)fo[5], (double)fo[4]);
+    ff[3] = (float)log1p(chi2_rphi);
+    ff[4] = (float)log1p(chi2_rz);
+    ff[5] = fo[3];
+    ff[6] = fo[2];
+}
+
+// The feature row from the anchors and the fit features above.
+__device__ inline void t5_features_from(const CutParams &p, const double *x, const double *y, const double *z,
+                                        const int *layer, const bool *endc, const float *ff, float *ft) {
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         double r = sqrt(x[i] * x[i] + y[i] * y[i]);
@@ -317,19 +349,23 @@ __device__ inline void t5_features(const CutParams &p, const double *x, const do
     ft[31] = (float)clamp_log(circumradius_d(x[0], y[0], x[1], y[1], x[2], y[2]));
     ft[32] = (float)clamp_log(p.kb_d / (2.0 * cou));
     ft[33] = (float)clamp_log(circumradius_d(x[2], y[2], x[3], y[3], x[4], y[4]));
-    ft[34] = (float)clamp_log(p.kb_d * f.R);
-    ft[35] = (float)asinh(f.t);
-    double u0 = -f.xm, v0 = -f.ym;
-    double d0 = circle_distance(f.A, f.B, f.C, f.D, u0, v0);
-    double gx = 2.0 * f.A * u0 + f.B, gy = 2.0 * f.A * v0 + f.C;
-    double dx = -gy, dy = gx;
-    if (x[0] * dx + y[0] * dy < 0) { dx = -dx; dy = -dy; }
-    ft[36] = (float)atan2(dy, dx);
+    ft[34] = ff[0];
+    ft[35] = ff[1];
+    ft[36] = ff[2];
     ft[37] = (float)clamp_log(circumradius_d(x[1], y[1], x[2], y[2], x[3], y[3]));
-    ft[38] = (float)log1p(f.chi2_rphi);
-    ft[39] = (float)log1p(f.chi2_rz);
-    ft[40] = (float)fabs(d0);
-    ft[41] = (float)f.z0;
+    ft[38] = ff[3];
+    ft[39] = ff[4];
+    ft[40] = ff[5];
+    ft[41] = ff[6];
+}
+
+__device__ inline void t5_features(const CutParams &p, const double *x, const double *y,
+                                   const double *z, const int *layer, const bool *endc,
+                                   const Fit5 &f, float *ft) {
+    float fo[kNFitOut], ff[kNFitFeat];
+    t5_fit_outputs(x, y, f, fo);
+    t5_fit_features_from(p, fo, f.chi2_rphi, f.chi2_rz, ff);
+    t5_features_from(p, x, y, z, layer, endc, ff, ft);
 }
 
 // T5-DNN forward pass, FP32 vector ALU (weights read with wave-uniform

@@ -56,7 +56,7 @@ __device__ __forceinline__ void layer(const uint4 *Lf, const bf16x8 (*B)[kNB], f
 #pragma unroll
         for (int nb = 0; nb < kNB; ++nb) D[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
+    for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             const bf16x8 a = __builtin_bit_cast(bf16x8, Lf[(mb * KS + ks) * 64 + lane]);
@@ -64,6 +64,11 @@ __device__ __forceinline__ void layer(const uint4 *Lf, const bf16x8 (*B)[kNB], f
             for (int nb = 0; nb < kNB; ++nb)
                 D[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[ks][nb], D[mb][nb], 0, 0, 0);
         }
+        // keep one K chunk of weight fragments live at a time (otherwise the
+        // scheduler hoists every fragment of the layer and occupancy drops to
+        // one wave per SIMD)
+        __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
 // FP32 values in accumulator layout (units 16 q + 4 g + j) -> two B chunks

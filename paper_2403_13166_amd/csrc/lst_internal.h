@@ -14,7 +14,7 @@ constexpr int kBlock = 256;
 constexpr int kScanBlocks = 1024;
 constexpr int kEvalBlocks = 4096;     // persistent compaction blocks (256 CUs x 16)
 constexpr int kMaxStride = 8192;      // grid cap of grid-stride kernels
-constexpr int kMaxRecBytes = 32;      // largest per-candidate record a stage compacts
+constexpr int kMaxRecBytes = 48;      // largest per-candidate record a stage compacts
 constexpr int kBinLdsMax = 65536;     // LDS bytes of one binning block's histogram, at most
 
 // Launch shapes (never change results: outputs are in candidate order for any
@@ -69,6 +69,7 @@ struct Work {
     int64_t cap_t5pre;
     int2 *t5_pre;                     // [cap_t5pre] T3 pairs passing the FP32 cuts
     float *t5_feat;                   // [cap_t5][42] feature rows for the MFMA scorer
+    float *t5_fitf;                   // [cap_t5][8] fit features of each T5 (first kNFitFeat used)
     int64_t *ev_off;                  // [2] event offsets of a single-event call
 };
 

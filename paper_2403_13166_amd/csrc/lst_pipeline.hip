@@ -180,6 +180,43 @@ struct TileLds {
     int32_t ent_mod[kEnt > 0 ? kEnt : 1];
 };
 
+// Two-phase stages split their cuts: phase 1 runs on every candidate, and the
+// survivors of each wavefront are queued in LDS so that phase 2 (the costly
+// remainder) runs on dense batches of 64 instead of wave-wide on every
+// sub-round; results return to the candidate's slot, so the outcome and the
+// output order are those of the single-phase evaluation.
+constexpr int kQCap = 128;            // queued survivors per wavefront (flushed at 64)
+
+template <class S, int kPer, bool kOn>
+struct PhaseQ { };
+template <class S, int kPer>
+struct PhaseQ<S, kPer, true> {
+    typename S::Mid e[kBlock / 64][kQCap];
+    uint16_t slot[kBlock / 64][kQCap];
+    uint8_t res[kBlock / 64][kPer * 64];
+};
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// run phase 2 on queue entries [0, n) (n <= 64), then move entries [64, qn) to the front
+template <class S, class Q>
+__device__ __forceinline__ void phase2_flush(const S &st, Q &q, int wv, int lane, int n, int qn) {
+    wave_sync_lds();
+    if (lane < n) q.res[wv][q.slot[wv][lane]] = st.eval2(q.e[wv][lane]) ? 1 : 0;
+    const int rest = qn - n;
+    typename S::Mid te;
+    uint16_t ts = 0;
+    wave_sync_lds();
+    if (lane < rest) { te = q.e[wv][n + lane]; ts = q.slot[wv][n + lane]; }
+    wave_sync_lds();
+    if (lane < rest) { q.e[wv][lane] = te; q.slot[wv][lane] = ts; }
+    wave_sync_lds();
+}
+
 // Compaction of one stage in three steps, none of which waits on another
 // block: (1) the eval kernel takes tiles of kBlock * kPer candidates
 // (grid-stride), stages the tile's anchor window in LDS, applies the cuts and
@@ -198,6 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_eval(S st, const int64_t *cand
     constexpr int kSeg = kPer * kWaves;     // output segments, in candidate order
     __shared__ TileLds<S::kEnt> L;
     __shared__ int s_cnt[kSeg];
+    __shared__ PhaseQ<S, kPer, S::kTwoPhase> Q;
     const int64_t na = n_dev ? dev_count(n_dev, n_cap) : n_cap;
     const int64_t total = cand_off[na];
     int64_t ntiles = (total + kTileC - 1) / kTileC;
@@ -229,10 +267,12 @@ __global__ __launch_bounds__(kBlock) void k_stage_eval(S st, const int64_t *cand
         bool pass[kPer];
         int wlo = 0;                 // window index (staged)
         int64_t glo = alo;           // anchor index (global search)
+        int qn = 0;                  // queued phase-2 entries of this wavefront
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int64_t g = tile * kTileC + i * kBlock + threadIdx.x;
             pass[i] = false;
+            typename S::Mid mid_i;
             if (g < total) {
                 if (staged) {
                     int hi = nw;      // largest w in [wlo, nw) with off[w] <= g
@@ -240,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_eval(S st, const int64_t *cand
                         int mid = (wlo + hi) >> 1;
                         if (L.off[mid] <= g) wlo = mid; else hi = mid;
                     }
-                    pass[i] = st.eval(alo + wlo, (int32_t)(g - L.off[wlo]), L.info[wlo], L, rec[i]);
+                    pass[i] = st.eval(alo + wlo, (int32_t)(g - L.off[wlo]), L.info[wlo], L, rec[i], mid_i);
                 } else {
                     int64_t hi = ahi + 1;
                     while (hi - glo > 1) {
@@ -250,9 +290,28 @@ __global__ __launch_bounds__(kBlock) void k_stage_eval(S st, const int64_t *cand
                     int32_t f[4];
                     st.info(glo, f);
                     f[2] = S::kEnt > 0 ? -1 : f[2];
-                    pass[i] = st.eval(glo, (int32_t)(g - cand_off[glo]), f, L, rec[i]);
+                    pass[i] = st.eval(glo, (int32_t)(g - cand_off[glo]), f, L, rec[i], mid_i);
                 }
             }
+            if constexpr (S::kTwoPhase) {
+                const unsigned long long m = __ballot(pass[i]);
+                const int rk = __popcll(m & ((1ull << lane) - 1ull));
+                if (pass[i]) {
+                    Q.e[wv][qn + rk] = mid_i;
+                    Q.slot[wv][qn + rk] = (uint16_t)(i * 64 + lane);
+                }
+                qn += __popcll(m);
+                if (qn >= 64) {
+                    phase2_flush(st, Q, wv, lane, 64, qn);
+                    qn -= 64;
+                }
+            }
+        }
+        if constexpr (S::kTwoPhase) {
+            if (qn > 0) phase2_flush(st, Q, wv, lane, qn, qn);
+#pragma unroll
+            for (int i = 0; i < kPer; ++i)
+                if (pass[i]) pass[i] = Q.res[wv][i * 64 + lane] != 0;
         }
         int rank[kPer];
 #pragma unroll
@@ -356,6 +415,8 @@ static void run_stage(const S &s, const int64_t *n_dev, int64_t n_cap, const Wor
 constexpr int kBinThreads = 1024;
 constexpr int kBinU = 8;          // hits per thread per round
 constexpr int kBinSortReg = 8;    // bins up to this size are ordered in registers
+constexpr int kBigBins = 1024;    // larger bins one block ranks in parallel, at most
+constexpr int kBigPer = 8;        // their elements per thread, at most
 
 __device__ __forceinline__ void cswap_key(float4 &a, float4 &b) {
     if (__float_as_int(a.w) > __float_as_int(b.w)) { const float4 t = a; a = b; b = t; }
@@ -368,6 +429,9 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_event(const float *x, const
     extern __shared__ int32_t s_hist[];          // [range + 1]
     __shared__ int64_t s_red[kBinThreads / 64];
     __shared__ int64_t s_base;
+    __shared__ int32_t s_big[kBigBins];
+    __shared__ int32_t s_bigpre[kBigBins + 1];
+    __shared__ int s_nbig;
     const int e = blockIdx.x / split, r = blockIdx.x - e * split;
     const int range = (n_sens + split - 1) / split;
     // ranges past the last sensor are empty (nb = 0), never negative
@@ -440,21 +504,32 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_event(const float *x, const
             const int64_t h = hb + (int64_t)u * kBinThreads;
             sv[u] = h < h1 ? sensor[h] : -1;
         }
+        // coordinates of the range's hits are requested before the LDS
+        // atomics so that both latencies overlap
+        float4 hv[kBinU];
+#pragma unroll
+        for (int u = 0; u < kBinU; ++u) {
+            const int64_t h = hb + (int64_t)u * kBinThreads;
+            hv[u] = (sv[u] >= lo && sv[u] < hi) ? make_float4(x[h], y[h], z[h], __int_as_float((int)h))
+                                                : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
         int pos[kBinU];
 #pragma unroll
         for (int u = 0; u < kBinU; ++u)
             pos[u] = (sv[u] >= lo && sv[u] < hi) ? atomicAdd(&s_hist[sv[u] - lo], 1) : -1;
 #pragma unroll
-        for (int u = 0; u < kBinU; ++u) {
-            if (pos[u] < 0) continue;
-            const int64_t h = hb + (int64_t)u * kBinThreads;
-            bin_hit[base + pos[u]] = make_float4(x[h], y[h], z[h], __int_as_float((int)h));
-        }
+        for (int u = 0; u < kBinU; ++u)
+            if (pos[u] >= 0) bin_hit[base + pos[u]] = hv[u];
     }
     __syncthreads();
     // each cursor now holds the end of its bin (the next bin's start); order
-    // every bin by input index: small bins with a sorting network in
-    // registers, larger ones (rare) by insertion in place
+    // every bin by input index. Bins of up to kBinSortReg hits: a sorting
+    // network in registers by the bin's owner thread. Larger bins: listed in
+    // LDS, then every element of them gets its own thread, which counts the
+    // smaller keys of its bin (its rank); all elements are read before any is
+    // written back at its rank (in place, the block owns these positions).
+    if (threadIdx.x == 0) s_nbig = 0;
+    __syncthreads();
     for (int i = threadIdx.x; i < nb; i += kBinThreads) {
         const int64_t bs = base + (i == 0 ? 0 : s_hist[i - 1]), be = base + s_hist[i];
         const int n = (int)(be - bs);
@@ -473,6 +548,58 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_event(const float *x, const
             for (int k = 0; k < kBinSortReg; ++k)
                 if (k < n) bin_hit[bs + k] = v[k];
         } else {
+            const int slot = atomicAdd(&s_nbig, 1);
+            if (slot < kBigBins) s_big[slot] = i;
+        }
+    }
+    __syncthreads();
+    const int nbig = s_nbig;
+    // sizes of the listed big bins -> exclusive prefix (one entry per thread)
+    int my_n = 0;
+    if (threadIdx.x < nbig && threadIdx.x < kBigBins) {
+        const int i = s_big[threadIdx.x];
+        my_n = s_hist[i] - (i == 0 ? 0 : s_hist[i - 1]);
+    }
+    const int64_t incl = wave_incl_scan((int64_t)my_n);
+    if (lane == 63) s_red[wv] = incl;
+    __syncthreads();
+    int64_t boff = 0, btot = 0;
+    for (int k = 0; k < kBinThreads / 64; ++k) { if (k < wv) boff += s_red[k]; btot += s_red[k]; }
+    if (threadIdx.x < kBigBins) s_bigpre[threadIdx.x] = (int32_t)(boff + incl - my_n);
+    if (threadIdx.x == 0) s_bigpre[kBigBins] = (int32_t)btot;
+    __syncthreads();
+    if (nbig <= kBigBins && btot <= (int64_t)kBinThreads * kBigPer) {
+        const int nl = nbig;
+        float4 v[kBigPer];
+        int64_t dst[kBigPer];
+#pragma unroll
+        for (int k = 0; k < kBigPer; ++k) {
+            const int q = threadIdx.x + k * kBinThreads;
+            dst[k] = -1;
+            if (q < btot) {
+                int lo2 = 0, hi2 = nl;            // listed bin holding element q
+                while (hi2 - lo2 > 1) {
+                    const int mid = (lo2 + hi2) >> 1;
+                    if (s_bigpre[mid] <= q) lo2 = mid; else hi2 = mid;
+                }
+                const int i = s_big[lo2];
+                const int64_t bs = base + (i == 0 ? 0 : s_hist[i - 1]), be = base + s_hist[i];
+                v[k] = bin_hit[bs + (q - s_bigpre[lo2])];
+                const int key = __float_as_int(v[k].w);
+                int rank = 0;
+                for (int64_t m = bs; m < be; ++m) rank += __float_as_int(bin_hit[m].w) < key ? 1 : 0;
+                dst[k] = bs + rank;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kBigPer; ++k)
+            if (dst[k] >= 0) bin_hit[dst[k]] = v[k];
+    } else {
+        // (rare) too many large bins for the list: their owners sort in place
+        for (int i = threadIdx.x; i < nb; i += kBinThreads) {
+            const int64_t bs = base + (i == 0 ? 0 : s_hist[i - 1]), be = base + s_hist[i];
+            if (be - bs <= kBinSortReg) continue;
             for (int64_t k = bs + 1; k < be; ++k) {
                 const float4 v = bin_hit[k];
                 const int key = __float_as_int(v.w);
@@ -499,7 +626,9 @@ struct MDStage {
     float2 *md_o;
     static constexpr int kEnt = 0;
     static constexpr int kStage = 0;
+    static constexpr bool kTwoPhase = false;
     struct Rec { float4 a; float2 o; int hl, hu; };
+    struct Mid {};
 
     __device__ int64_t count(int64_t gm) const {
         int64_t e = gm / n_mod, m = gm - e * n_mod;
@@ -515,7 +644,7 @@ struct MDStage {
     template <class LDS>
     __device__ void prepare(LDS &, int64_t, int) const {}
     template <class LDS>
-    __device__ bool eval(int64_t gm, int32_t local, const int32_t *f, const LDS &, Rec &r) const {
+    __device__ bool eval(int64_t gm, int32_t local, const int32_t *f, const LDS &, Rec &r, Mid &) const {
         const int nR = f[2];
         const int l = local / nR, rr = local - l * nR;
         float4 hi = bin_hit[f[0] + l];
@@ -606,17 +735,20 @@ struct LSStage {
     int2 *ls_md;
     static constexpr int kEnt = 1536;
     static constexpr int kStage = 1;
+    static constexpr bool kTwoPhase = true;
     struct Rec { int a, b; };
+    struct Mid { int a, b; float cp; int bits; };   // bits: 1 bends positive, 2/4 direction cut on A/B
 
     __device__ int64_t count(int64_t gm) const {
         return (md_mod_off[gm + 1] - md_mod_off[gm]) * (int64_t)rsum[gm];
     }
+    // f[3]: map entries of the module (low 16 bits), bit 16: the module is an endcap module
     __device__ void info(int64_t gm, int32_t *f) const {
         int64_t e = gm / n_mod, m = gm - e * n_mod;
         f[0] = (int32_t)md_mod_off[gm];
         f[1] = rsum[gm];
         f[2] = -1;
-        f[3] = map_off[m + 1] - map_off[m];
+        f[3] = (map_off[m + 1] - map_off[m]) | (mod[m].kind != 0 ? (1 << 16) : 0);
     }
     // stage the map-entry tables of the window's non-empty modules: one entry
     // per thread, so the dependent loads of all entries overlap
@@ -624,8 +756,8 @@ struct LSStage {
     __device__ void prepare(LDS &L, int64_t alo, int nw) const {
         // thread t owns window anchors 2t and 2t+1 (nw <= 2 * kBlock)
         const int i0 = 2 * threadIdx.x, i1 = i0 + 1;
-        const int d0 = (i0 < nw && L.off[i0 + 1] > L.off[i0]) ? L.info[i0][3] : 0;
-        const int d1 = (i1 < nw && L.off[i1 + 1] > L.off[i1]) ? L.info[i1][3] : 0;
+        const int d0 = (i0 < nw && L.off[i0 + 1] > L.off[i0]) ? (L.info[i0][3] & 0xffff) : 0;
+        const int d1 = (i1 < nw && L.off[i1 + 1] > L.off[i1]) ? (L.info[i1][3] & 0xffff) : 0;
         int64_t tot;
         const int64_t inc = block_incl_scan((int64_t)(d0 + d1), &tot);
         const int base0 = (int)(inc - d0 - d1), base1 = base0 + d0;
@@ -650,26 +782,35 @@ struct LSStage {
                 const int32_t tg = map_tgt[k];
                 L.ent_rp[q] = rpref[e * n_map + k];
                 L.ent_md[q] = (int32_t)md_mod_off[e * n_mod + tg];
-                L.ent_mod[q] = tg;
+                L.ent_mod[q] = tg | (mod[tg].kind != 0 ? (1 << 30) : 0);   // bit 30: endcap
             }
         }
         __syncthreads();
     }
     template <class LDS>
-    __device__ bool eval(int64_t gm, int32_t local, const int32_t *f, const LDS &L, Rec &r) const {
+    // phase 1: decode the candidate and apply the pair cuts
+    __device__ bool eval(int64_t gm, int32_t local, const int32_t *f, const LDS &L, Rec &r, Mid &q) const {
         const int nR = f[1];
-        const int l = local / nR, rr = local - l * nR;
+        // local = l * nR + rr: quotient from the FP32 reciprocal, then made exact
+        int l = (int)((float)local * __builtin_amdgcn_rcpf((float)nR));
+        int rr = local - l * nR;
+        while (rr < 0) { --l; rr += nR; }
+        while (rr >= nR) { ++l; rr -= nR; }
         const int64_t a = f[0] + l;
+        const bool eA = (f[3] >> 16) & 1;
         int64_t b;
         int mb;
+        bool eB;
         if (f[2] >= 0) {
-            int lo = f[2], hi = f[2] + f[3];   // largest entry with ent_rp <= rr
+            int lo = f[2], hi = f[2] + (f[3] & 0xffff);   // largest entry with ent_rp <= rr
             while (hi - lo > 1) {
                 int mid = (lo + hi) >> 1;
                 if (L.ent_rp[mid] <= rr) lo = mid; else hi = mid;
             }
             b = L.ent_md[lo] + (rr - L.ent_rp[lo]);
-            mb = L.ent_mod[lo];
+            const int em = L.ent_mod[lo];
+            mb = em & 0x3fffffff;
+            eB = (em >> 30) & 1;
         } else {
             const int64_t e = gm / n_mod, m = gm - e * n_mod;
             const int32_t *rp = rpref + e * n_map;
@@ -680,16 +821,30 @@ struct LSStage {
             }
             mb = map_tgt[lo];
             b = md_mod_off[e * n_mod + mb] + (rr - rp[lo]);
+            eB = mod[mb].kind != 0;
         }
-        const int ma = (int)(gm % n_mod);
-        float4 A = md_a[a], B = md_a[b];
+        const float4 A = md_a[a], B = md_a[b];
         r.a = (int)a; r.b = (int)b;
-        bool eA = mod[ma].kind != 0, eB = mod[mb].kind != 0;
         float c, sg;
         if (!pair_pass(p, P3{A.x, A.y, A.z}, eA, P3{B.x, B.y, B.z}, eB, c, sg)) return false;
-        float cp = fminf(c, p.cmax);
-        if (!eA) { float2 o = md_o[a]; if (!md_dir_pass(p, P3{A.x, A.y, A.z}, o.x, o.y, cp, sg)) return false; }
-        if (!eB) { float2 o = md_o[b]; if (!md_dir_pass(p, P3{B.x, B.y, B.z}, o.x, o.y, cp, sg)) return false; }
+        q.a = (int)a; q.b = (int)b;
+        q.cp = fminf(c, p.cmax);
+        q.bits = (sg > 0.0f ? 1 : 0) | (eA ? 0 : 2) | (eB ? 0 : 4);
+        return true;
+    }
+    // phase 2: the MD direction cut of the barrel MDs
+    __device__ bool eval2(const Mid &q) const {
+        const float sg = (q.bits & 1) ? 1.0f : -1.0f;
+        if (q.bits & 2) {
+            const float4 A = md_a[q.a];
+            const float2 o = md_o[q.a];
+            if (!md_dir_pass(p, P3{A.x, A.y, A.z}, o.x, o.y, q.cp, sg)) return false;
+        }
+        if (q.bits & 4) {
+            const float4 B = md_a[q.b];
+            const float2 o = md_o[q.b];
+            if (!md_dir_pass(p, P3{B.x, B.y, B.z}, o.x, o.y, q.cp, sg)) return false;
+        }
         return true;
     }
     __device__ void write(int64_t pos, const Rec &r) const { ls_md[pos] = make_int2(r.a, r.b); }
@@ -713,7 +868,9 @@ struct T3Stage {
     int4 *t3_mds;
     static constexpr int kEnt = 0;
     static constexpr int kStage = 2;
+    static constexpr bool kTwoPhase = false;
     struct Rec { int li, lo, A, B, C; };
+    struct Mid {};
 
     __device__ int64_t count(int64_t l1) const {
         const int B = ls_md[l1].y;
@@ -727,7 +884,7 @@ struct T3Stage {
     template <class LDS>
     __device__ void prepare(LDS &, int64_t, int) const {}
     template <class LDS>
-    __device__ bool eval(int64_t l1, int32_t local, const int32_t *f, const LDS &, Rec &r) const {
+    __device__ bool eval(int64_t l1, int32_t local, const int32_t *f, const LDS &, Rec &r, Mid &) const {
         const int lo = f[0] + local;
         const int A = f[2], B = f[3];
         const int C = ls_md[lo].y;
@@ -767,7 +924,9 @@ struct T5PreStage {
     int2 *pre;
     static constexpr int kEnt = 0;
     static constexpr int kStage = 3;
+    static constexpr bool kTwoPhase = false;
     struct Rec { int u, v; };
+    struct Mid {};
 
     __device__ int64_t count(int64_t u) const {
         const int C = t3_mds[u].z;
@@ -781,7 +940,7 @@ struct T5PreStage {
     template <class LDS>
     __device__ void prepare(LDS &, int64_t, int) const {}
     template <class LDS>
-    __device__ bool eval(int64_t u, int32_t local, const int32_t *f, const LDS &, Rec &r) const {
+    __device__ bool eval(int64_t u, int32_t local, const int32_t *f, const LDS &, Rec &r, Mid &) const {
         const int v = f[0] + local;
         r.u = (int)u; r.v = v;
         const int E = t3_mds[v].z;
@@ -824,16 +983,19 @@ struct T5FitStage {
     float score_min;
     int2 *t5_t3;
     float *chi2_rphi, *chi2_rz;
+    float *fitf;                  // [n_t5][8]: the fit outputs of each written T5
     static constexpr int kEnt = 0;
     static constexpr int kStage = 4;
-    struct Rec { int u, v; float cr, cz; };
+    static constexpr bool kTwoPhase = false;
+    struct Rec { int u, v; float cr, cz; float fo[kNFitOut]; };
+    struct Mid {};
 
     __device__ int64_t count(int64_t) const { return 1; }
     __device__ void info(int64_t, int32_t *f) const { f[0] = f[1] = f[2] = f[3] = 0; }
     template <class LDS>
     __device__ void prepare(LDS &, int64_t, int) const {}
     template <class LDS>
-    __device__ bool eval(int64_t q, int32_t, const int32_t *, const LDS &, Rec &r) const {
+    __device__ bool eval(int64_t q, int32_t, const int32_t *, const LDS &, Rec &r, Mid &) const {
         const int2 uv = pre[q];
         r.u = uv.x; r.v = uv.y;
         T5Anchors t;
@@ -843,9 +1005,11 @@ struct T5FitStage {
         r.cr = (float)fit.chi2_rphi; r.cz = (float)fit.chi2_rz;
         if (!(fit.chi2_rz <= (double)p.chi2rz)) return false;
         if (mode == 1 && !(fit.chi2_rphi <= (double)p.chi2rphi)) return false;
+        t5_fit_outputs(t.x, t.y, fit, r.fo);
         if (kScoreCut) {
-            float ft[kNFeat];
-            t5_features(p, t.x, t.y, t.z, t.lay, t.endc, fit, ft);
+            float ff[kNFitFeat], ft[kNFeat];
+            t5_fit_features_from(p, r.fo, (double)r.cr, (double)r.cz, ff);
+            t5_features_from(p, t.x, t.y, t.z, t.lay, t.endc, ff, ft);
             if (!(score_min <= mlp_f32(mdl, ft))) return false;
         }
         return true;
@@ -854,10 +1018,14 @@ struct T5FitStage {
         t5_t3[pos] = make_int2(r.u, r.v);
         chi2_rphi[pos] = r.cr;
         chi2_rz[pos] = r.cz;
+        float4 *f4 = reinterpret_cast<float4 *>(fitf + pos * 8);
+        f4[0] = make_float4(r.fo[0], r.fo[1], r.fo[2], r.fo[3]);
+        f4[1] = make_float4(r.fo[4], r.fo[5], r.cr, r.cz);
     }
 };
 
-// T5 features and T5-DNN score, one thread per T5 (FP32 vector ALU).
+// T5 features (from the anchors and the fit features stored by the fit stage)
+// and the T5-DNN score, one thread per T5 (FP32 vector ALU).
 __global__ __launch_bounds__(kBlock) void k_t5_score_f32(T5FitStage<false> s, const int64_t *n_dev, int64_t cap,
                                                          float *score, float *feat, int do_mlp) {
     int64_t n = dev_count(n_dev, cap);
@@ -865,10 +1033,12 @@ __global__ __launch_bounds__(kBlock) void k_t5_score_f32(T5FitStage<false> s, co
         const int2 uv = s.t5_t3[i];
         T5Anchors t;
         load_t5_anchors(s.t3_mds, s.md_a, s.mod, s.n_mod, uv.x, uv.y, t);
-        Fit5 f;
-        t5_fit(s.p, t.x, t.y, t.z, t.endc, f);
-        float ft[kNFeat];
-        t5_features(s.p, t.x, t.y, t.z, t.lay, t.endc, f, ft);
+        const float4 a = reinterpret_cast<const float4 *>(s.fitf)[2 * i];
+        const float4 b = reinterpret_cast<const float4 *>(s.fitf)[2 * i + 1];
+        const float fo[kNFitOut] = {a.x, a.y, a.z, a.w, b.x, b.y};
+        float ff[kNFitFeat], ft[kNFeat];
+        t5_fit_features_from(s.p, fo, (double)b.z, (double)b.w, ff);
+        t5_features_from(s.p, t.x, t.y, t.z, t.lay, t.endc, ff, ft);
         if (feat) {
 #pragma unroll
             for (int k = 0; k < kNFeat; ++k) feat[i * kNFeat + k] = ft[k];
@@ -978,10 +1148,10 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     mark(ev, 10, st);
     run_stage(t5p, cnt + LST_COUNT_T3, w.cap_t3, w, cnt + LST_COUNT_T5PRE, w.cap_t5pre, cnt, st, nullptr, 0, a.tune);
     T5FitStage<false> t5{w.t5_pre, w.t3_mds, w.md_a, a.g.mod, a.p, a.m, n_mod, a.mode, a.score_min, o.t5_t3,
-                         o.t5_chi2_rphi, o.t5_chi2_rz};
+                         o.t5_chi2_rphi, o.t5_chi2_rz, w.t5_fitf};
     if (score_cut) {
         T5FitStage<true> t5c{w.t5_pre, w.t3_mds, w.md_a, a.g.mod, a.p, a.m, n_mod, a.mode, a.score_min, o.t5_t3,
-                             o.t5_chi2_rphi, o.t5_chi2_rz};
+                             o.t5_chi2_rphi, o.t5_chi2_rz, w.t5_fitf};
         run_stage(t5c, cnt + LST_COUNT_T5PRE, w.cap_t5pre, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, nullptr, 0, a.tune);
     } else {
         run_stage(t5, cnt + LST_COUNT_T5PRE, w.cap_t5pre, w, cnt + LST_COUNT_T5, w.cap_t5, cnt, st, nullptr, 0, a.tune);
