@@ -45,6 +45,32 @@ static inline int grid_for(int64_t n) {
     return (int)g;
 }
 
+// XCD-aware tile walk. Workgroups are dispatched round-robin over the 8
+// accelerator dies (XCDs), each with its own L2; neighbouring tiles share
+// their inputs (MDs of adjacent modules, the same event's hits), so each XCD
+// takes one contiguous range of tiles and its blocks stride through it. With
+// a grid that is not a multiple of 8 this is a plain grid-stride walk.
+constexpr int kXcds = 8;
+struct TileWalk {
+    int64_t first, end, step;
+    __device__ TileWalk(int64_t ntiles) {
+        if (gridDim.x % kXcds == 0) {
+            const int64_t x = blockIdx.x % kXcds, per = gridDim.x / kXcds;
+            const int64_t chunk = (ntiles + kXcds - 1) / kXcds;
+            const int64_t t0 = x * chunk;
+            first = t0 + blockIdx.x / kXcds;
+            end = t0 + chunk < ntiles ? t0 + chunk : ntiles;
+            step = per;
+        } else {
+            first = blockIdx.x;
+            end = ntiles;
+            step = gridDim.x;
+        }
+    }
+};
+
+static inline int round_up_xcd(int nb) { return nb < kXcds ? nb : (nb + kXcds - 1) / kXcds * kXcds; }
+
 __global__ void k_fill_i32_dev(int32_t *p, const int64_t *n_dev, int64_t cap, int32_t v) {
     int64_t n = dev_count(n_dev, cap);
     for (int64_t i = grid_tid(); i < n; i += grid_stride()) p[i] = v;
@@ -248,7 +274,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_eval(S st, const int64_t *cand
         if (total > cap_cand) atomicOr((unsigned long long *)&counts[LST_COUNT_ERR], 2ull);
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const TileWalk walk(ntiles);
+    for (int64_t tile = walk.first; tile < walk.end; tile += walk.step) {
         const int64_t alo = tile_anchor[tile];
         const int64_t ahi = (tile + 1 < ntiles) ? (int64_t)tile_anchor[tile + 1] : na - 1;
         const int nw = (int)(ahi - alo + 1 < (int64_t)kWin + 1 ? ahi - alo + 1 : (int64_t)kWin + 1);
@@ -347,7 +374,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_copy(S st, const typename S::R
     constexpr int kTileC = kBlock * kPer;
     const int64_t ntiles = *ntiles_dev;
     if (blockIdx.x == 0 && threadIdx.x == 0) *out_count = tile_pre[ntiles];
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const TileWalk walk(ntiles);
+    for (int64_t tile = walk.first; tile < walk.end; tile += walk.step) {
         const int n = tile_cnt[tile];
         const int64_t base = tile_pre[tile];
         const typename S::Rec *slot = scratch + tile * kTileC;
@@ -378,6 +406,7 @@ static void run_stage_p(const S &s, const int64_t *n_dev, int64_t n_cap, const W
     scan(StageCount<S>{s}, n_dev, n_cap, w, w.cand_off, w.tile_anchor, st, tile);
     int nb = (int)(w.max_tiles < eval_blocks ? w.max_tiles : eval_blocks);
     if (nb < 1) nb = 1;
+    nb = round_up_xcd(nb);
     typename S::Rec *scratch = (typename S::Rec *)w.rec_scratch;
     mark(ev, 2 * win, st);
     hipLaunchKernelGGL((k_stage_eval<S, kPer>), dim3(nb), dim3(kBlock), 0, st, s, w.cand_off, n_dev, n_cap,
@@ -424,15 +453,26 @@ __device__ __forceinline__ void cswap_key(float4 &a, float4 &b) {
 
 __global__ __launch_bounds__(kBinThreads) void k_bin_event(const float *x, const float *y, const float *z,
                                                            const int32_t *sensor, const int64_t *ev_off,
-                                                           int n_ev, int n_sens, int split, int64_t *bin_off,
-                                                           float4 *bin_hit, int64_t *counts) {
+                                                           int n_ev, int n_sens, int split, int xcd_map,
+                                                           int64_t *bin_off, float4 *bin_hit, int64_t *counts) {
     extern __shared__ int32_t s_hist[];          // [range + 1]
     __shared__ int64_t s_red[kBinThreads / 64];
     __shared__ int64_t s_base;
     __shared__ int32_t s_big[kBigBins];
     __shared__ int32_t s_bigpre[kBigBins + 1];
     __shared__ int s_nbig;
-    const int e = blockIdx.x / split, r = blockIdx.x - e * split;
+    // block -> (event, sensor range); with xcd_map all ranges of an event run
+    // on one XCD (blocks b with equal b % 8), so its hits are fetched into one L2
+    int e, r;
+    if (xcd_map) {
+        const int x = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
+        e = (k / split) * kXcds + x;
+        r = k % split;
+        if (e >= n_ev) return;
+    } else {
+        e = blockIdx.x / split;
+        r = blockIdx.x - e * split;
+    }
     const int range = (n_sens + split - 1) / split;
     // ranges past the last sensor are empty (nb = 0), never negative
     const int lo = r * range < n_sens ? r * range : n_sens;
@@ -1114,8 +1154,10 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
         int split = a.tune.bin_split;
         while ((int64_t)((n_sens + split - 1) / split + 1) * 4 > kBinLdsMax) ++split;
         const int range = (n_sens + split - 1) / split;
-        hipLaunchKernelGGL(k_bin_event, dim3(a.n_ev * split), dim3(kBinThreads), (size_t)(range + 1) * 4, st,
-                           a.x, a.y, a.z, a.sensor, a.ev_off, a.n_ev, n_sens, split, w.bin_off, w.bin_hit, cnt);
+        const int xcd_map = a.n_ev >= kXcds ? 1 : 0;
+        const int grid = xcd_map ? (a.n_ev + kXcds - 1) / kXcds * kXcds * split : a.n_ev * split;
+        hipLaunchKernelGGL(k_bin_event, dim3(grid), dim3(kBinThreads), (size_t)(range + 1) * 4, st, a.x, a.y, a.z,
+                           a.sensor, a.ev_off, a.n_ev, n_sens, split, xcd_map, w.bin_off, w.bin_hit, cnt);
     }
     mark(ev, 3, st);
 
