@@ -469,8 +469,9 @@ static size_t gnn_layout(int64_t n_nodes, int64_t n_edges, char *base, GnnWork *
     };
     char *h0 = take((size_t)n_nodes * 64 * 4), *h1 = take((size_t)n_nodes * 64 * 4);
     char *e1 = take((size_t)n_edges * 64 * 4), *io = take((size_t)(n_nodes + 1) * 8), *er = take(8);
+    char *mg = take((size_t)n_nodes * 64 * 4);
     if (w) {
-        w->h0 = (float *)h0; w->h1 = (float *)h1; w->e1 = (float *)e1;
+        w->h0 = (float *)h0; w->h1 = (float *)h1; w->e1 = (float *)e1; w->msg = (float *)mg;
         w->in_off = (int64_t *)io; w->err = (int64_t *)er;
     }
     return off;

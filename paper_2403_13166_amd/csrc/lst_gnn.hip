@@ -19,9 +19,9 @@
 // A-operand fragment order (one 16-byte fragment per lane per (m block, K
 // chunk)) and staged in LDS once per block.
 //
-// Four kernels: encode; edge init fused with the step-0 edge update; step-0
-// node update (incoming sums over the dst-sorted edge list, no atomics);
-// step-1 edge update fused with the head. The step-1 node update is not
+// Five kernels: encode; edge init fused with the step-0 edge update;
+// incoming sums over the dst-sorted edge list (no atomics, edge order);
+// step-0 node update; step-1 edge update fused with the head. The step-1 node update is not
 // computed: no output depends on it.
 #include <hip/hip_runtime.h>
 
@@ -237,9 +237,35 @@ __global__ __launch_bounds__(kGnnThreads) void k_gnn_edge_first(GnnDev m, const 
 
 // ------------------------------------------------- step-0 node update
 
+// m[v] = sum of the states of the edges entering v, in edge order (dst-sorted
+// list); one thread per (node, 4-unit slice), so the per-node loops of many
+// nodes are in flight at once
+__global__ __launch_bounds__(256) void k_gnn_msum(const float *e, const int64_t *in_off, int64_t n_nodes, float *m) {
+    const int64_t n = n_nodes * 16;
+    for (int64_t t = g_tid(); t < n; t += g_stride()) {
+        const int64_t v = t >> 4;
+        const int q = (int)(t & 15);
+        const int64_t j0 = in_off[v], j1 = in_off[v + 1];
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        int64_t j = j0;
+        // four rows in flight, summed in edge order
+        for (; j + 4 <= j1; j += 4) {
+            float4 x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = reinterpret_cast<const float4 *>(e + (j + u) * 64)[q];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { acc.x += x[u].x; acc.y += x[u].y; acc.z += x[u].z; acc.w += x[u].w; }
+        }
+        for (; j < j1; ++j) {
+            const float4 x = reinterpret_cast<const float4 *>(e + j * 64)[q];
+            acc.x += x.x; acc.y += x.y; acc.z += x.z; acc.w += x.w;
+        }
+        reinterpret_cast<float4 *>(m + v * 64)[q] = acc;
+    }
+}
+
 __global__ __launch_bounds__(kGnnThreads) void k_gnn_node(GnnDev m, int lay_a, int lay_b, const float *h,
-                                                          const float *e, const int64_t *in_off, int64_t n_nodes,
-                                                          float *h_out) {
+                                                          const float *msg, int64_t n_nodes, float *h_out) {
     __shared__ uint4 Lfa[4 * 4 * 64], Lfb[4 * 2 * 64];
     __shared__ float Lba[64], Lbb[64];
     stage(Lfa, m.frag + m.foff[lay_a], 4 * 4 * 64, Lba, m.bias + m.boff[lay_a], 64);
@@ -255,18 +281,8 @@ __global__ __launch_bounds__(kGnnThreads) void k_gnn_node(GnnDev m, int lay_a, i
             const int64_t v = base + nb * 16 + c;
             const bool ok = v < n_nodes;
             load_row(h + v * 64, g, ok, Rh[nb]);
-            float M[4][4] = {};
-            if (ok) {
-                const int64_t j0 = in_off[v], j1 = in_off[v + 1];
-                for (int64_t j = j0; j < j1; ++j) {
-                    float E[4][4];
-                    load_row(e + j * 64, g, true, E);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) M[q][t] += E[q][t];
-                }
-            }
+            float M[4][4];
+            load_row(msg + v * 64, g, ok, M);
             r_to_b(Rh[nb], &Bin[0][0], nb);
             r_to_b(M, &Bin[2][0], nb);
         }
@@ -384,9 +400,13 @@ hipError_t run_gnn(const GnnDev &m, const float *x, int64_t n_nodes, const int32
     if (n_edges == 0) return hipGetLastError();
     hipLaunchKernelGGL(k_gnn_edge_first, dim3(gnn_blocks(n_edges)), dim3(kGnnThreads), 0, st, m, (const float *)w.h0,
                        src, dst, n_nodes, n_edges, w.e1);
+    {
+        int64_t mb = (n_nodes * 16 + 255) / 256;
+        hipLaunchKernelGGL(k_gnn_msum, dim3((int)(mb < 16384 ? mb : 16384)), dim3(256), 0, st, (const float *)w.e1,
+                           (const int64_t *)w.in_off, n_nodes, w.msg);
+    }
     hipLaunchKernelGGL(k_gnn_node, dim3(gnn_blocks(n_nodes)), dim3(kGnnThreads), 0, st, m, (int)kGNodeA0,
-                       (int)kGNodeB0, (const float *)w.h0, (const float *)w.e1, (const int64_t *)w.in_off, n_nodes,
-                       w.h1);
+                       (int)kGNodeB0, (const float *)w.h0, (const float *)w.msg, n_nodes, w.h1);
     hipLaunchKernelGGL(k_gnn_edge_last, dim3(gnn_blocks(n_edges)), dim3(kGnnThreads), 0, st, m, (const float *)w.h1,
                        (const float *)w.e1, src, dst, n_nodes, n_edges, score);
     return hipGetLastError();

@@ -117,6 +117,7 @@ struct GnnDev {
 struct GnnWork {
     float *h0, *h1;                   // [n_nodes][64] node states
     float *e1;                        // [n_edges][64] edge states after step 0
+    float *msg;                       // [n_nodes][64] sums of the incoming edge states
     int64_t *in_off;                  // [n_nodes + 1] incoming-edge ranges
     int64_t *err;                     // [1] bit 0: invalid graph
 };

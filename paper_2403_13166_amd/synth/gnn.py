@@ -87,9 +87,9 @@ def make_graph(n_nodes: int = 200_000, n_edges: int = 1_000_000, n_layers: int =
                seed=(3, 3)) -> Graph:
     """LST-like graph: nodes in n_layers equal "layers" (segments by layer),
     edges only between consecutive layers (triplets chain segments outward);
-    an edge's target lies within +-window of the source's aligned index in the
-    next layer (the locality of detector neighbours). Features ~ N(0, 1).
-    Edges are sorted by (dst, src)."""
+    an edge's target is uniform within +-window of the source's aligned index
+    in the next layer, restricted to that layer (the locality of detector
+    neighbours). Features ~ N(0, 1). Edges are sorted by (dst, src)."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(list(seed))))
     per = n_nodes // n_layers
     n_nodes = per * n_layers
@@ -97,7 +97,13 @@ def make_graph(n_nodes: int = 200_000, n_edges: int = 1_000_000, n_layers: int =
     pairs = n_layers - 1
     lay = rng.integers(0, pairs, size=n_edges)
     s_loc = rng.integers(0, per, size=n_edges)
-    d_loc = np.clip(s_loc + rng.integers(-window, window + 1, size=n_edges), 0, per - 1)
+    # target uniform over the part of [s - window, s + window] inside the layer
+    # (drawing there instead of clipping keeps the layer's edge nodes from
+    # collecting every overflow: in-degrees stay Poisson-like)
+    lo = np.maximum(s_loc - window, 0)
+    hi = np.minimum(s_loc + window, per - 1)
+    d_loc = lo + (rng.random(n_edges) * (hi - lo + 1)).astype(np.int64)
+    d_loc = np.minimum(d_loc, hi)
     src = (lay * per + s_loc).astype(np.int64)
     dst = ((lay + 1) * per + d_loc).astype(np.int64)
     order = np.lexsort((src, dst))
