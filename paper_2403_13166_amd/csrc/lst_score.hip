@@ -1,7 +1,8 @@
 // T5-DNN scoring (paper Sec. 2: 42 inputs -> 32 -> 32 -> 1, ReLU hidden
 // layers, sigmoid output) over dense feature rows.
 //
-// BF16 path: one wavefront scores 64 rows per step on the matrix cores with
+// BF16 path: a block stages a tile of 256 contiguous rows in LDS with 16-byte
+// coalesced loads; one wavefront then scores 64 of them on the matrix cores with
 // v_mfma_f32_16x16x32_bf16, computing the transposed products
 //   H1^T [32 x 64] = W1 [32 x 64(K, 42 padded)] . Xs^T [64 x 64]
 //   H2^T [32 x 64] = W2 [32 x 32]               . relu(H1^T)
@@ -51,10 +52,43 @@ __global__ __launch_bounds__(256) void k_score_f32(ModelDev m, const void *X, co
 // Hidden unit carried by B-operand slot i of lane group g in layer 2.
 __device__ __forceinline__ int perm_unit(int g, int i) { return i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4); }
 
+constexpr int kScoreTile = 256;   // rows per block tile (4 wavefronts x 64 rows)
+
+// One block tile of rows is a contiguous chunk of X (256 x 42 features); the
+// block copies it to LDS with 16-byte coalesced loads (converting BF16 input
+// to FP32), then every wavefront builds its MFMA operands from LDS.
+template <int DT>
+__device__ __forceinline__ void stage_rows(float *sx, const void *X, int64_t row0, int nrows) {
+    const int nel = nrows * kNFeat;
+    if (DT == 0) {
+        const float *src = (const float *)X + row0 * kNFeat;
+        const bool vec = ((uintptr_t)src & 15) == 0;
+        const int n4 = vec ? nel / 4 : 0;
+        for (int i = threadIdx.x; i < n4; i += 256)
+            reinterpret_cast<float4 *>(sx)[i] = reinterpret_cast<const float4 *>(src)[i];
+        for (int i = 4 * n4 + threadIdx.x; i < nel; i += 256) sx[i] = src[i];
+    } else {
+        const uint16_t *src = (const uint16_t *)X + row0 * kNFeat;
+        const bool vec = ((uintptr_t)src & 15) == 0;
+        const int n8 = vec ? nel / 8 : 0;
+        for (int i = threadIdx.x; i < n8; i += 256) {
+            const uint4 u = reinterpret_cast<const uint4 *>(src)[i];
+            const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                sx[8 * i + 2 * k] = __uint_as_float(w[k] << 16);
+                sx[8 * i + 2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+            }
+        }
+        for (int i = 8 * n8 + threadIdx.x; i < nel; i += 256) sx[i] = bf16_to_f32(src[i]);
+    }
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_score_mfma(ModelDev m, const void *X, const int64_t *n_dev,
                                                     int64_t n_cap, float *out) {
-    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+    __shared__ float sx[kScoreTile * kNFeat];
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, wv = threadIdx.x >> 6;
     const int64_t n = n_dev ? (*n_dev < n_cap ? *n_dev : n_cap) : n_cap;
     // weights as A operands (kept in registers for the whole kernel)
     bf16x8 w1[2][2], w2[2];
@@ -90,8 +124,12 @@ __global__ __launch_bounds__(256) void k_score_mfma(ModelDev m, const void *X, c
             b2v[mb][j] = m.b2[mb * 16 + 4 * g + j];
             w3v[mb][j] = m.w3[mb * 16 + 4 * g + j];
         }
-    const int64_t wave = gtid() >> 6, nwaves = gstride() >> 6;
-    for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+    for (int64_t row0 = (int64_t)blockIdx.x * kScoreTile; row0 < n; row0 += (int64_t)gridDim.x * kScoreTile) {
+        const int nrows = n - row0 < kScoreTile ? (int)(n - row0) : kScoreTile;
+        __syncthreads();                                   // the previous tile is consumed
+        stage_rows<DT>(sx, X, row0, nrows);
+        __syncthreads();
+        const int base = wv * 64;                          // this wavefront's rows in the tile
         f32x4 acc1[2][4];
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
@@ -99,15 +137,15 @@ __global__ __launch_bounds__(256) void k_score_mfma(ModelDev m, const void *X, c
             for (int nb = 0; nb < 4; ++nb) acc1[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
-            const int64_t row = base + nb * 16 + c;
-            const bool ok = row < n;
+            const int r = base + nb * 16 + c;
+            const bool ok = r < nrows;
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
                 bf16x8 xb;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     int k = ks * 32 + 8 * g + i;
-                    float v = (ok && k < kNFeat) ? (load_x<DT>(X, row * kNFeat + k) - mu[ks][i]) * isd[ks][i] : 0.0f;
+                    float v = (ok && k < kNFeat) ? (sx[r * kNFeat + k] - mu[ks][i]) * isd[ks][i] : 0.0f;
                     xb[i] = (__bf16)v;
                 }
 #pragma unroll
@@ -132,8 +170,8 @@ __global__ __launch_bounds__(256) void k_score_mfma(ModelDev m, const void *X, c
             }
             part += __shfl_xor(part, 16, 64);
             part += __shfl_xor(part, 32, 64);
-            const int64_t row = base + nb * 16 + c;
-            if (g == 0 && row < n) out[row] = 1.0f / (1.0f + expf(-(part + m.b3)));
+            const int r = base + nb * 16 + c;
+            if (g == 0 && r < nrows) out[row0 + r] = 1.0f / (1.0f + expf(-(part + m.b3)));
         }
     }
 }
@@ -141,7 +179,7 @@ __global__ __launch_bounds__(256) void k_score_mfma(ModelDev m, const void *X, c
 static inline int blocks_for(int64_t n, int rows_per_block) {
     int64_t b = (n + rows_per_block - 1) / rows_per_block;
     if (b < 1) b = 1;
-    if (b > 4096) b = 4096;
+    if (b > 2048) b = 2048;
     return (int)b;
 }
 
