@@ -118,7 +118,7 @@ void lst_destroy(lst_ctx *ctx);
  * two sensors each, Sec. 1 pT-modules), the module map that defines which
  * module pairs are "adjacent" for line segments (Sec. 1), and the selection
  * parameters. Per-module FP32 thresholds are derived here from the FP64
- * parameters. LST_E_INVAL on a malformed blob. */
+ * parameters. LST_E_INVAL on a malformed blob or more than 524288 modules. */
 lst_status lst_load_geometry(lst_ctx *ctx, const void *blob, size_t nbytes);
 
 /* Load the T5-DNN ("LSTM" blob v1, host memory, copied): 42 -> 32 -> 32 -> 1
@@ -200,9 +200,9 @@ lst_status lst_gnn_score(lst_ctx *ctx, const float *x_dev, int64_t n_nodes, cons
 /* Launch shapes of the build kernels. They never change results: every stage
  * writes its objects in candidate order whatever the tiling, so a tuning only
  * changes speed (the autotuner in the Python package times them).
- *   bin_split    blocks per event in hit binning, each histogramming one range
- *                of sensor ids in LDS (1..64; raised at launch until one
- *                range's histogram fits in 64 KiB of LDS);
+ *   bin_split    sensor-id ranges per event in hit binning, each sorted by one
+ *                block in LDS (1..64; raised at launch to the number of ranges
+ *                of at most 1024 sensor ids that cover the geometry);
  *   tile_per[s]  candidates per thread of a 256-thread compaction tile, for
  *                stage s = 0 MD {2,4,8}, 1 LS {2,4,8}, 2 T3 {1,2,4},
  *                3 T5 FP32 pre-cuts {1,2,4}, 4 T5 FP64 fits {1,2};

@@ -1,8 +1,8 @@
 """Autotuner of the build's launch shapes on the current GPU and workload.
 
 Knobs (all exposed through lst_set_tuning; none changes a result):
-  * bin_split: blocks per event in hit binning, i.e. the sensor-id range
-    each block histograms in LDS (the module-bin size);
+  * bin_split: sensor-id ranges per event in hit binning, each sorted by one
+    block in LDS (the module-bin size);
   * tile_per[s]: candidates per thread of each stage's 256-thread compaction
     tile (the LDS tile: the tile's anchor window and, for line segments, its
     module-map entries are staged in LDS);
@@ -20,7 +20,7 @@ import statistics
 
 from . import binding as B
 
-BIN_SPLITS = (1, 2, 4, 8, 16, 32)
+BIN_SPLITS = (1, 48, 64)      # sensor ranges per event (raised to what the geometry needs)
 EVAL_BLOCKS = (1024, 2048, 4096, 8192)
 # (knob, stage index or None, choices, timing window)
 KNOBS = (
@@ -73,7 +73,7 @@ def autotune(builder, run, sync, reps: int = 5, log=None) -> tuple[dict, list]:
     for knob, idx, choices, window in KNOBS:
         cur = best[knob] if idx is None else best[knob][idx]
         res = {}
-        for v in choices:
+        for v in sorted(set(choices) | {cur}):
             res[v] = measure(_with(best, knob, idx, v), window)
         pick = min(res, key=res.get)
         if res[pick] < res[cur] * 0.98:       # move only on a clear gain

@@ -127,6 +127,9 @@ lst_status lst_load_geometry(lst_ctx *c, const void *blob, size_t nbytes) {
     size_t need = 152 + (size_t)nm * 64 + ((size_t)nm + 1) * 4 + (size_t)nmap * 4;
     if (nbytes != need || nm == 0 || nm > (1u << 24))
         return fail(c, LST_E_INVAL, "geometry blob: size %zu, expected %zu", nbytes, need);
+    // hit binning sorts at most kBinRangesMax ranges of 1024 sensors per event
+    if (2 * (uint64_t)nm > 1024ull * kBinRangesMax)
+        return fail(c, LST_E_INVAL, "geometry blob: %u modules, at most %d supported", nm, 512 * kBinRangesMax);
     double prm[16];
     memcpy(prm, b + 24, sizeof(prm));
     // parameters: k_b, pt_min, z_lum, n_sigma, sigma_rphi, sigma_z, sigma_r, gap,
@@ -242,8 +245,19 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     Work x{};
     x.cap_hits = k->hits; x.cap_ev = ev; x.cap_md = md; x.cap_ls = k->ls; x.cap_t3 = k->t3;
     x.cap_t5 = k->t5; x.cap_cand = k->cand; x.max_tiles = max_tiles; x.n_anchor_cap = anchors;
+    const int64_t hits = k->hits > 0 ? k->hits : 1;
     x.bin_off = (int64_t *)take(8 * (ev * nsens + 1));
-    x.bin_hit = (float4 *)take(16 * (k->hits > 0 ? k->hits : 1));
+    x.bin_hit = (float4 *)take(16 * hits);
+    // coarse binning tiles: every event adds at most one partial tile
+    x.max_bin_tiles = hits / kBinTileHits + ev + 1;
+    x.max_bin_entries = x.max_bin_tiles * kBinRangesMax;
+    x.bin_tbase = (int64_t *)take(8 * (ev + 1));
+    x.bin_nent = (int64_t *)take(8);
+    x.bin_cnt = (int32_t *)take(4 * x.max_bin_entries);
+    x.bin_cpos = (int64_t *)take(8 * (x.max_bin_entries + 1));
+    x.bin_tmp = (float4 *)take(16 * hits);
+    x.bin_tsens = (int32_t *)take(4 * hits);
+    x.bin_gpos = (int32_t *)take(4 * hits);
     x.cand_off = (int64_t *)take(8 * (anchors + 1));
     x.scan_part = (int64_t *)take(8 * (kScanBlocks + 1));
     x.tile_anchor = (int32_t *)take(4 * (max_tiles + 1));

@@ -15,7 +15,8 @@ constexpr int kScanBlocks = 1024;
 constexpr int kEvalBlocks = 4096;     // persistent compaction blocks (256 CUs x 16)
 constexpr int kMaxStride = 8192;      // grid cap of grid-stride kernels
 constexpr int kMaxRecBytes = 48;      // largest per-candidate record a stage compacts
-constexpr int kBinLdsMax = 65536;     // LDS bytes of one binning block's histogram, at most
+constexpr int kBinRangesMax = 1024;   // sensor ranges per event in hit binning, at most
+constexpr int kBinTileHits = 4096;     // hits of one binning tile
 
 // Launch shapes (never change results: outputs are in candidate order for any
 // tiling). Stage order: MD, LS, T3, T5 pre-cuts, T5 fit.
@@ -46,6 +47,14 @@ struct Work {
     // hits binned by (event, sensor)
     int64_t *bin_off;                 // [cap_ev * n_sens + 1]
     float4 *bin_hit;                  // [cap_hits] x, y, z, input index (bits)
+    int64_t max_bin_tiles, max_bin_entries;
+    int64_t *bin_tbase;               // [cap_ev + 1] first coarse tile of each event
+    int64_t *bin_nent;                // [1] coarse (event, range, tile) entries
+    int32_t *bin_cnt;                 // [max_bin_entries] hits per entry
+    int64_t *bin_cpos;                // [max_bin_entries + 1] their exclusive scan
+    float4 *bin_tmp;                  // [cap_hits] hits partitioned by (event, range)
+    int32_t *bin_tsens;               // [cap_hits] their sensor ids
+    int32_t *bin_gpos;                // [cap_hits] local positions of ranges too large for LDS
     // per-stage scratch
     int64_t *cand_off;                // [n_anchor_cap + 1]
     int64_t *scan_part;               // [kScanBlocks + 1]

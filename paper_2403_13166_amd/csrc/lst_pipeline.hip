@@ -432,223 +432,230 @@ static void run_stage(const S &s, const int64_t *n_dev, int64_t n_cap, const Wor
 }
 
 // ------------------------------------------------------------- binning
-// Counting sort of the hits by (event, sensor) without device-wide atomics:
-// block (e, r) owns sensor range r of event e. It histograms its range with
-// LDS atomics while counting the event's hits on lower sensors (its base),
-// scans the histogram in LDS, writes the bin offsets, scatters its hits with
-// LDS cursors and finally orders each of its (small) bins by input index, so
-// the binned layout is deterministic. Hits with an out-of-range sensor id set
-// error bit 0 and are dropped. Every pass over the event's hits keeps kBinU
-// independent loads in flight per thread (the passes are latency bound).
+// Hits are sorted by (event, sensor), and by input index within a sensor, in
+// two deterministic passes without device-wide atomics.
+//  * Coarse pass: each event's hits are cut into tiles of kBinTile; a tile
+//    counts its hits per sensor range (ranges of at most kFineRange sensor
+//    ids); an exclusive scan over (event, range, tile) gives every tile's
+//    output base per range; the tile then scatters its hits, ranked within
+//    the tile by wavefront ballots, so each range keeps the input order.
+//  * Fine pass: one block per (event, range) sorts that range's hits by
+//    sensor in LDS (histogram, scan, scatter of 16-bit local positions, then
+//    each bin is put back in local-position order, which is input order) and
+//    writes the bin offsets and the binned hits with coalesced stores. A range
+//    with more hits than LDS holds is done the same way through global memory.
+// Hits with an out-of-range sensor id set error bit 0 and are dropped.
 
-constexpr int kBinThreads = 1024;
-constexpr int kBinU = 8;          // hits per thread per round
-constexpr int kBinSortReg = 8;    // bins up to this size are ordered in registers
-constexpr int kBigBins = 1024;    // larger bins one block ranks in parallel, at most
-constexpr int kBigPer = 8;        // their elements per thread, at most
+constexpr int kBinTile = kBinTileHits;  // hits of one coarse tile
+constexpr int kBinThreads = 256;
+constexpr int kFineRange = 1024;        // sensor ids of one range, at most
+constexpr int kMaxRanges = kBinRangesMax;
+constexpr int kFineCap = 24576;         // hits one block orders in LDS
 
-__device__ __forceinline__ void cswap_key(float4 &a, float4 &b) {
-    if (__float_as_int(a.w) > __float_as_int(b.w)) { const float4 t = a; a = b; b = t; }
+// q = v / d for 0 <= v < 2^24, d >= 1: FP32 reciprocal estimate, made exact
+__device__ __forceinline__ int div_small(int v, int d, float inv) {
+    int q = (int)((float)v * inv);
+    int r = v - q * d;
+    while (r < 0) { --q; r += d; }
+    while (r >= d) { ++q; r -= d; }
+    return q;
 }
 
-__global__ __launch_bounds__(kBinThreads) void k_bin_event(const float *x, const float *y, const float *z,
-                                                           const int32_t *sensor, const int64_t *ev_off,
-                                                           int n_ev, int n_sens, int split, int xcd_map,
-                                                           int64_t *bin_off, float4 *bin_hit, int64_t *counts) {
-    extern __shared__ int32_t s_hist[];          // [range + 1]
-    __shared__ int64_t s_red[kBinThreads / 64];
-    __shared__ int64_t s_base;
-    __shared__ int32_t s_big[kBigBins];
-    __shared__ int32_t s_bigpre[kBigBins + 1];
-    __shared__ int s_nbig;
-    // block -> (event, sensor range); with xcd_map all ranges of an event run
-    // on one XCD (blocks b with equal b % 8), so its hits are fetched into one L2
+// tbase[e] = first coarse tile of event e; tbase[n_ev] = all tiles; *nent = tiles * nr
+__global__ __launch_bounds__(1024) void k_bin_tiles(const int64_t *ev_off, int n_ev, int nr, int64_t *tbase,
+                                                    int64_t *nent) {
+    __shared__ int64_t s_w[16];
+    __shared__ int64_t s_carry;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n_ev; base += 1024) {
+        const int e = base + threadIdx.x;
+        const int64_t v = e < n_ev ? (ev_off[e + 1] - ev_off[e] + kBinTile - 1) / kBinTile : 0;
+        const int64_t inc = wave_incl_scan(v);
+        if (lane == 63) s_w[wv] = inc;
+        __syncthreads();
+        int64_t off = 0, all = 0;
+        for (int k = 0; k < 16; ++k) { if (k < wv) off += s_w[k]; all += s_w[k]; }
+        if (e < n_ev) tbase[e] = s_carry + off + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry += all;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        tbase[n_ev] = s_carry;
+        *nent = s_carry * nr;
+    }
+}
+
+// block -> (event, tile of that event); false past the last tile
+__device__ __forceinline__ bool bin_tile_of(const int64_t *tbase, int n_ev, int &e, int64_t &t, int64_t &nt) {
+    const int64_t b = blockIdx.x;
+    if (b >= tbase[n_ev]) return false;
+    int lo = 0, hi = n_ev;                       // largest e with tbase[e] <= b
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tbase[mid] <= b) lo = mid; else hi = mid;
+    }
+    e = lo;
+    t = b - tbase[e];
+    nt = tbase[e + 1] - tbase[e];
+    return true;
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_count(const int32_t *sensor, const int64_t *ev_off, int n_ev,
+                                                           int n_sens, int nr, int rw, const int64_t *tbase,
+                                                           int32_t *cnt, int64_t *counts) {
+    __shared__ int32_t s_c[kMaxRanges];
+    int e;
+    int64_t t, nt;
+    if (!bin_tile_of(tbase, n_ev, e, t, nt)) return;
+    const int64_t h0 = ev_off[e] + t * kBinTile;
+    const int64_t h1 = h0 + kBinTile < ev_off[e + 1] ? h0 + kBinTile : ev_off[e + 1];
+    for (int r = threadIdx.x; r < nr; r += kBinThreads) s_c[r] = 0;
+    __syncthreads();
+    const float inv = 1.0f / (float)rw;
+    bool bad = false;
+    for (int64_t h = h0 + threadIdx.x; h < h1; h += kBinThreads) {
+        const int v = sensor[h];
+        if (v < 0 || v >= n_sens) { bad = true; continue; }
+        atomicAdd(&s_c[div_small(v, rw, inv)], 1);
+    }
+    if (bad) atomicOr((unsigned long long *)&counts[LST_COUNT_ERR], 1ull);
+    __syncthreads();
+    const int64_t base = tbase[e] * nr + t;
+    for (int r = threadIdx.x; r < nr; r += kBinThreads) cnt[base + (int64_t)r * nt] = s_c[r];
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const float *x, const float *y, const float *z,
+                                                             const int32_t *sensor, const int64_t *ev_off, int n_ev,
+                                                             int n_sens, int nr, int rw, const int64_t *tbase,
+                                                             const int64_t *cpos, float4 *tmp, int32_t *tsens) {
+    constexpr int kWaves = kBinThreads / 64;
+    __shared__ int64_t s_base[kMaxRanges];
+    __shared__ int32_t s_wc[kWaves][kMaxRanges];
+    int e;
+    int64_t t, nt;
+    if (!bin_tile_of(tbase, n_ev, e, t, nt)) return;
+    const int64_t h0 = ev_off[e] + t * kBinTile;
+    const int64_t h1 = h0 + kBinTile < ev_off[e + 1] ? h0 + kBinTile : ev_off[e + 1];
+    const int64_t ebase = tbase[e] * nr + t;
+    for (int r = threadIdx.x; r < nr; r += kBinThreads) s_base[r] = cpos[ebase + (int64_t)r * nt];
+    const float inv = 1.0f / (float)rw;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t hb = h0; hb < h1; hb += kBinThreads) {
+        const int64_t h = hb + threadIdx.x;
+        int d = -1, v = 0;
+        float4 hv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (h < h1) {
+            v = sensor[h];
+            if (v >= 0 && v < n_sens) {
+                d = div_small(v, rw, inv);
+                hv = make_float4(x[h], y[h], z[h], __int_as_float((int)h));
+            }
+        }
+        // rank among this wavefront's hits of the same range, and the
+        // wavefront's count per range
+        int rank = 0;
+        for (int dd = 0; dd < nr; ++dd) {
+            const unsigned long long m = __ballot(d == dd);
+            if (lane == 0) s_wc[wv][dd] = __popcll(m);
+            if (d == dd) rank = __popcll(m & ((1ull << lane) - 1ull));
+        }
+        __syncthreads();
+        if (d >= 0) {
+            int64_t pos = s_base[d] + rank;
+            for (int w = 0; w < wv; ++w) pos += s_wc[w][d];
+            tmp[pos] = hv;
+            tsens[pos] = v;
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < nr; r += kBinThreads) {
+            int sum = 0;
+            for (int w = 0; w < kWaves; ++w) sum += s_wc[w][r];
+            s_base[r] += sum;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_fine(const float4 *tmp, const int32_t *tsens, const int64_t *tbase,
+                                                          const int64_t *cpos, const int64_t *nent, int n_ev, int n_sens,
+                                                          int nr, int rw, int xcd_map, int64_t *bin_off, float4 *bin_hit,
+                                                          int32_t *gpos) {
+    __shared__ int32_t s_h[kFineRange + 1];
+    __shared__ uint16_t s_pos[kFineCap];
+    __shared__ int64_t s_w[kBinThreads / 64];
     int e, r;
     if (xcd_map) {
-        const int x = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
-        e = (k / split) * kXcds + x;
-        r = k % split;
+        const int xx = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
+        e = (k / nr) * kXcds + xx;
+        r = k % nr;
         if (e >= n_ev) return;
     } else {
-        e = blockIdx.x / split;
-        r = blockIdx.x - e * split;
+        e = blockIdx.x / nr;
+        r = blockIdx.x - e * nr;
     }
-    const int range = (n_sens + split - 1) / split;
-    // ranges past the last sensor are empty (nb = 0), never negative
-    const int lo = r * range < n_sens ? r * range : n_sens;
-    const int hi = lo + range < n_sens ? lo + range : n_sens;
+    const int64_t nt = tbase[e + 1] - tbase[e];
+    const int64_t cs = cpos[tbase[e] * nr + (int64_t)r * nt], ce = cpos[tbase[e] * nr + (int64_t)(r + 1) * nt];
+    const int cnt = (int)(ce - cs);
+    const int lo = r * rw < n_sens ? r * rw : n_sens;
+    const int hi = lo + rw < n_sens ? lo + rw : n_sens;
     const int nb = hi - lo;
-    const int64_t h0 = ev_off[e], h1 = ev_off[e + 1];
-    constexpr int64_t kRound = (int64_t)kBinThreads * kBinU;
-    for (int i = threadIdx.x; i <= nb; i += kBinThreads) s_hist[i] = 0;
+    for (int i = threadIdx.x; i <= nb; i += kBinThreads) s_h[i] = 0;
     __syncthreads();
-    int64_t below = 0;
-    bool bad = false;
-    for (int64_t hb = h0 + threadIdx.x; hb < h1; hb += kRound) {
-        int sv[kBinU];
-#pragma unroll
-        for (int u = 0; u < kBinU; ++u) {
-            const int64_t h = hb + (int64_t)u * kBinThreads;
-            sv[u] = h < h1 ? sensor[h] : lo - 1;
-        }
-#pragma unroll
-        for (int u = 0; u < kBinU; ++u) {
-            const int64_t h = hb + (int64_t)u * kBinThreads;
-            if (h >= h1) continue;
-            const int v = sv[u];
-            if (v < 0 || v >= n_sens) { bad = true; continue; }
-            if (v < lo) ++below;
-            else if (v < hi) atomicAdd(&s_hist[v - lo], 1);
-        }
-    }
-    if (bad && r == 0) atomicOr((unsigned long long *)&counts[LST_COUNT_ERR], 1ull);
-    // block reduction of `below`
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) below += __shfl_xor(below, d, 64);
-    if (lane == 0) s_red[wv] = below;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t b = 0;
-        for (int k = 0; k < kBinThreads / 64; ++k) b += s_red[k];
-        s_base = h0 + b;
-    }
+    for (int j = threadIdx.x; j < cnt; j += kBinThreads) atomicAdd(&s_h[tsens[cs + j] - lo], 1);
     __syncthreads();
     // exclusive scan of the histogram: thread t owns a contiguous run
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int per = (nb + kBinThreads - 1) / kBinThreads;
     const int a0 = threadIdx.x * per < nb ? threadIdx.x * per : nb;
     const int a1 = a0 + per < nb ? a0 + per : nb;
     int64_t run = 0;
-    for (int i = a0; i < a1; ++i) run += s_hist[i];
-    int64_t inc = wave_incl_scan(run);
-    if (lane == 63) s_red[wv] = inc;
+    for (int i = a0; i < a1; ++i) run += s_h[i];
+    const int64_t inc = wave_incl_scan(run);
+    if (lane == 63) s_w[wv] = inc;
     __syncthreads();
-    int64_t woff = 0, tot = 0;
-    for (int k = 0; k < kBinThreads / 64; ++k) { if (k < wv) woff += s_red[k]; tot += s_red[k]; }
-    int64_t acc = woff + inc - run;
-    const int64_t base = s_base;
+    int64_t acc = inc - run;
+    for (int k = 0; k < wv; ++k) acc += s_w[k];
     __syncthreads();
     for (int i = a0; i < a1; ++i) {
-        const int c = s_hist[i];
-        s_hist[i] = (int32_t)acc;                 // exclusive offset, then cursor
-        bin_off[(int64_t)e * n_sens + lo + i] = base + acc;
+        const int c = s_h[i];
+        s_h[i] = (int32_t)acc;                    // exclusive offset, then cursor
+        bin_off[(int64_t)e * n_sens + lo + i] = cs + acc;
         acc += c;
     }
-    if (e == n_ev - 1 && r == split - 1 && threadIdx.x == 0) bin_off[(int64_t)n_ev * n_sens] = base + tot;
-    if (threadIdx.x == 0) s_hist[nb] = (int32_t)tot;
+    if (e == n_ev - 1 && r == nr - 1 && threadIdx.x == 0) bin_off[(int64_t)n_ev * n_sens] = cpos[*nent];
     __syncthreads();
-    for (int64_t hb = h0 + threadIdx.x; hb < h1; hb += kRound) {
-        int sv[kBinU];
-#pragma unroll
-        for (int u = 0; u < kBinU; ++u) {
-            const int64_t h = hb + (int64_t)u * kBinThreads;
-            sv[u] = h < h1 ? sensor[h] : -1;
-        }
-        // coordinates of the range's hits are requested before the LDS
-        // atomics so that both latencies overlap
-        float4 hv[kBinU];
-#pragma unroll
-        for (int u = 0; u < kBinU; ++u) {
-            const int64_t h = hb + (int64_t)u * kBinThreads;
-            hv[u] = (sv[u] >= lo && sv[u] < hi) ? make_float4(x[h], y[h], z[h], __int_as_float((int)h))
-                                                : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        int pos[kBinU];
-#pragma unroll
-        for (int u = 0; u < kBinU; ++u)
-            pos[u] = (sv[u] >= lo && sv[u] < hi) ? atomicAdd(&s_hist[sv[u] - lo], 1) : -1;
-#pragma unroll
-        for (int u = 0; u < kBinU; ++u)
-            if (pos[u] >= 0) bin_hit[base + pos[u]] = hv[u];
+    const bool in_lds = cnt <= kFineCap;
+    for (int j = threadIdx.x; j < cnt; j += kBinThreads) {
+        const int p = atomicAdd(&s_h[tsens[cs + j] - lo], 1);
+        if (in_lds) s_pos[p] = (uint16_t)j; else gpos[cs + p] = j;
     }
     __syncthreads();
-    // each cursor now holds the end of its bin (the next bin's start); order
-    // every bin by input index. Bins of up to kBinSortReg hits: a sorting
-    // network in registers by the bin's owner thread. Larger bins: listed in
-    // LDS, then every element of them gets its own thread, which counts the
-    // smaller keys of its bin (its rank); all elements are read before any is
-    // written back at its rank (in place, the block owns these positions).
-    if (threadIdx.x == 0) s_nbig = 0;
-    __syncthreads();
+    // each cursor now holds the end of its bin; put every bin back in
+    // local-position (= input) order
     for (int i = threadIdx.x; i < nb; i += kBinThreads) {
-        const int64_t bs = base + (i == 0 ? 0 : s_hist[i - 1]), be = base + s_hist[i];
-        const int n = (int)(be - bs);
-        if (n <= 1) continue;
-        if (n <= kBinSortReg) {
-            float4 v[kBinSortReg];
-#pragma unroll
-            for (int k = 0; k < kBinSortReg; ++k)
-                v[k] = k < n ? bin_hit[bs + k] : make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fffffff));
-#pragma unroll
-            for (int p = 0; p < kBinSortReg; ++p) {
-#pragma unroll
-                for (int k = p & 1; k + 1 < kBinSortReg; k += 2) cswap_key(v[k], v[k + 1]);
+        const int bs = i == 0 ? 0 : s_h[i - 1], be = s_h[i];
+        if (in_lds) {
+            for (int k = bs + 1; k < be; ++k) {
+                const uint16_t v = s_pos[k];
+                int j = k - 1;
+                while (j >= bs && s_pos[j] > v) { s_pos[j + 1] = s_pos[j]; --j; }
+                s_pos[j + 1] = v;
             }
-#pragma unroll
-            for (int k = 0; k < kBinSortReg; ++k)
-                if (k < n) bin_hit[bs + k] = v[k];
         } else {
-            const int slot = atomicAdd(&s_nbig, 1);
-            if (slot < kBigBins) s_big[slot] = i;
-        }
-    }
-    __syncthreads();
-    const int nbig = s_nbig;
-    // sizes of the listed big bins -> exclusive prefix (one entry per thread)
-    int my_n = 0;
-    if (threadIdx.x < nbig && threadIdx.x < kBigBins) {
-        const int i = s_big[threadIdx.x];
-        my_n = s_hist[i] - (i == 0 ? 0 : s_hist[i - 1]);
-    }
-    const int64_t incl = wave_incl_scan((int64_t)my_n);
-    if (lane == 63) s_red[wv] = incl;
-    __syncthreads();
-    int64_t boff = 0, btot = 0;
-    for (int k = 0; k < kBinThreads / 64; ++k) { if (k < wv) boff += s_red[k]; btot += s_red[k]; }
-    if (threadIdx.x < kBigBins) s_bigpre[threadIdx.x] = (int32_t)(boff + incl - my_n);
-    if (threadIdx.x == 0) s_bigpre[kBigBins] = (int32_t)btot;
-    __syncthreads();
-    if (nbig <= kBigBins && btot <= (int64_t)kBinThreads * kBigPer) {
-        const int nl = nbig;
-        float4 v[kBigPer];
-        int64_t dst[kBigPer];
-#pragma unroll
-        for (int k = 0; k < kBigPer; ++k) {
-            const int q = threadIdx.x + k * kBinThreads;
-            dst[k] = -1;
-            if (q < btot) {
-                int lo2 = 0, hi2 = nl;            // listed bin holding element q
-                while (hi2 - lo2 > 1) {
-                    const int mid = (lo2 + hi2) >> 1;
-                    if (s_bigpre[mid] <= q) lo2 = mid; else hi2 = mid;
-                }
-                const int i = s_big[lo2];
-                const int64_t bs = base + (i == 0 ? 0 : s_hist[i - 1]), be = base + s_hist[i];
-                v[k] = bin_hit[bs + (q - s_bigpre[lo2])];
-                const int key = __float_as_int(v[k].w);
-                int rank = 0;
-                for (int64_t m = bs; m < be; ++m) rank += __float_as_int(bin_hit[m].w) < key ? 1 : 0;
-                dst[k] = bs + rank;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kBigPer; ++k)
-            if (dst[k] >= 0) bin_hit[dst[k]] = v[k];
-    } else {
-        // (rare) too many large bins for the list: their owners sort in place
-        for (int i = threadIdx.x; i < nb; i += kBinThreads) {
-            const int64_t bs = base + (i == 0 ? 0 : s_hist[i - 1]), be = base + s_hist[i];
-            if (be - bs <= kBinSortReg) continue;
-            for (int64_t k = bs + 1; k < be; ++k) {
-                const float4 v = bin_hit[k];
-                const int key = __float_as_int(v.w);
-                int64_t j = k - 1;
-                while (j >= bs && __float_as_int(bin_hit[j].w) > key) { bin_hit[j + 1] = bin_hit[j]; --j; }
-                bin_hit[j + 1] = v;
+            for (int k = bs + 1; k < be; ++k) {
+                const int v = gpos[cs + k];
+                int j = k - 1;
+                while (j >= bs && gpos[cs + j] > v) { gpos[cs + j + 1] = gpos[cs + j]; --j; }
+                gpos[cs + j + 1] = v;
             }
         }
     }
+    __syncthreads();
+    for (int p = threadIdx.x; p < cnt; p += kBinThreads)
+        bin_hit[cs + p] = tmp[cs + (in_lds ? (int)s_pos[p] : gpos[cs + p])];
 }
 
 // ------------------------------------------------------------ MD stage
@@ -1150,14 +1157,23 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     // a1: bin hits by (event, sensor)
     mark(ev, 2, st);
     {
-        // the requested split, raised until one range's histogram fits the LDS limit
-        int split = a.tune.bin_split;
-        while ((int64_t)((n_sens + split - 1) / split + 1) * 4 > kBinLdsMax) ++split;
-        const int range = (n_sens + split - 1) / split;
+        int nr = (n_sens + kFineRange - 1) / kFineRange;
+        if (a.tune.bin_split > nr) nr = a.tune.bin_split;
+        const int rw = (n_sens + nr - 1) / nr;
+        const int grid_t = (int)w.max_bin_tiles;
+        hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(1024), 0, st, a.ev_off, a.n_ev, nr, w.bin_tbase, w.bin_nent);
+        hipLaunchKernelGGL(k_bin_count, dim3(grid_t), dim3(kBinThreads), 0, st, a.sensor, a.ev_off, a.n_ev, n_sens, nr,
+                           rw, (const int64_t *)w.bin_tbase, w.bin_cnt, cnt);
+        scan(CntF{w.bin_cnt}, w.bin_nent, w.max_bin_entries, w, w.bin_cpos, nullptr, st);
+        hipLaunchKernelGGL(k_bin_scatter, dim3(grid_t), dim3(kBinThreads), 0, st, a.x, a.y, a.z, a.sensor, a.ev_off,
+                           a.n_ev, n_sens, nr, rw, (const int64_t *)w.bin_tbase, (const int64_t *)w.bin_cpos,
+                           w.bin_tmp, w.bin_tsens);
         const int xcd_map = a.n_ev >= kXcds ? 1 : 0;
-        const int grid = xcd_map ? (a.n_ev + kXcds - 1) / kXcds * kXcds * split : a.n_ev * split;
-        hipLaunchKernelGGL(k_bin_event, dim3(grid), dim3(kBinThreads), (size_t)(range + 1) * 4, st, a.x, a.y, a.z,
-                           a.sensor, a.ev_off, a.n_ev, n_sens, split, xcd_map, w.bin_off, w.bin_hit, cnt);
+        const int grid_f = xcd_map ? (a.n_ev + kXcds - 1) / kXcds * kXcds * nr : a.n_ev * nr;
+        hipLaunchKernelGGL(k_bin_fine, dim3(grid_f), dim3(kBinThreads), 0, st, (const float4 *)w.bin_tmp,
+                           (const int32_t *)w.bin_tsens, (const int64_t *)w.bin_tbase, (const int64_t *)w.bin_cpos,
+                           (const int64_t *)w.bin_nent, a.n_ev, n_sens, nr, rw, xcd_map, w.bin_off, w.bin_hit,
+                           w.bin_gpos);
     }
     mark(ev, 3, st);
 
