@@ -25,6 +25,7 @@ and clock; `GpuExecutor` is the device implementation.
 """
 from __future__ import annotations
 
+import ctypes
 import time
 from collections import deque
 from dataclasses import dataclass
@@ -135,6 +136,30 @@ def poisson_arrivals(rate: float, n: int, rng: np.random.Generator) -> np.ndarra
 
 # ------------------------------------------------------------------ device side
 
+_HIP = None
+
+
+def _hip():
+    """The HIP runtime this process already uses (the one torch loaded), for
+    2-D asynchronous copies: one call places an event's four hit arrays."""
+    global _HIP
+    if _HIP is None:
+        path = "libamdhip64.so.7"
+        with open("/proc/self/maps") as fh:
+            for line in fh:
+                if "libamdhip64" in line:
+                    path = line.split()[-1]
+                    break
+        L = ctypes.CDLL(path)
+        L.hipMemcpy2DAsync.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+        L.hipMemcpy2DAsync.restype = ctypes.c_int
+        _HIP = L
+    return _HIP
+
+
+_HIP_H2D = 1
+
 class _Slot:
     def __init__(self, geometry_blob, model_blob, caps, mode, precision, device, use_graph):
         import torch
@@ -152,11 +177,11 @@ class _Slot:
         self.caps = caps
         self.b.caps = None
         self.b.reserve(caps)
-        f32 = dict(dtype=torch.float32, device=self.dev)
-        self.dx = torch.zeros(caps.hits, **f32)
-        self.dy = torch.zeros(caps.hits, **f32)
-        self.dz = torch.zeros(caps.hits, **f32)
-        self.ds = torch.zeros(caps.hits, dtype=torch.int32, device=self.dev)
+        # hit arrays of the batch as the rows of one [4, hits] buffer (x, y, z,
+        # sensor bits), so one 2-D copy places an event's four arrays
+        self.dhits = torch.zeros((4, caps.hits), dtype=torch.float32, device=self.dev)
+        self.dx, self.dy, self.dz = self.dhits[0], self.dhits[1], self.dhits[2]
+        self.ds = self.dhits[3].view(torch.int32)
         self.doff = torch.zeros(caps.events + 1, dtype=torch.int64, device=self.dev)
         self.h_off = torch.zeros(caps.events + 1, dtype=torch.int64, pin_memory=True)
         self.h_counts = torch.zeros(8, dtype=torch.int64, pin_memory=True)
@@ -182,7 +207,7 @@ class _Slot:
         """Device bytes held by this slot (inputs, outputs, workspace)."""
         buf = self.b._buf
         dev = sum(t.numel() * t.element_size() for t in buf.values() if t is not None)
-        dev += sum(t.numel() * t.element_size() for t in (self.dx, self.dy, self.dz, self.ds, self.doff))
+        dev += sum(t.numel() * t.element_size() for t in (self.dhits, self.doff))
         return int(dev)
 
     def _launch_build(self):
@@ -214,14 +239,18 @@ class _Slot:
         off = 0
         ho = self.h_off.numpy()
         ho[0] = 0
+        hip = _hip()
+        base = self.dhits.data_ptr()
+        pitch = self.caps.hits * 4
+        sp = self.stream.cuda_stream
         with torch.cuda.stream(self.stream):
             for i, r in enumerate(batch):
-                x, y, z, s = r.payload
                 n = r.n_hits
-                self.dx[off:off + n].copy_(x, non_blocking=True)
-                self.dy[off:off + n].copy_(y, non_blocking=True)
-                self.dz[off:off + n].copy_(z, non_blocking=True)
-                self.ds[off:off + n].copy_(s, non_blocking=True)
+                if n:
+                    err = hip.hipMemcpy2DAsync(base + 4 * off, pitch, r.payload.data_ptr(), 4 * n, 4 * n, 4,
+                                               _HIP_H2D, sp)
+                    if err != 0:
+                        raise RuntimeError(f"hipMemcpy2DAsync failed ({err})")
                 off += n
                 ho[i + 1] = off
             ho[len(batch) + 1:] = off
@@ -343,15 +372,14 @@ def slot_caps(hits_cap: int, events_cap: int):
 
 
 def pinned_event(ev):
-    """Event arrays in pinned host memory (the source of asynchronous H2D copies)."""
+    """An event's hits in pinned host memory as one [4, n] float32 block (x, y,
+    z, sensor ids as bits): the source of one asynchronous 2-D copy."""
     import torch
-    out = []
-    for a in (ev.x, ev.y, ev.z, ev.sensor):
-        t = torch.empty(a.shape[0], dtype=torch.float32 if a.dtype == np.float32 else torch.int32,
-                        pin_memory=True)
-        t.numpy()[:] = a
-        out.append(t)
-    return tuple(out)
+    t = torch.empty((4, ev.n), dtype=torch.float32, pin_memory=True)
+    a = t.numpy()
+    a[0], a[1], a[2] = ev.x, ev.y, ev.z
+    a[3] = np.ascontiguousarray(ev.sensor, dtype=np.int32).view(np.float32)
+    return t
 
 
 def make_pool(n: int, seed: int = 0):
