@@ -141,6 +141,9 @@ lst_status lst_load_geometry(lst_ctx *c, const void *blob, size_t nbytes) {
     p.ls3slack = (float)prm[11]; p.chi2rz = (float)prm[8]; p.chi2rphi = (float)prm[9];
     p.kb_d = kb; p.cmax_d = cmax; p.zlum_d = prm[2]; p.nsig_d = ns; p.srphi_d = srphi;
     p.sz_d = prm[5]; p.sr_d = prm[6];
+    if (!(srphi > 0) || !(prm[5] > 0) || !(prm[6] > 0))
+        return fail(c, LST_E_INVAL, "geometry blob: resolutions must be positive");
+    p.isrphi_d = 1.0 / srphi; p.isr_d = 1.0 / prm[6]; p.isz_d = 1.0 / prm[5];
     std::vector<ModConst> mods(nm);
     const unsigned char *r = b + 152;
     for (uint32_t m = 0; m < nm; ++m, r += 64) {

@@ -34,6 +34,7 @@ struct ModConst {
 struct CutParams {
     float kb, cmax, zlum, nsig, srphi, sz, sr, e2slack, ls3slack, chi2rz, chi2rphi;
     double kb_d, cmax_d, zlum_d, nsig_d, srphi_d, sz_d, sr_d;
+    double isrphi_d, isr_d, isz_d;        // 1 / sigma, so the fits multiply instead of divide
 };
 
 struct ModelDev {
@@ -176,19 +177,23 @@ __device__ __forceinline__ double circle_distance(double A, double B, double C, 
 // the first to the last point: smallest root of the characteristic cubic of
 // the generalised eigenproblem by Newton from 0, null vector as the largest
 // cross product of two rows; straight lines give A = 0.
-__device__ inline void circle_fit5(const double *x, const double *y, const double *sig, Fit5 &f) {
+// isig[i] = 1 / sigma_i of point i (weights 1 / sigma^2).
+__device__ inline void circle_fit5(const double *x, const double *y, const double *isig, Fit5 &f) {
     double W = 0, xm = 0, ym = 0;
     double w[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) { w[i] = 1.0 / (sig[i] * sig[i]); W += w[i]; xm += w[i] * x[i]; ym += w[i] * y[i]; }
-    xm /= W; ym /= W;
+    for (int i = 0; i < 5; ++i) { w[i] = isig[i] * isig[i]; W += w[i]; xm += w[i] * x[i]; ym += w[i] * y[i]; }
+    const double iW = 1.0 / W;
+    xm *= iW; ym *= iW;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) w[i] *= iW;
     double cx = x[4] - x[0], cy = y[4] - y[0], cl = sqrt(cx * cx + cy * cy);
     double ca = cl > 0 ? cx / cl : 1.0, sa = cl > 0 ? cy / cl : 0.0;
     double u[5], v[5];
     double Mxx = 0, Myy = 0, Mxy = 0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        double wi = w[i] / W;
+        double wi = w[i];
         double u0 = x[i] - xm, v0 = y[i] - ym;
         u[i] = ca * u0 + sa * v0; v[i] = -sa * u0 + ca * v0;
         Mxx += wi * u[i] * u[i]; Myy += wi * v[i] * v[i]; Mxy += wi * u[i] * v[i];
@@ -197,7 +202,7 @@ __device__ inline void circle_fit5(const double *x, const double *y, const doubl
     double Mxz = 0, Myz = 0, varz = 0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        double wi = w[i] / W;
+        double wi = w[i];
         double zt = u[i] * u[i] + v[i] * v[i] - Mz;
         Mxz += wi * u[i] * zt; Myz += wi * v[i] * zt; varz += wi * zt * zt;
     }
@@ -230,15 +235,15 @@ __device__ inline void circle_fit5(const double *x, const double *y, const doubl
         if (nn > bn) { bn = nn; bA = v0; bB = v1; bC = v2; }
     }
     double A = bA, B = bB, C = bC, D = -A * Mz;
-    double S = sqrt(B * B + C * C - 4.0 * A * D);
-    A /= S; D /= S;
-    double Br = (ca * B - sa * C) / S, Cr = (sa * B + ca * C) / S;
+    const double iS = 1.0 / sqrt(B * B + C * C - 4.0 * A * D);
+    A *= iS; D *= iS;
+    double Br = (ca * B - sa * C) * iS, Cr = (sa * B + ca * C) * iS;
     f.xm = xm; f.ym = ym; f.A = A; f.B = Br; f.C = Cr; f.D = D;
     f.R = A != 0.0 ? 0.5 / fabs(A) : __builtin_huge_val();
     double chi2 = 0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        double d = circle_distance(A, Br, Cr, D, x[i] - xm, y[i] - ym) / sig[i];
+        double d = circle_distance(A, Br, Cr, D, x[i] - xm, y[i] - ym) * isig[i];
         chi2 += d * d;
     }
     f.chi2_rphi = chi2;
@@ -247,31 +252,34 @@ __device__ inline void circle_fit5(const double *x, const double *y, const doubl
 // Both fits of a quintuplet from its five anchors (x, y, z) and endcap flags.
 __device__ inline void t5_fit(const CutParams &p, const double *x, const double *y, const double *z,
                               const bool *endc, Fit5 &f) {
-    double sg[5], r[5], s[5];
+    double isg[5], r[5], s[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) { sg[i] = endc[i] ? p.sr_d : p.srphi_d; r[i] = sqrt(x[i] * x[i] + y[i] * y[i]); }
-    circle_fit5(x, y, sg, f);
+    for (int i = 0; i < 5; ++i) { isg[i] = endc[i] ? p.isr_d : p.isrphi_d; r[i] = sqrt(x[i] * x[i] + y[i] * y[i]); }
+    circle_fit5(x, y, isg, f);
     double cf = fabs(f.A);
 #pragma unroll
     for (int i = 0; i < 5; ++i) s[i] = arc_len_d(cf, r[i]);
     if (!(s[4] > s[0])) { f.t = __builtin_nan(""); f.z0 = __builtin_nan(""); f.chi2_rz = __builtin_huge_val(); return; }
     double kAE = fabs((z[4] - z[0]) / (s[4] - s[0]));
+    // endcap points: sigma_r times the r-z slope (floored at 0.1); barrel: sigma_z
+    const double ike = p.isr_d / (kAE > 0.1 ? kAE : 0.1);
+    double wz[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) sg[i] = endc[i] ? p.sr_d * (kAE > 0.1 ? kAE : 0.1) : p.sz_d;
+    for (int i = 0; i < 5; ++i) { const double iv = endc[i] ? ike : p.isz_d; wz[i] = iv * iv; }
     double Wt = 0, sm = 0, zm = 0;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) { double wi = 1.0 / (sg[i] * sg[i]); Wt += wi; sm += wi * s[i]; zm += wi * z[i]; }
-    sm /= Wt; zm /= Wt;
+    for (int i = 0; i < 5; ++i) { Wt += wz[i]; sm += wz[i] * s[i]; zm += wz[i] * z[i]; }
+    const double iWt = 1.0 / Wt;
+    sm *= iWt; zm *= iWt;
     double Sss = 0, Ssz = 0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        double wi = 1.0 / (sg[i] * sg[i]);
-        Sss += wi * (s[i] - sm) * (s[i] - sm); Ssz += wi * (s[i] - sm) * (z[i] - zm);
+        Sss += wz[i] * (s[i] - sm) * (s[i] - sm); Ssz += wz[i] * (s[i] - sm) * (z[i] - zm);
     }
     if (!(Sss > 0)) { f.t = __builtin_nan(""); f.z0 = __builtin_nan(""); f.chi2_rz = __builtin_huge_val(); return; }
     double t = Ssz / Sss, z0 = zm - t * sm, chi2 = 0;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) { double d = z[i] - z0 - t * s[i]; chi2 += d * d / (sg[i] * sg[i]); }
+    for (int i = 0; i < 5; ++i) { double d = z[i] - z0 - t * s[i]; chi2 += d * d * wz[i]; }
     f.t = t; f.z0 = z0; f.chi2_rz = chi2;
 }
 
