@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # documented marginal band), and NaN still fails every "v <= t" test.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fgpu-flush-denormals-to-zero",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 

@@ -270,6 +270,7 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     x.rec_scratch = (void *)take((size_t)kMaxRecBytes * kMinTile * max_tiles);
     x.md_a = (float4 *)take(16 * md);
     x.md_o = (float2 *)take(8 * md);
+    x.md_rq = (float2 *)take(8 * md);
     x.md_mod_off = (int64_t *)take(8 * (ev * nmod + 1));
     x.rsum = (int32_t *)take(4 * ev * nmod);
     x.rpref = (int32_t *)take(4 * ev * (c->n_map > 0 ? c->n_map : 1));

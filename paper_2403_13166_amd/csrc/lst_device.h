@@ -142,6 +142,42 @@ __device__ __forceinline__ bool pair_pass(const CutParams &p, P3 X, bool endX, P
     return fabsf(z0) <= p.zlum + p.nsig * sqrtf(var);
 }
 
+// Per-MD quantities the pair cuts use, computed once per MD: rq = {r, q}
+// with r the transverse radius of the anchor hit and q = srphi^2 / r^2 (plus
+// cmax^2 sr^2 for an endcap MD); the sign bit of q marks an endcap MD.
+__device__ __forceinline__ float2 make_md_rq(const CutParams &p, float x, float y, bool endcap) {
+    const float r = sqrtf(x * x + y * y);
+    float q = p.srphi * p.srphi / (r * r);
+    if (endcap) q += p.cmax * p.cmax * p.sr * p.sr;
+    return make_float2(r, endcap ? -q : q);
+}
+
+// pair_pass with the per-MD radii and resolution terms precomputed (md_rq).
+__device__ __forceinline__ bool pair_pass_rq(const CutParams &p, P3 X, float2 rqX, P3 Y, float2 rqY,
+                                             float &c_out, float &sgn_out) {
+    const float rX = rqX.x, rY = rqY.x;
+    const bool endX = signbit(rqX.y), endY = signbit(rqY.y);
+    float dx = Y.x - X.x, dy = Y.y - X.y;
+    float dl = sqrtf(dx * dx + dy * dy);
+    float cr = cross2(X.x, X.y, Y.x, Y.y);
+    float c = fabsf(cr) / (rX * rY * dl);
+    float srX = endX ? p.sr : 0.0f, srY = endY ? p.sr : 0.0f;
+    float szX = endX ? 0.0f : p.sz, szY = endY ? 0.0f : p.sz;
+    float sc = sqrtf(fabsf(rqX.y) + fabsf(rqY.y)) / dl;
+    c_out = c;
+    sgn_out = cr < 0.0f ? -1.0f : 1.0f;
+    if (!(c <= p.cmax + p.nsig * sc)) return false;
+    float cp = fminf(c, p.cmax);
+    float sX = arc_len_f(cp, rX), sY = arc_len_f(cp, rY);
+    if (!(sX < sY)) return false;
+    float ds = sY - sX;
+    float k = (Y.z - X.z) / ds;
+    float z0 = X.z - sX * k;
+    float a = sY * szX, b = sX * szY, e = sY * srX, f = sX * srY;
+    float var = (a * a + b * b + k * k * (e * e + f * f)) / (ds * ds);
+    return fabsf(z0) <= p.zlum + p.nsig * sqrtf(var);
+}
+
 // MD direction: the chord between the MD's hits follows the track direction at
 // the chord midpoint (angle asin(c'|M|) from radial, toward the bending side).
 __device__ __forceinline__ bool md_dir_pass(const CutParams &p, P3 hi, float ox, float oy, float cp,

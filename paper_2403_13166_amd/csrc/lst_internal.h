@@ -66,6 +66,7 @@ struct Work {
     // MD
     float4 *md_a;                     // [cap_md] anchor x, y, z, global module (bits)
     float2 *md_o;                     // [cap_md] other hit x, y
+    float2 *md_rq;                    // [cap_md] radius and resolution term (sign: endcap) for the pair cuts
     int64_t *md_mod_off;              // [cap_ev * n_mod + 1]
     int32_t *rsum;                    // [cap_ev * n_mod] MDs in the mapped modules
     int32_t *rpref;                   // [cap_ev * n_map] exclusive prefix over map entries

@@ -671,6 +671,7 @@ struct MDStage {
     int2 *md_hits;
     float4 *md_a;
     float2 *md_o;
+    float2 *md_rq;
     static constexpr int kEnt = 0;
     static constexpr int kStage = 0;
     static constexpr bool kTwoPhase = false;
@@ -706,6 +707,7 @@ struct MDStage {
         md_hits[pos] = make_int2(r.hl, r.hu);
         md_a[pos] = r.a;
         md_o[pos] = r.o;
+        md_rq[pos] = make_md_rq(p, r.a.x, r.a.y, mod[__float_as_int(r.a.w) % n_mod].kind != 0);
     }
 };
 
@@ -773,6 +775,7 @@ __global__ __launch_bounds__(kBlock) void k_ls_prefix(const int32_t *map_off, co
 struct LSStage {
     const float4 *md_a;
     const float2 *md_o;
+    const float2 *md_rq;
     const int64_t *md_mod_off;
     const int32_t *rsum, *rpref;
     const int32_t *map_off, *map_tgt;
@@ -871,9 +874,10 @@ struct LSStage {
             eB = mod[mb].kind != 0;
         }
         const float4 A = md_a[a], B = md_a[b];
+        const float2 qa = md_rq[a], qb = md_rq[b];
         r.a = (int)a; r.b = (int)b;
         float c, sg;
-        if (!pair_pass(p, P3{A.x, A.y, A.z}, eA, P3{B.x, B.y, B.z}, eB, c, sg)) return false;
+        if (!pair_pass_rq(p, P3{A.x, A.y, A.z}, qa, P3{B.x, B.y, B.z}, qb, c, sg)) return false;
         q.a = (int)a; q.b = (int)b;
         q.cp = fminf(c, p.cmax);
         q.bits = (sg > 0.0f ? 1 : 0) | (eA ? 0 : 2) | (eB ? 0 : 4);
@@ -908,6 +912,7 @@ struct T3Stage {
     const int64_t *ls_off;
     const float4 *md_a;
     const float2 *md_o;
+    const float2 *md_rq;
     const ModConst *mod;
     CutParams p;
     int32_t n_mod;
@@ -936,13 +941,13 @@ struct T3Stage {
         const int A = f[2], B = f[3];
         const int C = ls_md[lo].y;
         r.li = (int)l1; r.lo = lo; r.A = A; r.B = B; r.C = C;
-        float4 a = md_a[A], b = md_a[B], c = md_a[C];
-        int ma = __float_as_int(a.w) % n_mod, mb = __float_as_int(b.w) % n_mod, mc = __float_as_int(c.w) % n_mod;
+        const float4 a = md_a[A], c = md_a[C];
+        const float2 qa = md_rq[A], qc = md_rq[C];
         float cv, sg;
-        if (!pair_pass(p, P3{a.x, a.y, a.z}, mod[ma].kind != 0, P3{c.x, c.y, c.z}, mod[mc].kind != 0, cv, sg))
-            return false;
-        if (mod[mb].kind == 0) {
-            float2 o = md_o[B];
+        if (!pair_pass_rq(p, P3{a.x, a.y, a.z}, qa, P3{c.x, c.y, c.z}, qc, cv, sg)) return false;
+        if (!signbit(md_rq[B].y)) {                 // barrel middle MD: direction cut
+            const float4 b = md_a[B];
+            const float2 o = md_o[B];
             if (!md_dir_pass(p, P3{b.x, b.y, b.z}, o.x, o.y, fminf(cv, p.cmax), sg)) return false;
         }
         return true;
@@ -965,6 +970,7 @@ struct T5PreStage {
     const int4 *t3_mds;
     const int64_t *t3i_off;
     const float4 *md_a;
+    const float2 *md_rq;
     const ModConst *mod;
     CutParams p;
     int32_t n_mod;
@@ -993,8 +999,7 @@ struct T5PreStage {
         const int E = t3_mds[v].z;
         const float4 a = md_a[f[2]], e = md_a[E];
         float cv, sg;
-        return pair_pass(p, P3{a.x, a.y, a.z}, mod[__float_as_int(a.w) % n_mod].kind != 0, P3{e.x, e.y, e.z},
-                         mod[__float_as_int(e.w) % n_mod].kind != 0, cv, sg);
+        return pair_pass_rq(p, P3{a.x, a.y, a.z}, md_rq[f[2]], P3{e.x, e.y, e.z}, md_rq[E], cv, sg);
     }
     __device__ void write(int64_t pos, const Rec &r) const { pre[pos] = make_int2(r.u, r.v); }
 };
@@ -1178,7 +1183,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     mark(ev, 3, st);
 
     // a2: mini-doublets, anchored on (event, module)
-    MDStage md{w.bin_off, w.bin_hit, a.g.mod, a.p, n_mod, n_sens, o.md_hits, w.md_a, w.md_o};
+    MDStage md{w.bin_off, w.bin_hit, a.g.mod, a.p, n_mod, n_sens, o.md_hits, w.md_a, w.md_o, w.md_rq};
     run_stage(md, nullptr, ngm, w, cnt + LST_COUNT_MD, w.cap_md, cnt, st, ev, 2, a.tune);
     hipLaunchKernelGGL(k_fill_offsets<GmKey>, dim3(grid_for(ngm + 1)), dim3(kBlock), 0, st, GmKey{w.md_a},
                        cnt + LST_COUNT_MD, w.cap_md, nullptr, ngm, w.md_mod_off);
@@ -1187,14 +1192,14 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
 
     // a3: line segments, anchored on (event, module): the module's MDs against
     // the MDs of its mapped modules
-    LSStage ls{w.md_a, w.md_o, w.md_mod_off, w.rsum, w.rpref, a.g.map_off, a.g.map_tgt, a.g.mod, a.p,
+    LSStage ls{w.md_a, w.md_o, w.md_rq, w.md_mod_off, w.rsum, w.rpref, a.g.map_off, a.g.map_tgt, a.g.mod, a.p,
                n_mod, n_map, o.ls_md};
     run_stage(ls, nullptr, ngm, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st, ev, 3, a.tune);
     hipLaunchKernelGGL(k_fill_offsets<LsInKey>, dim3(grid_for(w.cap_md + 1)), dim3(kBlock), 0, st, LsInKey{o.ls_md},
                        cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w.ls_off);
 
     // a4: triplets, anchored on the inner LS
-    T3Stage t3{o.ls_md, w.ls_off, w.md_a, w.md_o, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
+    T3Stage t3{o.ls_md, w.ls_off, w.md_a, w.md_o, w.md_rq, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
     run_stage(t3, cnt + LST_COUNT_LS, w.cap_ls, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st, ev, 4, a.tune);
     hipLaunchKernelGGL(k_fill_offsets<T3InKey>, dim3(grid_for(w.cap_md + 1)), dim3(kBlock), 0, st, T3InKey{w.t3_mds},
                        cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w.t3i_off);
@@ -1202,7 +1207,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     // a5: quintuplets, anchored on the inner T3: FP32 beam-line cuts, then the
     // FP64 fits on the dense list of pre-candidates
     const bool score_cut = a.mode == 0 && a.score_min == a.score_min;
-    T5PreStage t5p{w.t3_mds, w.t3i_off, w.md_a, a.g.mod, a.p, n_mod, w.t5_pre};
+    T5PreStage t5p{w.t3_mds, w.t3i_off, w.md_a, w.md_rq, a.g.mod, a.p, n_mod, w.t5_pre};
     mark(ev, 10, st);
     run_stage(t5p, cnt + LST_COUNT_T3, w.cap_t3, w, cnt + LST_COUNT_T5PRE, w.cap_t5pre, cnt, st, nullptr, 0, a.tune);
     T5FitStage<false> t5{w.t5_pre, w.t3_mds, w.md_a, a.g.mod, a.p, a.m, n_mod, a.mode, a.score_min, o.t5_t3,
