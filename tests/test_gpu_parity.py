@@ -281,3 +281,45 @@ def test_autotune_keeps_results(geo_f, mdl):
     for k in ("md_hits", "ls_md", "t3_ls", "t5_t3", "t5_score"):
         assert np.array_equal(getattr(got, k), getattr(ref, k)), k
     b.close()
+
+
+def test_benchmark_batch_sampled_parity(geo_f, mdl):
+    """The 64-event batch of the benchmark (same seeds, tuned launch shapes,
+    replayed from a captured HIP graph): the replay equals the eager build bit
+    for bit, and sampled events agree with the oracle."""
+    from paper_2403_13166_amd import binding as B
+    from paper_2403_13166_amd.runtime import Builder, Caps
+    rng = E.event_rng(2, 0)
+    evs = [E.make_event(geo_f, E.batch_event_config(rng), (2, 0, e)) for e in range(64)]
+    x, y, z, s, off = E.concat_events(evs)
+    b = Builder(geo_f.to_blob(), mdl.to_blob(), 0)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(b.device)
+    dx, dy, dz, ds, doff = T(x), T(y), T(z), T(s), T(off)
+    eager = b.build(dx, dy, dz, ds, event_offsets=doff, precision=B.LST_PREC_BF16).to_host()
+    _say("batch counts", [len(eager.md_hits), len(eager.ls_md), len(eager.t3_ls), len(eager.t5_t3)])
+    B.lst_set_tuning(b.ctx, {"bin_split": 4, "tile_per": [2, 8, 2, 2, 1], "eval_blocks": 8192})
+    stream = torch.cuda.Stream(device=b.device)
+    with torch.cuda.stream(stream):
+        b.launch(dx, dy, dz, ds, event_offsets=doff, precision=B.LST_PREC_BF16)
+        stream.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream, capture_error_mode="relaxed"):
+            b.launch(dx, dy, dz, ds, event_offsets=doff, precision=B.LST_PREC_BF16)
+        for _ in range(3):
+            g.replay()
+            stream.synchronize()
+            rep = b.view().to_host()
+            for k in ("md_hits", "ls_md", "t3_ls", "t5_t3", "t5_score", "t5_chi2_rphi", "t5_chi2_rz",
+                      "event_offsets"):
+                assert np.array_equal(getattr(rep, k), getattr(eager, k)), k
+    eo = eager.event_offsets
+    for i in (0, 31, 63):
+        md = eager.md_hits[eo[0, i]:eo[0, i + 1]] - off[i]
+        ls = eager.ls_md[eo[1, i]:eo[1, i + 1]] - eo[0, i]
+        t3 = eager.t3_ls[eo[2, i]:eo[2, i + 1]] - eo[1, i]
+        t5 = eager.t5_t3[eo[3, i]:eo[3, i + 1]] - eo[2, i]
+        sl = slice(eo[3, i], eo[3, i + 1])
+        from paper_2403_13166_amd.runtime import HostObjects
+        gh = HostObjects(md, ls, t3, t5, eager.t5_score[sl], eager.t5_chi2_rphi[sl], eager.t5_chi2_rz[sl], None)
+        check_parity(geo_f, mdl, evs[i], gh, score_tol=2e-2, label=f"bench batch event {i}")
+    b.close()
