@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # elementwise kernel), kept with the hash of the kernel sources they were
 # taken on: a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("ls stage", 8): {"bytes": 323844325.9, "source_sha1": "ae3e279a05877fe055a7ea70374f6dfb06dbcd95"},
+    ("ls stage", 8): {"bytes": 210996240.9, "source_sha1": "0e14f8ebe13084786b292923340e5cb4ac3488cf"},
 }
 KERNEL_SOURCES = ("paper_2403_13166_amd/csrc/lst_pipeline.hip", "paper_2403_13166_amd/csrc/lst_device.h",
                   "paper_2403_13166_amd/csrc/lst_internal.h")
