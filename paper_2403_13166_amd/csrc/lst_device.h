@@ -377,13 +377,17 @@ __device__ inline void t5_fit_features_from(const CutParams &p, const float *fo,
 // The feature row from the anchors and the fit features above.
 __device__ inline void t5_features_from(const CutParams &p, const double *x, const double *y, const double *z,
                                         const int *layer, const bool *endc, const float *ff, float *ft) {
+    // per-anchor features in FP32 (the anchors are FP32 positions); the
+    // three-point radii and curvatures below keep FP64 (near-collinear
+    // triplets cancel badly in FP32)
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        double r = sqrt(x[i] * x[i] + y[i] * y[i]);
-        ft[6 * i + 0] = (float)r;
-        ft[6 * i + 1] = (float)atan2(y[i], x[i]);
-        ft[6 * i + 2] = (float)z[i];
-        ft[6 * i + 3] = (float)asinh(z[i] / r);
+        const float xf = (float)x[i], yf = (float)y[i], zf = (float)z[i];
+        const float r = sqrtf(xf * xf + yf * yf);
+        ft[6 * i + 0] = r;
+        ft[6 * i + 1] = atan2f(yf, xf);
+        ft[6 * i + 2] = zf;
+        ft[6 * i + 3] = asinhf(zf / r);
         ft[6 * i + 4] = (float)layer[i];
         ft[6 * i + 5] = endc[i] ? 1.0f : 0.0f;
     }

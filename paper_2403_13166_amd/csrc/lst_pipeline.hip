@@ -516,8 +516,18 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const int32_t *sensor
     __syncthreads();
     const float inv = 1.0f / (float)rw;
     bool bad = false;
-    for (int64_t h = h0 + threadIdx.x; h < h1; h += kBinThreads) {
-        const int v = sensor[h];
+    constexpr int kU = kBinTile / kBinThreads;      // all of the tile's loads in flight
+    int sv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int64_t h = h0 + threadIdx.x + (int64_t)u * kBinThreads;
+        sv[u] = h < h1 ? sensor[h] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int64_t h = h0 + threadIdx.x + (int64_t)u * kBinThreads;
+        if (h >= h1) continue;
+        const int v = sv[u];
         if (v < 0 || v >= n_sens) { bad = true; continue; }
         atomicAdd(&s_c[div_small(v, rw, inv)], 1);
     }
@@ -543,17 +553,21 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const float *x, con
     for (int r = threadIdx.x; r < nr; r += kBinThreads) s_base[r] = cpos[ebase + (int64_t)r * nt];
     const float inv = 1.0f / (float)rw;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the next round's hit is loaded while the current one is ranked
+    int64_t hn = h0 + threadIdx.x;
+    int vn = hn < h1 ? sensor[hn] : -1;
+    float4 hvn = hn < h1 ? make_float4(x[hn], y[hn], z[hn], __int_as_float((int)hn)) : make_float4(0.f, 0.f, 0.f, 0.f);
     for (int64_t hb = h0; hb < h1; hb += kBinThreads) {
         const int64_t h = hb + threadIdx.x;
-        int d = -1, v = 0;
-        float4 hv = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (h < h1) {
-            v = sensor[h];
-            if (v >= 0 && v < n_sens) {
-                d = div_small(v, rw, inv);
-                hv = make_float4(x[h], y[h], z[h], __int_as_float((int)h));
-            }
+        const int v = vn;
+        const float4 hv = hvn;
+        hn = h + kBinThreads;
+        if (hn < h1) {
+            vn = sensor[hn];
+            hvn = make_float4(x[hn], y[hn], z[hn], __int_as_float((int)hn));
         }
+        int d = -1;
+        if (h < h1 && v >= 0 && v < n_sens) d = div_small(v, rw, inv);
         // rank among this wavefront's hits of the same range, and the
         // wavefront's count per range
         int rank = 0;
@@ -604,7 +618,18 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fine(const float4 *tmp, con
     const int nb = hi - lo;
     for (int i = threadIdx.x; i <= nb; i += kBinThreads) s_h[i] = 0;
     __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += kBinThreads) atomicAdd(&s_h[tsens[cs + j] - lo], 1);
+    constexpr int kFU = 8;                           // loads in flight per thread
+    for (int jb = 0; jb < cnt; jb += kBinThreads * kFU) {
+        int sv[kFU];
+#pragma unroll
+        for (int u = 0; u < kFU; ++u) {
+            const int j = jb + threadIdx.x + u * kBinThreads;
+            sv[u] = j < cnt ? tsens[cs + j] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kFU; ++u)
+            if (sv[u] >= 0) atomicAdd(&s_h[sv[u] - lo], 1);
+    }
     __syncthreads();
     // exclusive scan of the histogram: thread t owns a contiguous run
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -628,9 +653,20 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fine(const float4 *tmp, con
     if (e == n_ev - 1 && r == nr - 1 && threadIdx.x == 0) bin_off[(int64_t)n_ev * n_sens] = cpos[*nent];
     __syncthreads();
     const bool in_lds = cnt <= kFineCap;
-    for (int j = threadIdx.x; j < cnt; j += kBinThreads) {
-        const int p = atomicAdd(&s_h[tsens[cs + j] - lo], 1);
-        if (in_lds) s_pos[p] = (uint16_t)j; else gpos[cs + p] = j;
+    for (int jb = 0; jb < cnt; jb += kBinThreads * kFU) {
+        int sv[kFU];
+#pragma unroll
+        for (int u = 0; u < kFU; ++u) {
+            const int j = jb + threadIdx.x + u * kBinThreads;
+            sv[u] = j < cnt ? tsens[cs + j] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kFU; ++u) {
+            if (sv[u] < 0) continue;
+            const int j = jb + threadIdx.x + u * kBinThreads;
+            const int p = atomicAdd(&s_h[sv[u] - lo], 1);
+            if (in_lds) s_pos[p] = (uint16_t)j; else gpos[cs + p] = j;
+        }
     }
     __syncthreads();
     // each cursor now holds the end of its bin; put every bin back in
@@ -654,8 +690,19 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fine(const float4 *tmp, con
         }
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < cnt; p += kBinThreads)
-        bin_hit[cs + p] = tmp[cs + (in_lds ? (int)s_pos[p] : gpos[cs + p])];
+    for (int pb = 0; pb < cnt; pb += kBinThreads * kFU) {
+        float4 hv[kFU];
+#pragma unroll
+        for (int u = 0; u < kFU; ++u) {
+            const int p = pb + threadIdx.x + u * kBinThreads;
+            if (p < cnt) hv[u] = tmp[cs + (in_lds ? (int)s_pos[p] : gpos[cs + p])];
+        }
+#pragma unroll
+        for (int u = 0; u < kFU; ++u) {
+            const int p = pb + threadIdx.x + u * kBinThreads;
+            if (p < cnt) bin_hit[cs + p] = hv[u];
+        }
+    }
 }
 
 // ------------------------------------------------------------ MD stage
