@@ -319,25 +319,30 @@ __device__ inline void t5_fit(const CutParams &p, const double *x, const double 
     f.t = t; f.z0 = z0; f.chi2_rz = chi2;
 }
 
+// Circumradius |AB| |BC| |CA| / (2 |cross|), with one square root of the
+// product of the squared sides.
 __device__ __forceinline__ double circumradius_d(double ax, double ay, double bx, double by, double cx,
                                                  double cy) {
-    double ab = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
-    double bc = sqrt((cx - bx) * (cx - bx) + (cy - by) * (cy - by));
-    double ca = sqrt((ax - cx) * (ax - cx) + (ay - cy) * (ay - cy));
+    double ab2 = (bx - ax) * (bx - ax) + (by - ay) * (by - ay);
+    double bc2 = (cx - bx) * (cx - bx) + (cy - by) * (cy - by);
+    double ca2 = (ax - cx) * (ax - cx) + (ay - cy) * (ay - cy);
     double cr = (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
-    return ab * bc * ca / (2.0 * fabs(cr));
+    return sqrt(ab2 * bc2 * ca2) / (2.0 * fabs(cr));
 }
 
+// Beam-line curvature |A x B| / (rA rB |B - A|), one square root.
 __device__ __forceinline__ double beam_curv_d(double ax, double ay, double bx, double by) {
-    double rA = sqrt(ax * ax + ay * ay), rB = sqrt(bx * bx + by * by);
-    double dl = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
-    return fabs(ax * by - ay * bx) / (rA * rB * dl);
+    double rA2 = ax * ax + ay * ay, rB2 = bx * bx + by * by;
+    double dl2 = (bx - ax) * (bx - ax) + (by - ay) * (by - ay);
+    return fabs(ax * by - ay * bx) / sqrt(rA2 * rB2 * dl2);
 }
 
-__device__ __forceinline__ double clamp_log(double v) {
-    if (!(v >= 1e-3)) v = (v != v) ? 1e6 : 1e-3;
-    if (v > 1e6) v = 1e6;
-    return log(v);
+// log of v clamped to [1e-3, 1e6] (NaN -> 1e6), in FP32
+__device__ __forceinline__ float clamp_logf(double vd) {
+    float v = (float)vd;
+    if (!(v >= 1e-3f)) v = (vd != vd) ? 1e6f : 1e-3f;
+    if (v > 1e6f) v = 1e6f;
+    return logf(v);
 }
 
 // The 42 DNN inputs (Sec. 2 list plus this project's additions), FP64 -> FP32,
@@ -365,11 +370,11 @@ __device__ inline void t5_fit_outputs(const double *x, const double *y, const Fi
 constexpr int kNFitFeat = 7;
 __device__ inline void t5_fit_features_from(const CutParams &p, const float *fo, double chi2_rphi,
                                             double chi2_rz, float *ff) {
-    ff[0] = (float)clamp_log(p.kb_d * (double)fo[0]);
-    ff[1] = (float)asinh((double)fo[1]);
-    ff[2] = (float)atan2((double)fo[5], (double)fo[4]);
-    ff[3] = (float)log1p(chi2_rphi);
-    ff[4] = (float)log1p(chi2_rz);
+    ff[0] = clamp_logf(p.kb_d * (double)fo[0]);
+    ff[1] = asinhf(fo[1]);
+    ff[2] = atan2f(fo[5], fo[4]);
+    ff[3] = log1pf((float)chi2_rphi);
+    ff[4] = log1pf((float)chi2_rz);
     ff[5] = fo[3];
     ff[6] = fo[2];
 }
@@ -393,14 +398,14 @@ __device__ inline void t5_features_from(const CutParams &p, const double *x, con
     }
     double cin = beam_curv_d(x[0], y[0], x[2], y[2]);
     double cou = beam_curv_d(x[2], y[2], x[4], y[4]);
-    ft[30] = (float)clamp_log(p.kb_d / (2.0 * cin));
-    ft[31] = (float)clamp_log(circumradius_d(x[0], y[0], x[1], y[1], x[2], y[2]));
-    ft[32] = (float)clamp_log(p.kb_d / (2.0 * cou));
-    ft[33] = (float)clamp_log(circumradius_d(x[2], y[2], x[3], y[3], x[4], y[4]));
+    ft[30] = clamp_logf(p.kb_d / (2.0 * cin));
+    ft[31] = clamp_logf(circumradius_d(x[0], y[0], x[1], y[1], x[2], y[2]));
+    ft[32] = clamp_logf(p.kb_d / (2.0 * cou));
+    ft[33] = clamp_logf(circumradius_d(x[2], y[2], x[3], y[3], x[4], y[4]));
     ft[34] = ff[0];
     ft[35] = ff[1];
     ft[36] = ff[2];
-    ft[37] = (float)clamp_log(circumradius_d(x[1], y[1], x[2], y[2], x[3], y[3]));
+    ft[37] = clamp_logf(circumradius_d(x[1], y[1], x[2], y[2], x[3], y[3]));
     ft[38] = ff[3];
     ft[39] = ff[4];
     ft[40] = ff[5];

@@ -1153,27 +1153,25 @@ hipError_t score_rows_dev(const ModelDev &m, const float *X, const int64_t *n_de
 
 // ---------------------------------------------------- per-event offsets
 
-__global__ void k_event_offsets(const int64_t *md_mod_off, const int64_t *ls_off, const int4 *t3_mds,
-                                const int2 *t5_t3, const int64_t *counts, int64_t cap_md, int64_t cap_ls,
-                                int64_t cap_t3, int64_t cap_t5, int32_t n_mod, int32_t n_ev, int64_t *out) {
+// Per-event first indices: MD from the module offsets, LS from the LS CSR by
+// inner MD, T3 from the T3 CSR by inner MD (T3 are sorted by it), T5 by one
+// search over their inner T3 (T5 are sorted by it).
+__global__ void k_event_offsets(const int64_t *md_mod_off, const int64_t *ls_off, const int64_t *t3i_off,
+                                const int2 *t5_t3, const int64_t *counts, int64_t cap_md, int64_t cap_t5,
+                                int32_t n_mod, int32_t n_ev, int64_t *out) {
     int e = threadIdx.x + blockIdx.x * blockDim.x;
     if (e > n_ev) return;
-    int64_t nmd = dev_count(counts + 0, cap_md), nls = dev_count(counts + 1, cap_ls);
-    int64_t nt3 = dev_count(counts + 2, cap_t3), nt5 = dev_count(counts + 3, cap_t5);
+    int64_t nmd = dev_count(counts + 0, cap_md), nt5 = dev_count(counts + 3, cap_t5);
     int64_t md0 = md_mod_off[(int64_t)e * n_mod];
     if (md0 > nmd) md0 = nmd;
-    int64_t ls0 = ls_off[md0];
-    // T3 and T5 are sorted by their inner MD: first one with inner MD >= md0
-    int64_t lo = 0, hi = nt3;
-    while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (t3_mds[mid].x < md0) lo = mid + 1; else hi = mid; }
-    int64_t t30 = lo;
-    lo = 0; hi = nt5;
+    const int64_t ls0 = ls_off[md0], t30 = t3i_off[md0];
+    int64_t lo = 0, hi = nt5;
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
-        if (t3_mds[t5_t3[mid].x].x < md0) lo = mid + 1; else hi = mid;
+        if (t5_t3[mid].x < t30) lo = mid + 1; else hi = mid;
     }
     out[0 * (n_ev + 1) + e] = md0;
-    out[1 * (n_ev + 1) + e] = e == n_ev ? nls : ls0;
+    out[1 * (n_ev + 1) + e] = ls0;
     out[2 * (n_ev + 1) + e] = t30;
     out[3 * (n_ev + 1) + e] = lo;
 }
@@ -1282,8 +1280,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     mark(ev, 13, st);
     if (a.ev_obj_off) {
         hipLaunchKernelGGL(k_event_offsets, dim3((a.n_ev + 64) / 64), dim3(64), 0, st, w.md_mod_off, w.ls_off,
-                           w.t3_mds, o.t5_t3, cnt, w.cap_md, w.cap_ls, w.cap_t3, w.cap_t5, n_mod, a.n_ev,
-                           a.ev_obj_off);
+                           w.t3i_off, o.t5_t3, cnt, w.cap_md, w.cap_t5, n_mod, a.n_ev, a.ev_obj_off);
     }
     mark(ev, 1, st);
     return hipGetLastError();
