@@ -253,7 +253,9 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     x.bin_hit = (float4 *)take(16 * hits);
     // coarse binning tiles: every event adds at most one partial tile
     x.max_bin_tiles = hits / kBinTileHits + ev + 1;
-    x.max_bin_entries = x.max_bin_tiles * kBinRangesMax;
+    // ranges per event: enough for 1024 sensor ids each, or the largest bin_split
+    const int64_t nr_max = (nsens + 1023) / 1024 > 64 ? (nsens + 1023) / 1024 : 64;
+    x.max_bin_entries = x.max_bin_tiles * nr_max;
     x.bin_tbase = (int64_t *)take(8 * (ev + 1));
     x.bin_nent = (int64_t *)take(8);
     x.bin_cnt = (int32_t *)take(4 * x.max_bin_entries);
