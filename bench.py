@@ -308,11 +308,11 @@ def main():
     if a.serve_events > 0:
         from paper_2403_13166_amd import serve as S
         sgeo, pool = S.make_pool(32)
+        slots = [(250_000, 1), (4_800_000, 48), (4_800_000, 48), (4_800_000, 48)]
         served = {"pool": "32 events, PU ~ U[50, 200], 30 tracks + 500 noise hits per unit PU",
-                  "slots": 3, "events_cap": 48, "hits_cap": 4_800_000, "budget_gib": 64, "streams": []}
+                  "slots": slots, "budget_gib": 64, "streams": []}
         for rate in [float(r) for r in a.serve_rates.split(",")]:
-            st = S.serve_stream(sgeo, pool, rate, a.serve_events, 3, 4_800_000, 48, 64 << 30, mode=mode,
-                                precision=prec)
+            st = S.serve_stream(sgeo, pool, rate, a.serve_events, slots, 64 << 30, mode=mode, precision=prec)
             served["streams"].append({k: st[k] for k in ("rate", "events", "events_per_s", "p50_ms", "p99_ms",
                                                          "mean_batch", "max_batch", "max_inflight")})
             print(f"served stream at {rate:.0f} ev/s: {st['events_per_s']:.1f} ev/s, p50 {st['p50_ms']:.2f} ms, "

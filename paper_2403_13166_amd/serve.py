@@ -75,9 +75,26 @@ class Admission:
         return batch
 
 
-def run_loop(requests, executor, admission: Admission, clock=time.perf_counter, sleep=time.sleep,
+def choose_slot(free: list, n_queued: int, limits, busy=()):
+    """Slot for the next batch among the free ones: the smallest slot (by
+    events) that takes every queued request; if none does, the largest free
+    slot, unless a larger slot is busy, in which case None (wait for it).
+    Small slots serve light load with little padding; large ones absorb
+    bursts, and a backlog is not fed one event at a time to a small slot."""
+    fit = [s for s in free if limits(s)[1] >= n_queued]
+    if fit:
+        return min(fit, key=lambda s: (limits(s)[1], limits(s)[0], s))
+    best = max(free, key=lambda s: (limits(s)[1], limits(s)[0], -s))
+    if any(limits(b)[1] > limits(best)[1] for b in busy):
+        return None
+    return best
+
+
+def run_loop(requests, executor, admission: Admission | None = None, clock=time.perf_counter, sleep=time.sleep,
              idle_poll: float = 50e-6):
-    """Serve `requests` (sorted by arrival) on executor.n_slots slots.
+    """Serve `requests` (sorted by arrival) on executor.n_slots slots. With
+    `admission` every slot admits by those limits; without, each slot by its
+    own (executor.slot_limits) and choose_slot picks the slot.
     Returns (done list in finishing order, stats dict)."""
     reqs = sorted(requests, key=lambda r: (r.arrival, r.idx))
     nxt = 0
@@ -105,8 +122,15 @@ def run_loop(requests, executor, admission: Admission, clock=time.perf_counter, 
                 free.append(slot)
                 progressed = True
         while free and queue:
-            batch = admission.take(queue)
-            slot = free.pop()
+            if admission is not None:
+                slot = free.pop()
+                batch = admission.take(queue)
+            else:
+                slot = choose_slot(free, len(queue), executor.slot_limits, list(inflight))
+                if slot is None:
+                    break
+                free.remove(slot)
+                batch = Admission(*executor.slot_limits(slot)).take(queue)
             t_adm = clock() - t0
             h = executor.launch(slot, batch)
             inflight[slot] = (h, batch, t_adm, n_batch)
@@ -339,14 +363,33 @@ class GpuExecutor:
 
     def __init__(self, geometry_blob: bytes, model_blob: bytes, n_slots: int, caps, mode: int = 0,
                  precision: int = 1, device: int = 0, use_graph: bool = True, keep_results: bool = False):
-        self.slots = [_Slot(geometry_blob, model_blob, caps, mode, precision, device, use_graph)
-                      for _ in range(n_slots)]
+        """caps: one Caps for every slot, or a list of n_slots Caps (slots of different sizes)."""
+        per = list(caps) if isinstance(caps, (list, tuple)) else [caps] * n_slots
+        if len(per) != n_slots:
+            raise ValueError("one Caps per slot")
+        self.slots = [_Slot(geometry_blob, model_blob, c, mode, precision, device, use_graph) for c in per]
         self.n_slots = n_slots
         self.keep_results = keep_results
         self.results = {}
 
     def slot_bytes(self) -> int:
         return max(s.nbytes() for s in self.slots)
+
+    def total_bytes(self) -> int:
+        return sum(s.nbytes() for s in self.slots)
+
+    def slot_limits(self, slot: int):
+        """(hits, events) one batch on `slot` may hold."""
+        c = self.slots[slot].caps
+        return c.hits, c.events
+
+    def warm(self, request):
+        """Run one request on every slot (capture the graphs, page memory in)."""
+        for slot in range(self.n_slots):
+            h = self.launch(slot, [request])
+            while not self.poll(h):
+                pass
+            self.finish(h)
 
     def launch(self, slot: int, batch):
         h = self.slots[slot].launch(batch)
@@ -392,28 +435,26 @@ def make_pool(n: int, seed: int = 0):
     return geo, [E.make_event(geo, E.pileup_event_config(float(pu)), (4, seed, i)) for i, pu in enumerate(pus)]
 
 
-def serve_stream(geo, pool, rate: float, n_events: int, n_slots: int, hits_cap: int, events_cap: int,
-                 budget_bytes: int, mode: int = 0, precision: int = 1, seed: int = 0, use_graph: bool = True,
-                 executor=None):
-    """One Poisson stream over events drawn cyclically from `pool`. Returns stats."""
+def serve_stream(geo, pool, rate: float, n_events: int, slots, budget_bytes: int, mode: int = 0,
+                 precision: int = 1, seed: int = 0, use_graph: bool = True, executor=None):
+    """One Poisson stream over events drawn cyclically from `pool`. `slots` is a
+    list of (hits_cap, events_cap), one per slot. Returns stats."""
     from .synth import model as M
     own = executor is None
     if own:
-        executor = GpuExecutor(geo.to_blob(), M.make_model().to_blob(), n_slots,
-                               slot_caps(hits_cap, events_cap), mode, precision, use_graph=use_graph)
-    used = executor.slot_bytes() * executor.n_slots
+        executor = GpuExecutor(geo.to_blob(), M.make_model().to_blob(), len(slots),
+                               [slot_caps(h, e) for h, e in slots], mode, precision, use_graph=use_graph)
+    used = executor.total_bytes()
     if used > budget_bytes:
         raise ValueError(f"{executor.n_slots} slots need {used} B, over the HBM budget {budget_bytes} B")
     pins = [pinned_event(e) for e in pool]
     rng = np.random.default_rng([4, int(rate), seed])
     arr = poisson_arrivals(rate, n_events, rng)
     reqs = [Request(i, float(arr[i]), pool[i % len(pool)].n, pins[i % len(pool)]) for i in range(n_events)]
-    # one untimed batch per slot to page everything in
-    warm = [Request(-1 - s, 0.0, pool[s % len(pool)].n, pins[s % len(pool)]) for s in range(executor.n_slots)]
-    run_loop(warm, executor, Admission(hits_cap, 1))
-    done, stats = run_loop(reqs, executor, Admission(hits_cap, events_cap))
-    stats.update({"rate": rate, "slots": executor.n_slots, "hits_cap": hits_cap, "events_cap": events_cap,
-                  "slot_bytes": executor.slot_bytes(), "budget_bytes": budget_bytes})
+    executor.warm(Request(-1, 0.0, pool[0].n, pins[0]))
+    done, stats = run_loop(reqs, executor)
+    stats.update({"rate": rate, "slots": [list(executor.slot_limits(s)) for s in range(executor.n_slots)],
+                  "slot_bytes": [s.nbytes() for s in executor.slots], "budget_bytes": budget_bytes})
     if own:
         executor.close()
     return stats
@@ -426,20 +467,20 @@ def main():
     ap.add_argument("--rates", default="50,100,200,300,500")
     ap.add_argument("--events", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=48)
-    ap.add_argument("--slots", type=int, default=3)
-    ap.add_argument("--hits-cap", type=int, default=1_600_000)
-    ap.add_argument("--events-cap", type=int, default=16)
+    ap.add_argument("--slots", default="250000x1,4800000x48,4800000x48,4800000x48",
+                    help="comma-separated HITSxEVENTS capacities, one per slot")
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--plain", action="store_true", help="also serve each stream one event at a time")
     a = ap.parse_args()
     geo, pool = make_pool(a.pool)
     budget = int(a.budget_gib * (1 << 30))
+    slots = [tuple(int(v) for v in c.split("x")) for c in a.slots.split(",")]
     for rate in [float(r) for r in a.rates.split(",")]:
-        s = serve_stream(geo, pool, rate, a.events, a.slots, a.hits_cap, a.events_cap, budget)
+        s = serve_stream(geo, pool, rate, a.events, slots, budget)
         s["path"] = "served"
         print(json.dumps(s), flush=True)
         if a.plain:
-            p = serve_stream(geo, pool, rate, a.events, 1, max(e.n for e in pool), 1, budget, use_graph=False)
+            p = serve_stream(geo, pool, rate, a.events, [(max(e.n for e in pool), 1)], budget, use_graph=False)
             p["path"] = "plain"
             print(json.dumps(p), flush=True)
 

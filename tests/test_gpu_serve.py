@@ -80,6 +80,24 @@ def test_served_equals_alone(setup, use_graph):
     ex.close()
 
 
+def test_heterogeneous_slots_equal_alone(setup):
+    from paper_2403_13166_amd.serve import GpuExecutor, Request, pinned_event, run_loop, slot_caps
+    geo, mdl, pool = setup
+    ref = _alone(geo, mdl, pool, 1)
+    big = sum(sorted(e.n for e in pool)[-4:])
+    caps = [slot_caps(max(e.n for e in pool), 1), slot_caps(big, 4)]
+    ex = GpuExecutor(geo.to_blob(), mdl.to_blob(), 2, caps, precision=1, use_graph=True, keep_results=True)
+    pins = [pinned_event(e) for e in pool]
+    arr = [0, 0, 0, 0, 0, 0.003, 0.02]
+    reqs = [Request(i, a, pool[i].n, pins[i]) for i, a in enumerate(arr)]
+    done, st = run_loop(reqs, ex)
+    _say("heterogeneous slots", st, sorted({d.slot for d in done}))
+    assert st["events"] == len(reqs) and {d.slot for d in done} == {0, 1}
+    for i in range(len(reqs)):
+        _check(ex.results[i], ref[i], f"request {i}")
+    ex.close()
+
+
 def test_served_capacity_overflow_recovers(setup):
     from paper_2403_13166_amd.runtime import Caps
     from paper_2403_13166_amd.serve import Admission, GpuExecutor, Request, pinned_event, run_loop

@@ -129,3 +129,50 @@ def test_poisson_arrival_rate():
     arr = poisson_arrivals(200.0, 20000, np.random.default_rng(2))
     assert np.all(np.diff(arr) > 0)
     assert 20000 / arr[-1] == pytest.approx(200.0, rel=0.03)
+
+
+def test_choose_slot_prefers_smallest_fitting():
+    from paper_2403_13166_amd.serve import choose_slot
+    lim = {0: (250_000, 1), 1: (4_000_000, 48), 2: (4_000_000, 48), 3: (1_000_000, 8)}.get
+    assert choose_slot([0, 1, 2, 3], 1, lim) == 0
+    assert choose_slot([1, 2, 3], 1, lim) == 3
+    assert choose_slot([0, 1, 2, 3], 5, lim) == 3
+    assert choose_slot([0, 1, 2, 3], 30, lim) == 1
+    assert choose_slot([0, 3], 30, lim) == 3          # none fits: the largest free one
+    assert choose_slot([0], 30, lim, busy=[1, 2]) is None   # backlog: wait for a large slot
+    assert choose_slot([0], 1, lim, busy=[1, 2]) == 0
+
+
+class SizedExecutor(SimExecutor):
+    """Slots of different sizes; a batch costs fixed + per-event-slot padding."""
+
+    def __init__(self, clock, limits, fixed=2e-4, per_slot=2e-5, per_hit=1e-8):
+        super().__init__(clock, len(limits), fixed, per_hit)
+        self.limits, self.per_slot = limits, per_slot
+
+    def slot_limits(self, slot):
+        return self.limits[slot]
+
+    def launch(self, slot, batch):
+        h = super().launch(slot, batch)
+        h["end"] += self.per_slot * self.limits[slot][1]
+        return h
+
+
+def test_heterogeneous_slots_light_and_heavy_load():
+    limits = [(250_000, 1), (4_000_000, 48), (4_000_000, 48)]
+    clk = Clock()
+    arr = np.arange(100) * 0.01                     # 100 ev/s: the small slot takes them all
+    ex = SizedExecutor(clk, limits)
+    done, st = run_loop(_reqs(arr, [100_000] * 100), ex, clock=clk, sleep=clk.sleep)
+    assert sorted(d.idx for d in done) == list(range(100))
+    assert {d.slot for d in done} == {0} and st["max_batch"] == 1
+    clk = Clock()
+    ex = SizedExecutor(clk, limits)
+    done, st = run_loop(_reqs(np.zeros(300), [100_000] * 300), ex, clock=clk, sleep=clk.sleep)
+    assert sorted(d.idx for d in done) == list(range(300))
+    assert st["max_batch"] == 40                    # 4M hits / 100k per event
+    # the backlog went to the large slots, not one event at a time to the small one
+    assert sum(len(ids) for slot, ids, _ in ex.launched if slot == 0) <= 2
+    for slot, ids, _ in ex.launched:
+        assert len(ids) <= limits[slot][1] and len(ids) * 100_000 <= limits[slot][0] or len(ids) == 1
