@@ -251,7 +251,7 @@ __device__ __forceinline__ void phase2_flush(const S &st, Q &q, int wv, int lane
 // counts gives every tile its output offset; (3) a copy kernel moves each
 // tile's survivors to their final position. Output order = candidate order.
 template <class S, int kPer>
-__global__ __launch_bounds__(kBlock) void k_stage_eval(S st, const int64_t *cand_off,
+__global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, const int64_t *cand_off,
                                                        const int64_t *n_dev, int64_t n_cap,
                                                        const int32_t *tile_anchor, int64_t max_tiles,
                                                        int32_t *tile_cnt, typename S::Rec *scratch,
@@ -721,6 +721,7 @@ struct MDStage {
     float2 *md_rq;
     static constexpr int kEnt = 0;
     static constexpr int kStage = 0;
+    static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = false;
     struct Rec { float4 a; float2 o; int hl, hu; };
     struct Mid {};
@@ -832,6 +833,7 @@ struct LSStage {
     int2 *ls_md;
     static constexpr int kEnt = 1536;
     static constexpr int kStage = 1;
+    static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = true;
     struct Rec { int a, b; };
     struct Mid { int a, b; float cp; int bits; };   // bits: 1 bends positive, 2/4 direction cut on A/B
@@ -967,6 +969,7 @@ struct T3Stage {
     int4 *t3_mds;
     static constexpr int kEnt = 0;
     static constexpr int kStage = 2;
+    static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = false;
     struct Rec { int li, lo, A, B, C; };
     struct Mid {};
@@ -1024,6 +1027,7 @@ struct T5PreStage {
     int2 *pre;
     static constexpr int kEnt = 0;
     static constexpr int kStage = 3;
+    static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = false;
     struct Rec { int u, v; };
     struct Mid {};
@@ -1085,6 +1089,7 @@ struct T5FitStage {
     float *fitf;                  // [n_t5][8]: the fit outputs of each written T5
     static constexpr int kEnt = 0;
     static constexpr int kStage = 4;
+    static constexpr int kMinBlocks = 3;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = false;
     struct Rec { int u, v; float cr, cz; float fo[kNFitOut]; };
     struct Mid {};
