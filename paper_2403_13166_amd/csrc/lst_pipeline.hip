@@ -191,11 +191,10 @@ struct CntF {
     __device__ int64_t operator()(int64_t i) const { return c[i]; }
 };
 
-constexpr int kWin = 512;   // anchors of one tile staged in LDS
-
 // LDS of one tile: the anchor offsets and per-anchor list bases of the tile's
-// window, and (LS only) the module-map tables of the window's modules.
-template <int kEnt>
+// window (at most kWin anchors), and (LS only) the module-map tables of the
+// window's modules.
+template <int kEnt, int kWin>
 struct TileLds {
     int64_t off[kWin + 1];
     int32_t info[kWin][4];
@@ -259,11 +258,13 @@ __global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, cons
     constexpr int kWaves = kBlock / 64;
     constexpr int kTileC = kBlock * kPer;
     constexpr int kSeg = kPer * kWaves;     // output segments, in candidate order
-    __shared__ TileLds<S::kEnt> L;
+    constexpr int kWin = S::kWin;
+    __shared__ TileLds<S::kEnt, (S::kUnitCount ? 1 : S::kWin)> L;
     __shared__ int s_cnt[kSeg];
     __shared__ PhaseQ<S, kPer, S::kTwoPhase> Q;
     const int64_t na = n_dev ? dev_count(n_dev, n_cap) : n_cap;
-    const int64_t total = cand_off[na];
+    // unit-count stages: candidate g is anchor g (no offsets, no decode)
+    const int64_t total = S::kUnitCount ? na : cand_off[na];
     int64_t ntiles = (total + kTileC - 1) / kTileC;
     // max_tiles counts tiles of kMinTile candidates (the scratch size)
     const int64_t max_t = max_tiles * kMinTile / kTileC;
@@ -276,10 +277,10 @@ __global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, cons
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const TileWalk walk(ntiles);
     for (int64_t tile = walk.first; tile < walk.end; tile += walk.step) {
-        const int64_t alo = tile_anchor[tile];
-        const int64_t ahi = (tile + 1 < ntiles) ? (int64_t)tile_anchor[tile + 1] : na - 1;
+        const int64_t alo = S::kUnitCount ? 0 : tile_anchor[tile];
+        const int64_t ahi = S::kUnitCount ? 0 : (tile + 1 < ntiles) ? (int64_t)tile_anchor[tile + 1] : na - 1;
         const int nw = (int)(ahi - alo + 1 < (int64_t)kWin + 1 ? ahi - alo + 1 : (int64_t)kWin + 1);
-        const bool staged = nw <= kWin;
+        const bool staged = !S::kUnitCount && nw <= kWin;
         if (staged) {
             for (int i = threadIdx.x; i <= nw; i += kBlock) {
                 L.off[i] = cand_off[alo + i];
@@ -301,7 +302,11 @@ __global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, cons
             pass[i] = false;
             typename S::Mid mid_i;
             if (g < total) {
-                if (staged) {
+                if constexpr (S::kUnitCount) {
+                    int32_t f[4];
+                    st.info(g, f);
+                    pass[i] = st.eval(g, 0, f, L, rec[i], mid_i);
+                } else if (staged) {
                     int hi = nw;      // largest w in [wlo, nw) with off[w] <= g
                     while (hi - wlo > 1) {
                         int mid = (wlo + hi) >> 1;
@@ -403,7 +408,7 @@ static void run_stage_p(const S &s, const int64_t *n_dev, int64_t n_cap, const W
     static_assert(sizeof(typename S::Rec) <= kMaxRecBytes, "scratch record too large");
     static_assert((kPerMask[S::kStage] & kPer) != 0, "tile size not offered for this stage");
     const int tile = kBlock * kPer;
-    scan(StageCount<S>{s}, n_dev, n_cap, w, w.cand_off, w.tile_anchor, st, tile);
+    if constexpr (!S::kUnitCount) scan(StageCount<S>{s}, n_dev, n_cap, w, w.cand_off, w.tile_anchor, st, tile);
     int nb = (int)(w.max_tiles < eval_blocks ? w.max_tiles : eval_blocks);
     if (nb < 1) nb = 1;
     nb = round_up_xcd(nb);
@@ -721,6 +726,8 @@ struct MDStage {
     float2 *md_rq;
     static constexpr int kEnt = 0;
     static constexpr int kStage = 0;
+    static constexpr int kWin = 512;             // anchors staged per tile
+    static constexpr bool kUnitCount = false;
     static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = false;
     struct Rec { float4 a; float2 o; int hl, hu; };
@@ -831,8 +838,10 @@ struct LSStage {
     CutParams p;
     int32_t n_mod, n_map;
     int2 *ls_md;
-    static constexpr int kEnt = 1536;
+    static constexpr int kEnt = 1024;
     static constexpr int kStage = 1;
+    static constexpr int kWin = 256;             // anchors staged per tile
+    static constexpr bool kUnitCount = false;
     static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = true;
     struct Rec { int a, b; };
@@ -969,6 +978,8 @@ struct T3Stage {
     int4 *t3_mds;
     static constexpr int kEnt = 0;
     static constexpr int kStage = 2;
+    static constexpr int kWin = 512;             // anchors staged per tile
+    static constexpr bool kUnitCount = false;
     static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = false;
     struct Rec { int li, lo, A, B, C; };
@@ -1027,6 +1038,8 @@ struct T5PreStage {
     int2 *pre;
     static constexpr int kEnt = 0;
     static constexpr int kStage = 3;
+    static constexpr int kWin = 512;             // anchors staged per tile
+    static constexpr bool kUnitCount = false;
     static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = false;
     struct Rec { int u, v; };
@@ -1089,6 +1102,8 @@ struct T5FitStage {
     float *fitf;                  // [n_t5][8]: the fit outputs of each written T5
     static constexpr int kEnt = 0;
     static constexpr int kStage = 4;
+    static constexpr int kWin = 512;             // anchors staged per tile
+    static constexpr bool kUnitCount = true;
     static constexpr int kMinBlocks = 3;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = false;
     struct Rec { int u, v; float cr, cz; float fo[kNFitOut]; };
