@@ -131,21 +131,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(F f, const int64_t *n_de
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_partials(int64_t *part, int nb) {
-    // single block of 1024 threads, nb <= 1024
-    __shared__ int64_t s_w[16];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int64_t v = threadIdx.x < nb ? part[threadIdx.x] : 0;
-    int64_t inc = wave_incl_scan(v);
-    if (lane == 63) s_w[wv] = inc;
-    __syncthreads();
-    int64_t off = 0, all = 0;
-    for (int k = 0; k < 16; ++k) { if (k < wv) off += s_w[k]; all += s_w[k]; }
-    __syncthreads();
-    if (threadIdx.x < nb) part[threadIdx.x] = inc + off - v;
-    if (threadIdx.x == 0) part[nb] = all;
-}
-
 template <class F>
 __global__ __launch_bounds__(kBlock) void k_scan_down(F f, const int64_t *n_dev, int64_t n_cap,
                                                       const int64_t *part, int64_t *out,
@@ -153,7 +138,18 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(F f, const int64_t *n_dev,
     int64_t n = n_dev ? dev_count(n_dev, n_cap) : n_cap;
     int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
-    int64_t run = part[blockIdx.x];
+    // this block's offset: the sum of the totals of the blocks before it (and,
+    // for the last block, the grand total)
+    int64_t pre = 0, all = 0;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += kBlock) {
+        const int64_t v = part[k];
+        all += v;
+        if (k < (int)blockIdx.x) pre += v;
+    }
+    int64_t pre_tot, all_tot;
+    block_incl_scan(pre, &pre_tot);
+    block_incl_scan(all, &all_tot);
+    int64_t run = pre_tot;
     for (int64_t base = b0; base < b1; base += kBlock) {
         int64_t i = base + threadIdx.x;
         int64_t c = i < b1 ? f(i) : 0;
@@ -169,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(F f, const int64_t *n_dev,
         }
         run += tot;
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[gridDim.x];
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = all_tot;
 }
 
 template <class F>
@@ -179,7 +175,6 @@ static void scan(F f, const int64_t *n_dev, int64_t n_cap, const Work &w, int64_
     if (nb < 1) nb = 1;
     if (nb > kScanBlocks) nb = kScanBlocks;
     hipLaunchKernelGGL(k_scan_reduce<F>, dim3(nb), dim3(kBlock), 0, st, f, n_dev, n_cap, w.scan_part);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, w.scan_part, nb);
     hipLaunchKernelGGL(k_scan_down<F>, dim3(nb), dim3(kBlock), 0, st, f, n_dev, n_cap, w.scan_part,
                        out, tile_anchor, w.max_tiles, tile);
 }
@@ -456,6 +451,7 @@ constexpr int kBinThreads = 256;
 constexpr int kFineRange = 1024;        // sensor ids of one range, at most
 constexpr int kMaxRanges = kBinRangesMax;
 constexpr int kFineCap = 24576;         // hits one block orders in LDS
+constexpr int kFineThreads = 512;       // threads of a fine-pass block
 
 // q = v / d for 0 <= v < 2^24, d >= 1: FP32 reciprocal estimate, made exact
 __device__ __forceinline__ int div_small(int v, int d, float inv) {
@@ -598,13 +594,13 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const float *x, con
     }
 }
 
-__global__ __launch_bounds__(kBinThreads) void k_bin_fine(const float4 *tmp, const int32_t *tsens, const int64_t *tbase,
+__global__ __launch_bounds__(kFineThreads) void k_bin_fine(const float4 *tmp, const int32_t *tsens, const int64_t *tbase,
                                                           const int64_t *cpos, const int64_t *nent, int n_ev, int n_sens,
                                                           int nr, int rw, int xcd_map, int64_t *bin_off, float4 *bin_hit,
                                                           int32_t *gpos) {
     __shared__ int32_t s_h[kFineRange + 1];
     __shared__ uint16_t s_pos[kFineCap];
-    __shared__ int64_t s_w[kBinThreads / 64];
+    __shared__ int64_t s_w[kFineThreads / 64];
     int e, r;
     if (xcd_map) {
         const int xx = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
@@ -621,14 +617,14 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fine(const float4 *tmp, con
     const int lo = r * rw < n_sens ? r * rw : n_sens;
     const int hi = lo + rw < n_sens ? lo + rw : n_sens;
     const int nb = hi - lo;
-    for (int i = threadIdx.x; i <= nb; i += kBinThreads) s_h[i] = 0;
+    for (int i = threadIdx.x; i <= nb; i += kFineThreads) s_h[i] = 0;
     __syncthreads();
     constexpr int kFU = 8;                           // loads in flight per thread
-    for (int jb = 0; jb < cnt; jb += kBinThreads * kFU) {
+    for (int jb = 0; jb < cnt; jb += kFineThreads * kFU) {
         int sv[kFU];
 #pragma unroll
         for (int u = 0; u < kFU; ++u) {
-            const int j = jb + threadIdx.x + u * kBinThreads;
+            const int j = jb + threadIdx.x + u * kFineThreads;
             sv[u] = j < cnt ? tsens[cs + j] : -1;
         }
 #pragma unroll
@@ -638,7 +634,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fine(const float4 *tmp, con
     __syncthreads();
     // exclusive scan of the histogram: thread t owns a contiguous run
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int per = (nb + kBinThreads - 1) / kBinThreads;
+    const int per = (nb + kFineThreads - 1) / kFineThreads;
     const int a0 = threadIdx.x * per < nb ? threadIdx.x * per : nb;
     const int a1 = a0 + per < nb ? a0 + per : nb;
     int64_t run = 0;
@@ -658,17 +654,17 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fine(const float4 *tmp, con
     if (e == n_ev - 1 && r == nr - 1 && threadIdx.x == 0) bin_off[(int64_t)n_ev * n_sens] = cpos[*nent];
     __syncthreads();
     const bool in_lds = cnt <= kFineCap;
-    for (int jb = 0; jb < cnt; jb += kBinThreads * kFU) {
+    for (int jb = 0; jb < cnt; jb += kFineThreads * kFU) {
         int sv[kFU];
 #pragma unroll
         for (int u = 0; u < kFU; ++u) {
-            const int j = jb + threadIdx.x + u * kBinThreads;
+            const int j = jb + threadIdx.x + u * kFineThreads;
             sv[u] = j < cnt ? tsens[cs + j] : -1;
         }
 #pragma unroll
         for (int u = 0; u < kFU; ++u) {
             if (sv[u] < 0) continue;
-            const int j = jb + threadIdx.x + u * kBinThreads;
+            const int j = jb + threadIdx.x + u * kFineThreads;
             const int p = atomicAdd(&s_h[sv[u] - lo], 1);
             if (in_lds) s_pos[p] = (uint16_t)j; else gpos[cs + p] = j;
         }
@@ -676,7 +672,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fine(const float4 *tmp, con
     __syncthreads();
     // each cursor now holds the end of its bin; put every bin back in
     // local-position (= input) order
-    for (int i = threadIdx.x; i < nb; i += kBinThreads) {
+    for (int i = threadIdx.x; i < nb; i += kFineThreads) {
         const int bs = i == 0 ? 0 : s_h[i - 1], be = s_h[i];
         if (in_lds) {
             for (int k = bs + 1; k < be; ++k) {
@@ -695,16 +691,16 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fine(const float4 *tmp, con
         }
     }
     __syncthreads();
-    for (int pb = 0; pb < cnt; pb += kBinThreads * kFU) {
+    for (int pb = 0; pb < cnt; pb += kFineThreads * kFU) {
         float4 hv[kFU];
 #pragma unroll
         for (int u = 0; u < kFU; ++u) {
-            const int p = pb + threadIdx.x + u * kBinThreads;
+            const int p = pb + threadIdx.x + u * kFineThreads;
             if (p < cnt) hv[u] = tmp[cs + (in_lds ? (int)s_pos[p] : gpos[cs + p])];
         }
 #pragma unroll
         for (int u = 0; u < kFU; ++u) {
-            const int p = pb + threadIdx.x + u * kBinThreads;
+            const int p = pb + threadIdx.x + u * kFineThreads;
             if (p < cnt) bin_hit[cs + p] = hv[u];
         }
     }
@@ -1240,7 +1236,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
                            w.bin_tmp, w.bin_tsens);
         const int xcd_map = a.n_ev >= kXcds ? 1 : 0;
         const int grid_f = xcd_map ? (a.n_ev + kXcds - 1) / kXcds * kXcds * nr : a.n_ev * nr;
-        hipLaunchKernelGGL(k_bin_fine, dim3(grid_f), dim3(kBinThreads), 0, st, (const float4 *)w.bin_tmp,
+        hipLaunchKernelGGL(k_bin_fine, dim3(grid_f), dim3(kFineThreads), 0, st, (const float4 *)w.bin_tmp,
                            (const int32_t *)w.bin_tsens, (const int64_t *)w.bin_tbase, (const int64_t *)w.bin_cpos,
                            (const int64_t *)w.bin_nent, a.n_ev, n_sens, nr, rw, xcd_map, w.bin_off, w.bin_hit,
                            w.bin_gpos);
