@@ -281,7 +281,6 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     x.t3i_off = (int64_t *)take(8 * (md + 1));
     x.cap_t5pre = k->cand;
     x.t5_pre = (int2 *)take(8 * (k->cand > 0 ? k->cand : 1));
-    x.t5_feat = (float *)take(4 * kNFeat * (k->t5 > 0 ? k->t5 : 1));
     x.t5_fitf = (float *)take(4 * 8 * (k->t5 > 0 ? k->t5 : 1));
     x.ev_off = (int64_t *)take(16);
     if (w) *w = x;

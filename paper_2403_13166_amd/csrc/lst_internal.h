@@ -78,8 +78,7 @@ struct Work {
     // T5
     int64_t cap_t5pre;
     int2 *t5_pre;                     // [cap_t5pre] T3 pairs passing the FP32 cuts
-    float *t5_feat;                   // [cap_t5][42] feature rows for the MFMA scorer
-    float *t5_fitf;                   // [cap_t5][8] fit features of each T5 (first kNFitFeat used)
+    float *t5_fitf;                   // [cap_t5][8] fit outputs and chi2s of each T5
     int64_t *ev_off;                  // [2] event offsets of a single-event call
 };
 

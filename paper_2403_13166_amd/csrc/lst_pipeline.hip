@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lst_internal.h"
+#include "lst_mlp_tile.h"
 
 namespace lst {
 
@@ -1162,10 +1163,46 @@ __global__ __launch_bounds__(kBlock) void k_t5_score_f32(T5FitStage<false> s, co
     }
 }
 
-// BF16 MFMA scoring of the T5 features written by the pass above (defined in
-// the scoring translation unit).
-hipError_t score_rows_dev(const ModelDev &m, const float *X, const int64_t *n_dev, int64_t n_cap,
-                          float *out, hipStream_t st);
+// T5 features and the T5-DNN score on the matrix cores: each thread computes
+// one T5's features into the block's LDS tile (standardised BF16), then the
+// block scores the tile with MFMA; feature rows go to HBM only when asked for.
+__global__ __launch_bounds__(kTileRows, 3) void k_t5_score_mfma(T5FitStage<false> s, const int64_t *n_dev,
+                                                             int64_t cap, float *score, float *feat) {
+    __shared__ __align__(16) uint16_t tile[kTileRows * kRowStride];
+    __shared__ MlpFrags fr;
+    mlp_tile_init(&fr, tile, s.mdl);
+    const int64_t n = dev_count(n_dev, cap);
+    for (int64_t row0 = (int64_t)blockIdx.x * kTileRows; row0 < n; row0 += (int64_t)gridDim.x * kTileRows) {
+        const int nrows = n - row0 < kTileRows ? (int)(n - row0) : kTileRows;
+        const int64_t i = row0 + threadIdx.x;
+        __syncthreads();                               // the previous tile is consumed
+        if (threadIdx.x < nrows) {
+            const int2 uv = s.t5_t3[i];
+            T5Anchors t;
+            load_t5_anchors(s.t3_mds, s.md_a, s.mod, s.n_mod, uv.x, uv.y, t);
+            const float4 a = reinterpret_cast<const float4 *>(s.fitf)[2 * i];
+            const float4 b = reinterpret_cast<const float4 *>(s.fitf)[2 * i + 1];
+            const float fo[kNFitOut] = {a.x, a.y, a.z, a.w, b.x, b.y};
+            float ff[kNFitFeat], ft[kNFeat];
+            t5_fit_features_from(s.p, fo, (double)b.z, (double)b.w, ff);
+            t5_features_from(s.p, t.x, t.y, t.z, t.lay, t.endc, ff, ft);
+            if (feat) {
+#pragma unroll
+                for (int k = 0; k < kNFeat; ++k) feat[i * kNFeat + k] = ft[k];
+            }
+            mlp_tile_store_row(tile, threadIdx.x, ft, s.mdl);
+        }
+        __syncthreads();
+        mlp_tile_score(tile, &fr, nrows, s.mdl, score + row0);
+    }
+}
+
+static inline int grid_for_tiles(int64_t n) {
+    int64_t g = (n + kTileRows - 1) / kTileRows;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return (int)g;
+}
 
 // ---------------------------------------------------- per-event offsets
 
@@ -1285,14 +1322,13 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     // a6: features and T5-DNN scores (BF16 MFMA runs over the feature rows;
     // a score cut forces the FP32 path, which the T5 stage itself applied)
     bool mfma = a.mode == 0 && a.precision == 1 && !score_cut;
-    float *feat = o.t5_feat ? o.t5_feat : (mfma ? w.t5_feat : nullptr);
     mark(ev, 12, st);
-    hipLaunchKernelGGL(k_t5_score_f32, dim3(grid_for(w.cap_t5)), dim3(kBlock), 0, st, t5,
-                       cnt + LST_COUNT_T5, w.cap_t5, o.t5_score, feat, (int)!mfma);
-    if (mfma) {
-        hipError_t e = score_rows_dev(a.m, feat, cnt + LST_COUNT_T5, w.cap_t5, o.t5_score, st);
-        if (e != hipSuccess) return e;
-    }
+    if (mfma)
+        hipLaunchKernelGGL(k_t5_score_mfma, dim3(grid_for_tiles(w.cap_t5)), dim3(kTileRows), 0, st, t5,
+                           cnt + LST_COUNT_T5, w.cap_t5, o.t5_score, o.t5_feat);
+    else
+        hipLaunchKernelGGL(k_t5_score_f32, dim3(grid_for(w.cap_t5)), dim3(kBlock), 0, st, t5,
+                           cnt + LST_COUNT_T5, w.cap_t5, o.t5_score, o.t5_feat, 1);
     mark(ev, 13, st);
     if (a.ev_obj_off) {
         hipLaunchKernelGGL(k_event_offsets, dim3((a.n_ev + 64) / 64), dim3(64), 0, st, w.md_mod_off, w.ls_off,

@@ -183,13 +183,6 @@ static inline int blocks_for(int64_t n, int rows_per_block) {
     return (int)b;
 }
 
-hipError_t score_rows_dev(const ModelDev &m, const float *X, const int64_t *n_dev, int64_t n_cap, float *out,
-                          hipStream_t st) {
-    hipLaunchKernelGGL(k_score_mfma<0>, dim3(blocks_for(n_cap, 256)), dim3(256), 0, st, m, (const void *)X,
-                       n_dev, n_cap, out);
-    return hipGetLastError();
-}
-
 hipError_t run_score(const ModelDev &m, const void *X, int dtype, int64_t n, float *out, int precision,
                      hipStream_t st) {
     if (precision == 1) {
