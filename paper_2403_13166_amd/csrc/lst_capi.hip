@@ -262,7 +262,6 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     x.bin_cpos = (int64_t *)take(8 * (x.max_bin_entries + 1));
     x.bin_tmp = (float4 *)take(16 * hits);
     x.bin_tsens = (int32_t *)take(4 * hits);
-    x.bin_gpos = (int32_t *)take(4 * hits);
     x.cand_off = (int64_t *)take(8 * (anchors + 1));
     x.scan_part = (int64_t *)take(8 * (kScanBlocks + 1));
     x.tile_anchor = (int32_t *)take(4 * (max_tiles + 1));

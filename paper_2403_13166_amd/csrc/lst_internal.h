@@ -54,7 +54,6 @@ struct Work {
     int64_t *bin_cpos;                // [max_bin_entries + 1] their exclusive scan
     float4 *bin_tmp;                  // [cap_hits] hits partitioned by (event, range)
     int32_t *bin_tsens;               // [cap_hits] their sensor ids
-    int32_t *bin_gpos;                // [cap_hits] local positions of ranges too large for LDS
     // per-stage scratch
     int64_t *cand_off;                // [n_anchor_cap + 1]
     int64_t *scan_part;               // [kScanBlocks + 1]

@@ -229,12 +229,26 @@ __device__ __forceinline__ void phase2_flush(const S &st, Q &q, int wv, int lane
     wave_sync_lds();
     if (lane < n) q.res[wv][q.slot[wv][lane]] = st.eval2(q.e[wv][lane]) ? 1 : 0;
     const int rest = qn - n;
-    typename S::Mid te;
-    uint16_t ts = 0;
-    wave_sync_lds();
-    if (lane < rest) { te = q.e[wv][n + lane]; ts = q.slot[wv][n + lane]; }
-    wave_sync_lds();
-    if (lane < rest) { q.e[wv][lane] = te; q.slot[wv][lane] = ts; }
+    if (rest > 0) {                    // wavefront-uniform
+        // moved word by word: an aggregate copy between LDS and registers
+        // would be staged through private (scratch) memory
+        constexpr int kWords = sizeof(typename S::Mid) / 4;
+        static_assert(sizeof(typename S::Mid) % 4 == 0, "queue entries are whole words");
+        wave_sync_lds();
+        const int src = n + (lane < rest ? lane : 0);
+        uint32_t te[kWords];
+        const uint32_t *ps = reinterpret_cast<const uint32_t *>(&q.e[wv][src]);
+#pragma unroll
+        for (int k = 0; k < kWords; ++k) te[k] = ps[k];
+        const uint16_t ts = q.slot[wv][src];
+        wave_sync_lds();
+        if (lane < rest) {
+            uint32_t *pd = reinterpret_cast<uint32_t *>(&q.e[wv][lane]);
+#pragma unroll
+            for (int k = 0; k < kWords; ++k) pd[k] = te[k];
+            q.slot[wv][lane] = ts;
+        }
+    }
     wave_sync_lds();
 }
 
@@ -438,20 +452,22 @@ static void run_stage(const S &s, const int64_t *n_dev, int64_t n_cap, const Wor
 //  * Coarse pass: each event's hits are cut into tiles of kBinTile; a tile
 //    counts its hits per sensor range (ranges of at most kFineRange sensor
 //    ids); an exclusive scan over (event, range, tile) gives every tile's
-//    output base per range; the tile then scatters its hits, ranked within
-//    the tile by wavefront ballots, so each range keeps the input order.
-//  * Fine pass: one block per (event, range) sorts that range's hits by
-//    sensor in LDS (histogram, scan, scatter of 16-bit local positions, then
-//    each bin is put back in local-position order, which is input order) and
-//    writes the bin offsets and the binned hits with coalesced stores. A range
-//    with more hits than LDS holds is done the same way through global memory.
+//    output base per range; the tile then scatters its hits, each ranked
+//    among the tile's earlier hits of its range, so each range keeps the
+//    input order.
+//  * Fine pass: one block per (event, range) ranks that range's hits by
+//    sensor the same way, writes the bin offsets and moves every hit to its
+//    binned position.
+// Ranks come from ballots: the lanes holding the same key are found with one
+// ballot per key bit, and per-wavefront running counters in LDS carry the
+// count of earlier rounds, so the order within a key is the input order
+// without atomics or sorting.
 // Hits with an out-of-range sensor id set error bit 0 and are dropped.
 
 constexpr int kBinTile = kBinTileHits;  // hits of one coarse tile
 constexpr int kBinThreads = 256;
 constexpr int kFineRange = 1024;        // sensor ids of one range, at most
 constexpr int kMaxRanges = kBinRangesMax;
-constexpr int kFineCap = 24576;         // hits one block orders in LDS
 constexpr int kFineThreads = 512;       // threads of a fine-pass block
 
 // q = v / d for 0 <= v < 2^24, d >= 1: FP32 reciprocal estimate, made exact
@@ -539,11 +555,53 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const int32_t *sensor
     for (int r = threadIdx.x; r < nr; r += kBinThreads) cnt[base + (int64_t)r * nt] = s_c[r];
 }
 
+// Lanes of the wavefront whose key equals this lane's key (key in [0, 2^nbits),
+// valid lanes only): one ballot per key bit.
+__device__ __forceinline__ unsigned long long match_key(int key, bool valid, int nbits) {
+    unsigned long long m = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (key >> b) & 1;
+        const unsigned long long bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+// Stable rank of this lane's key among the wavefront's earlier keys, counting
+// the earlier rounds through the wavefront's running counters wc[key]. Every
+// lane of the wavefront calls it (uniform control flow).
+__device__ __forceinline__ int wave_rank(int32_t *wc, int key, bool valid, int nbits) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long m = match_key(key, valid, nbits);
+    const unsigned long long below = m & ((1ull << lane) - 1ull);
+    const int prev = valid ? wc[key] : 0;
+    wave_sync_lds();
+    if (valid && below == 0) wc[key] = prev + __popcll(m);   // the group's first lane
+    wave_sync_lds();
+    return prev + __popcll(below);
+}
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));   // native vector (copies stay in registers)
+
+__device__ __forceinline__ int key_bits(int n) { return n > 1 ? 32 - __clz(n - 1) : 0; }
+
+// Wait for every outstanding vector-memory access of this wavefront. Stores
+// count in the same counter as loads; after a branch the compiler can lose
+// track of which loads are done and then waits for all, including the stores
+// just issued, before each later use of a loaded value. Waiting once for the
+// loads of a batch before its stores avoids that serialisation.
+__device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // vmcnt(0)
+
+// Coarse pass: wavefront w of a tile takes the tile's hits [w * 1024, (w + 1) * 1024)
+// in 16 rounds of 64, all loaded up front, and ranks each hit among the
+// wavefront's hits of the same range (running counters per wavefront); the
+// wavefronts' counts then give every hit its position in input order.
 __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const float *x, const float *y, const float *z,
                                                              const int32_t *sensor, const int64_t *ev_off, int n_ev,
                                                              int n_sens, int nr, int rw, const int64_t *tbase,
                                                              const int64_t *cpos, float4 *tmp, int32_t *tsens) {
     constexpr int kWaves = kBinThreads / 64;
+    constexpr int kRounds = kBinTile / kBinThreads;
     __shared__ int64_t s_base[kMaxRanges];
     __shared__ int32_t s_wc[kWaves][kMaxRanges];
     int e;
@@ -552,56 +610,70 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const float *x, con
     const int64_t h0 = ev_off[e] + t * kBinTile;
     const int64_t h1 = h0 + kBinTile < ev_off[e + 1] ? h0 + kBinTile : ev_off[e + 1];
     const int64_t ebase = tbase[e] * nr + t;
-    for (int r = threadIdx.x; r < nr; r += kBinThreads) s_base[r] = cpos[ebase + (int64_t)r * nt];
+    for (int r = threadIdx.x; r < nr; r += kBinThreads) {
+        s_base[r] = cpos[ebase + (int64_t)r * nt];
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) s_wc[w][r] = 0;
+    }
     const float inv = 1.0f / (float)rw;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // the next round's hit is loaded while the current one is ranked
-    int64_t hn = h0 + threadIdx.x;
-    int vn = hn < h1 ? sensor[hn] : -1;
-    float4 hvn = hn < h1 ? make_float4(x[hn], y[hn], z[hn], __int_as_float((int)hn)) : make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int64_t hb = h0; hb < h1; hb += kBinThreads) {
-        const int64_t h = hb + threadIdx.x;
-        const int v = vn;
-        const float4 hv = hvn;
-        hn = h + kBinThreads;
-        if (hn < h1) {
-            vn = sensor[hn];
-            hvn = make_float4(x[hn], y[hn], z[hn], __int_as_float((int)hn));
+    const int nbits = key_bits(nr);
+    const int64_t hw = h0 + (int64_t)wv * (kRounds * 64) + lane;
+    int sv[kRounds];
+    float4 hv[kRounds];
+#pragma unroll
+    for (int j = 0; j < kRounds; ++j) {
+        const int64_t h = hw + j * 64;
+        sv[j] = -1;
+        if (h < h1) {
+            sv[j] = sensor[h];
+            hv[j] = make_float4(x[h], y[h], z[h], __int_as_float((int)h));
         }
-        int d = -1;
-        if (h < h1 && v >= 0 && v < n_sens) d = div_small(v, rw, inv);
-        // rank among this wavefront's hits of the same range, and the
-        // wavefront's count per range
-        int rank = 0;
-        for (int dd = 0; dd < nr; ++dd) {
-            const unsigned long long m = __ballot(d == dd);
-            if (lane == 0) s_wc[wv][dd] = __popcll(m);
-            if (d == dd) rank = __popcll(m & ((1ull << lane) - 1ull));
+    }
+    __syncthreads();
+    int dr[kRounds];           // range << 16 | rank within the wavefront's hits of that range
+#pragma unroll
+    for (int j = 0; j < kRounds; ++j) {
+        const bool ok = sv[j] >= 0 && sv[j] < n_sens;
+        const int d = ok ? div_small(sv[j], rw, inv) : 0;
+        const int rk = wave_rank(s_wc[wv], d, ok, nbits);
+        dr[j] = ok ? (d << 16) | rk : -1;
+    }
+    __syncthreads();
+    // exclusive prefix over the wavefronts, per range
+    for (int r = threadIdx.x; r < nr; r += kBinThreads) {
+        int run = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const int c = s_wc[w][r];
+            s_wc[w][r] = run;
+            run += c;
         }
-        __syncthreads();
-        if (d >= 0) {
-            int64_t pos = s_base[d] + rank;
-            for (int w = 0; w < wv; ++w) pos += s_wc[w][d];
-            tmp[pos] = hv;
-            tsens[pos] = v;
-        }
-        __syncthreads();
-        for (int r = threadIdx.x; r < nr; r += kBinThreads) {
-            int sum = 0;
-            for (int w = 0; w < kWaves; ++w) sum += s_wc[w][r];
-            s_base[r] += sum;
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+    vmem_wait_all();
+#pragma unroll
+    for (int j = 0; j < kRounds; ++j) {
+        if (dr[j] < 0) continue;
+        const int d = dr[j] >> 16;
+        const int64_t pos = s_base[d] + s_wc[wv][d] + (dr[j] & 0xffff);
+        tmp[pos] = hv[j];
+        tsens[pos] = sv[j];
     }
 }
 
+// Fine pass, one block per (event, range): wavefront w takes the range's hits
+// [w * chunk, (w + 1) * chunk) and counts them per sensor (running counters per
+// wavefront and sensor); per sensor, the counts of the wavefronts give their
+// offsets and the sensor totals the bin offsets, which turn the counters into
+// output cursors; ranking the same hits again then yields each hit's binned
+// position directly.
 __global__ __launch_bounds__(kFineThreads) void k_bin_fine(const float4 *tmp, const int32_t *tsens, const int64_t *tbase,
                                                           const int64_t *cpos, const int64_t *nent, int n_ev, int n_sens,
-                                                          int nr, int rw, int xcd_map, int64_t *bin_off, float4 *bin_hit,
-                                                          int32_t *gpos) {
-    __shared__ int32_t s_h[kFineRange + 1];
-    __shared__ uint16_t s_pos[kFineCap];
-    __shared__ int64_t s_w[kFineThreads / 64];
+                                                          int nr, int rw, int xcd_map, int64_t *bin_off, float4 *bin_hit) {
+    constexpr int kW = kFineThreads / 64;
+    __shared__ int32_t s_wc[kW][kFineRange];
+    __shared__ int64_t s_w[kW];
     int e, r;
     if (xcd_map) {
         const int xx = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
@@ -614,95 +686,91 @@ __global__ __launch_bounds__(kFineThreads) void k_bin_fine(const float4 *tmp, co
     }
     const int64_t nt = tbase[e + 1] - tbase[e];
     const int64_t cs = cpos[tbase[e] * nr + (int64_t)r * nt], ce = cpos[tbase[e] * nr + (int64_t)(r + 1) * nt];
-    const int cnt = (int)(ce - cs);
+    const int64_t cnt = ce - cs;
     const int lo = r * rw < n_sens ? r * rw : n_sens;
     const int hi = lo + rw < n_sens ? lo + rw : n_sens;
     const int nb = hi - lo;
-    for (int i = threadIdx.x; i <= nb; i += kFineThreads) s_h[i] = 0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < nb; k += kFineThreads)
+#pragma unroll
+        for (int w = 0; w < kW; ++w) s_wc[w][k] = 0;
     __syncthreads();
-    constexpr int kFU = 8;                           // loads in flight per thread
-    for (int jb = 0; jb < cnt; jb += kFineThreads * kFU) {
-        int sv[kFU];
+    const int64_t chunk = (cnt + kW * 64 - 1) / (kW * 64) * 64;
+    const int64_t j0 = wv * chunk, j1 = j0 + chunk < cnt ? j0 + chunk : cnt;
+    const int nbits = key_bits(nb);
+    constexpr int kFU = 4;                           // rounds loaded ahead
+    for (int64_t jb = j0; jb < j1; jb += 64 * kFU) {
+        // loads from a clamped index, so none sits behind a branch (each
+        // would then be waited for on its own)
+        int kv[kFU];
 #pragma unroll
         for (int u = 0; u < kFU; ++u) {
-            const int j = jb + threadIdx.x + u * kFineThreads;
-            sv[u] = j < cnt ? tsens[cs + j] : -1;
+            const int64_t j = jb + u * 64 + lane;
+            kv[u] = tsens[cs + (j < j1 ? j : j1 - 1)];
         }
 #pragma unroll
-        for (int u = 0; u < kFU; ++u)
-            if (sv[u] >= 0) atomicAdd(&s_h[sv[u] - lo], 1);
+        for (int u = 0; u < kFU; ++u) kv[u] = jb + u * 64 + lane < j1 ? kv[u] - lo : -1;
+#pragma unroll
+        for (int u = 0; u < kFU; ++u) {
+            if (jb + u * 64 < j1) {                  // wavefront-uniform
+                const bool ok = kv[u] >= 0;
+                (void)wave_rank(s_wc[wv], ok ? kv[u] : 0, ok, nbits);
+            }
+        }
     }
     __syncthreads();
-    // exclusive scan of the histogram: thread t owns a contiguous run
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int per = (nb + kFineThreads - 1) / kFineThreads;
-    const int a0 = threadIdx.x * per < nb ? threadIdx.x * per : nb;
-    const int a1 = a0 + per < nb ? a0 + per : nb;
-    int64_t run = 0;
-    for (int i = a0; i < a1; ++i) run += s_h[i];
-    const int64_t inc = wave_incl_scan(run);
+    // per sensor: the wavefronts' offsets, then the sensors' exclusive scan
+    // (thread t owns sensors 2t and 2t + 1); counters become output cursors
+    int tot[2] = {0, 0};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int k = 2 * threadIdx.x + q;
+        if (k >= nb) continue;
+        int run = 0;
+#pragma unroll
+        for (int w = 0; w < kW; ++w) {
+            const int c = s_wc[w][k];
+            s_wc[w][k] = run;
+            run += c;
+        }
+        tot[q] = run;
+    }
+    const int64_t inc = wave_incl_scan((int64_t)(tot[0] + tot[1]));
     if (lane == 63) s_w[wv] = inc;
     __syncthreads();
-    int64_t acc = inc - run;
+    int64_t acc = inc - tot[0] - tot[1];
     for (int k = 0; k < wv; ++k) acc += s_w[k];
-    __syncthreads();
-    for (int i = a0; i < a1; ++i) {
-        const int c = s_h[i];
-        s_h[i] = (int32_t)acc;                    // exclusive offset, then cursor
-        bin_off[(int64_t)e * n_sens + lo + i] = cs + acc;
-        acc += c;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int k = 2 * threadIdx.x + q;
+        if (k < nb) {
+            bin_off[(int64_t)e * n_sens + lo + k] = cs + acc;
+#pragma unroll
+            for (int w = 0; w < kW; ++w) s_wc[w][k] += (int32_t)acc;
+        }
+        acc += tot[q];
     }
     if (e == n_ev - 1 && r == nr - 1 && threadIdx.x == 0) bin_off[(int64_t)n_ev * n_sens] = cpos[*nent];
     __syncthreads();
-    const bool in_lds = cnt <= kFineCap;
-    for (int jb = 0; jb < cnt; jb += kFineThreads * kFU) {
-        int sv[kFU];
+    for (int64_t jb = j0; jb < j1; jb += 64 * kFU) {
+        int kv[kFU];
+        f32x4_t hv[kFU];
 #pragma unroll
         for (int u = 0; u < kFU; ++u) {
-            const int j = jb + threadIdx.x + u * kFineThreads;
-            sv[u] = j < cnt ? tsens[cs + j] : -1;
+            const int64_t j = jb + u * 64 + lane, jc = j < j1 ? j : j1 - 1;
+            kv[u] = tsens[cs + jc];
+            hv[u] = reinterpret_cast<const f32x4_t *>(tmp)[cs + jc];
         }
+        vmem_wait_all();
+#pragma unroll
+        for (int u = 0; u < kFU; ++u) kv[u] = jb + u * 64 + lane < j1 ? kv[u] - lo : -1;
 #pragma unroll
         for (int u = 0; u < kFU; ++u) {
-            if (sv[u] < 0) continue;
-            const int j = jb + threadIdx.x + u * kFineThreads;
-            const int p = atomicAdd(&s_h[sv[u] - lo], 1);
-            if (in_lds) s_pos[p] = (uint16_t)j; else gpos[cs + p] = j;
-        }
-    }
-    __syncthreads();
-    // each cursor now holds the end of its bin; put every bin back in
-    // local-position (= input) order
-    for (int i = threadIdx.x; i < nb; i += kFineThreads) {
-        const int bs = i == 0 ? 0 : s_h[i - 1], be = s_h[i];
-        if (in_lds) {
-            for (int k = bs + 1; k < be; ++k) {
-                const uint16_t v = s_pos[k];
-                int j = k - 1;
-                while (j >= bs && s_pos[j] > v) { s_pos[j + 1] = s_pos[j]; --j; }
-                s_pos[j + 1] = v;
+            if (jb + u * 64 < j1) {                  // wavefront-uniform
+                const bool ok = kv[u] >= 0;
+                const int p = wave_rank(s_wc[wv], ok ? kv[u] : 0, ok, nbits);
+                if (ok) reinterpret_cast<f32x4_t *>(bin_hit)[cs + p] = hv[u];
             }
-        } else {
-            for (int k = bs + 1; k < be; ++k) {
-                const int v = gpos[cs + k];
-                int j = k - 1;
-                while (j >= bs && gpos[cs + j] > v) { gpos[cs + j + 1] = gpos[cs + j]; --j; }
-                gpos[cs + j + 1] = v;
-            }
-        }
-    }
-    __syncthreads();
-    for (int pb = 0; pb < cnt; pb += kFineThreads * kFU) {
-        float4 hv[kFU];
-#pragma unroll
-        for (int u = 0; u < kFU; ++u) {
-            const int p = pb + threadIdx.x + u * kFineThreads;
-            if (p < cnt) hv[u] = tmp[cs + (in_lds ? (int)s_pos[p] : gpos[cs + p])];
-        }
-#pragma unroll
-        for (int u = 0; u < kFU; ++u) {
-            const int p = pb + threadIdx.x + u * kFineThreads;
-            if (p < cnt) bin_hit[cs + p] = hv[u];
         }
     }
 }
@@ -1275,8 +1343,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
         const int grid_f = xcd_map ? (a.n_ev + kXcds - 1) / kXcds * kXcds * nr : a.n_ev * nr;
         hipLaunchKernelGGL(k_bin_fine, dim3(grid_f), dim3(kFineThreads), 0, st, (const float4 *)w.bin_tmp,
                            (const int32_t *)w.bin_tsens, (const int64_t *)w.bin_tbase, (const int64_t *)w.bin_cpos,
-                           (const int64_t *)w.bin_nent, a.n_ev, n_sens, nr, rw, xcd_map, w.bin_off, w.bin_hit,
-                           w.bin_gpos);
+                           (const int64_t *)w.bin_nent, a.n_ev, n_sens, nr, rw, xcd_map, w.bin_off, w.bin_hit);
     }
     mark(ev, 3, st);
 
