@@ -663,11 +663,11 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const float *x, con
 }
 
 // Fine pass, one block per (event, range): wavefront w takes the range's hits
-// [w * chunk, (w + 1) * chunk) and counts them per sensor (running counters per
+// [w * chunk, (w + 1) * chunk) and counts them per sensor (counters per
 // wavefront and sensor); per sensor, the counts of the wavefronts give their
 // offsets and the sensor totals the bin offsets, which turn the counters into
-// output cursors; ranking the same hits again then yields each hit's binned
-// position directly.
+// output cursors; ranking the same hits in order then yields each hit's
+// binned position directly.
 __global__ __launch_bounds__(kFineThreads) void k_bin_fine(const float4 *tmp, const int32_t *tsens, const int64_t *tbase,
                                                           const int64_t *cpos, const int64_t *nent, int n_ev, int n_sens,
                                                           int nr, int rw, int xcd_map, int64_t *bin_off, float4 *bin_hit) {
@@ -710,13 +710,10 @@ __global__ __launch_bounds__(kFineThreads) void k_bin_fine(const float4 *tmp, co
         }
 #pragma unroll
         for (int u = 0; u < kFU; ++u) kv[u] = jb + u * 64 + lane < j1 ? kv[u] - lo : -1;
+        // counts only: their order does not matter
 #pragma unroll
-        for (int u = 0; u < kFU; ++u) {
-            if (jb + u * 64 < j1) {                  // wavefront-uniform
-                const bool ok = kv[u] >= 0;
-                (void)wave_rank(s_wc[wv], ok ? kv[u] : 0, ok, nbits);
-            }
-        }
+        for (int u = 0; u < kFU; ++u)
+            if (kv[u] >= 0) atomicAdd(&s_wc[wv][kv[u]], 1);
     }
     __syncthreads();
     // per sensor: the wavefronts' offsets, then the sensors' exclusive scan
