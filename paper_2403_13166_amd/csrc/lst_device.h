@@ -319,6 +319,92 @@ __device__ inline void t5_fit(const CutParams &p, const double *x, const double 
     f.t = t; f.z0 = z0; f.chi2_rz = chi2;
 }
 
+// FP32 estimate of a quintuplet's r-z chi2 from its anchors (x, y, z, transverse
+// radius r): the steps of circle_fit5 and t5_fit in single precision (moments
+// in the chord frame, Taubin root by Newton from 0, arc lengths at the fitted
+// curvature, weighted line fit).
+// NaN when a step degenerates (zero chord, non-increasing arc length, no
+// spread in s), where the FP64 fit decides alone.
+__device__ inline float t5_chi2rz_f32(const CutParams &p, const float *x, const float *y, const float *z,
+                                      const float *r, const bool *endc) {
+    const float isrphi = 1.0f / p.srphi, isr = 1.0f / p.sr, isz = 1.0f / p.sz;
+    float w[5], W = 0.0f, xm = 0.0f, ym = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const float is = endc[i] ? isr : isrphi;
+        w[i] = is * is; W += w[i]; xm += w[i] * x[i]; ym += w[i] * y[i];
+    }
+    const float iW = 1.0f / W;
+    xm *= iW; ym *= iW;
+    const float cx = x[4] - x[0], cy = y[4] - y[0], cl = sqrtf(cx * cx + cy * cy);
+    if (!(cl > 0.0f)) return __builtin_nanf("");
+    const float ca = cx / cl, sa = cy / cl;
+    float u[5], v[5], Mxx = 0.0f, Myy = 0.0f, Mxy = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const float wi = w[i] * iW, u0 = x[i] - xm, v0 = y[i] - ym;
+        u[i] = ca * u0 + sa * v0; v[i] = -sa * u0 + ca * v0;
+        Mxx += wi * u[i] * u[i]; Myy += wi * v[i] * v[i]; Mxy += wi * u[i] * v[i];
+    }
+    const float Mz = Mxx + Myy;
+    float Mxz = 0.0f, Myz = 0.0f, varz = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const float wi = w[i] * iW, zt = u[i] * u[i] + v[i] * v[i] - Mz;
+        Mxz += wi * u[i] * zt; Myz += wi * v[i] * zt; varz += wi * zt * zt;
+    }
+    const float cov = Mxx * Myy - Mxy * Mxy;
+    const float c3 = 4.0f * Mz, c2 = -4.0f * Mz * Mz - varz;
+    const float c1 = varz * Mz + 4.0f * cov * Mz - Mxz * Mxz - Myz * Myz;
+    const float c0 = Mxz * (Mxz * Myy - Myz * Mxy) + Myz * (Myz * Mxx - Mxz * Mxy) - varz * cov;
+    float eta = 0.0f, fprev = __builtin_huge_valf();
+    for (int it = 0; it < 16; ++it) {
+        const float fv = c0 + eta * (c1 + eta * (c2 + eta * c3));
+        if (fabsf(fv) >= fabsf(fprev)) break;
+        fprev = fv;
+        const float df = c1 + eta * (2.0f * c2 + eta * 3.0f * c3);
+        const float nx = eta - fv / df;
+        if (!(nx >= 0.0f)) { eta = 0.0f; break; }
+        if (fabsf(nx - eta) <= 1e-6f * fabsf(nx)) { eta = nx; break; }
+        eta = nx;
+    }
+    const float k1[3] = {varz - 4.0f * Mz * eta, Mxz, Myz};
+    const float k2[3] = {Mxz, Mxx - eta, Mxy};
+    const float k3[3] = {Myz, Mxy, Myy - eta};
+    float bA = 0.0f, bB = 0.0f, bC = 0.0f, bn = -1.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float *a = c == 0 ? k2 : c == 1 ? k3 : k1;
+        const float *b = c == 0 ? k3 : c == 1 ? k1 : k2;
+        const float v0 = a[1] * b[2] - a[2] * b[1], v1 = a[2] * b[0] - a[0] * b[2], v2 = a[0] * b[1] - a[1] * b[0];
+        const float nn = v0 * v0 + v1 * v1 + v2 * v2;
+        if (nn > bn) { bn = nn; bA = v0; bB = v1; bC = v2; }
+    }
+    const float cf = fabsf(bA) / sqrtf(bB * bB + bC * bC + 4.0f * bA * bA * Mz);
+    float sv[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) sv[i] = arc_len_f(cf, r[i]);
+    if (!(sv[4] > sv[0])) return __builtin_nanf("");
+    const float kAE = fabsf((z[4] - z[0]) / (sv[4] - sv[0]));
+    const float ike = isr / (kAE > 0.1f ? kAE : 0.1f);
+    float wz[5], Wt = 0.0f, sm = 0.0f, zm = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const float iv = endc[i] ? ike : isz;
+        wz[i] = iv * iv; Wt += wz[i]; sm += wz[i] * sv[i]; zm += wz[i] * z[i];
+    }
+    sm /= Wt; zm /= Wt;
+    float Sss = 0.0f, Ssz = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { Sss += wz[i] * (sv[i] - sm) * (sv[i] - sm); Ssz += wz[i] * (sv[i] - sm) * (z[i] - zm); }
+    if (!(Sss > 0.0f)) return __builtin_nanf("");
+    const float t = Ssz / Sss, z0 = zm - t * sm;
+    float chi2 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { const float d = z[i] - z0 - t * sv[i]; chi2 += d * d * wz[i]; }
+    return chi2;
+}
+
 // Circumradius |AB| |BC| |CA| / (2 |cross|), with one square root of the
 // product of the squared sides.
 __device__ __forceinline__ double circumradius_d(double ax, double ay, double bx, double by, double cx,

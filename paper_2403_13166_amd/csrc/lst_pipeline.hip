@@ -215,7 +215,20 @@ struct PhaseQ<S, kPer, true> {
     typename S::Mid e[kBlock / 64][kQCap];
     uint16_t slot[kBlock / 64][kQCap];
     uint8_t res[kBlock / 64][kPer * 64];
+    // stages whose phase 2 produces the output record keep it per slot
+    typename S::Rec rec[S::kPhase2Rec ? kBlock / 64 : 1][S::kPhase2Rec ? kPer * 64 : 1];
 };
+
+// copy of a record of whole 32-bit words (keeps LDS <-> register copies out of
+// private memory)
+template <class T>
+__device__ __forceinline__ void copy_words(T &dst, const T &src) {
+    static_assert(sizeof(T) % 4 == 0, "records are whole words");
+    const uint32_t *ps = reinterpret_cast<const uint32_t *>(&src);
+    uint32_t *pd = reinterpret_cast<uint32_t *>(&dst);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) pd[k] = ps[k];
+}
 
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -227,7 +240,14 @@ __device__ __forceinline__ void wave_sync_lds() {
 template <class S, class Q>
 __device__ __forceinline__ void phase2_flush(const S &st, Q &q, int wv, int lane, int n, int qn) {
     wave_sync_lds();
-    if (lane < n) q.res[wv][q.slot[wv][lane]] = st.eval2(q.e[wv][lane]) ? 1 : 0;
+    if (lane < n) {
+        const int sl = q.slot[wv][lane];
+        typename S::Rec r2;
+        const bool ok = st.eval2(q.e[wv][lane], r2);
+        q.res[wv][sl] = ok ? 1 : 0;
+        if constexpr (S::kPhase2Rec)
+            if (ok) copy_words(q.rec[wv][sl], r2);
+    }
     const int rest = qn - n;
     if (rest > 0) {                    // wavefront-uniform
         // moved word by word: an aggregate copy between LDS and registers
@@ -353,7 +373,11 @@ __global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, cons
             if (qn > 0) phase2_flush(st, Q, wv, lane, qn, qn);
 #pragma unroll
             for (int i = 0; i < kPer; ++i)
-                if (pass[i]) pass[i] = Q.res[wv][i * 64 + lane] != 0;
+                if (pass[i]) {
+                    pass[i] = Q.res[wv][i * 64 + lane] != 0;
+                    if constexpr (S::kPhase2Rec)
+                        if (pass[i]) copy_words(rec[i], Q.rec[wv][i * 64 + lane]);
+                }
         }
         int rank[kPer];
 #pragma unroll
@@ -469,6 +493,7 @@ constexpr int kBinThreads = 256;
 constexpr int kFineRange = 1024;        // sensor ids of one range, at most
 constexpr int kMaxRanges = kBinRangesMax;
 constexpr int kFineThreads = 512;       // threads of a fine-pass block
+constexpr int kFineSrcCap = 12288;      // hits of a range gathered through LDS (16-bit indices)
 
 // q = v / d for 0 <= v < 2^24, d >= 1: FP32 reciprocal estimate, made exact
 __device__ __forceinline__ int div_small(int v, int d, float inv) {
@@ -673,6 +698,7 @@ __global__ __launch_bounds__(kFineThreads) void k_bin_fine(const float4 *tmp, co
                                                           int nr, int rw, int xcd_map, int64_t *bin_off, float4 *bin_hit) {
     constexpr int kW = kFineThreads / 64;
     __shared__ int32_t s_wc[kW][kFineRange];
+    __shared__ uint16_t s_src[kFineSrcCap];
     __shared__ int64_t s_w[kW];
     int e, r;
     if (xcd_map) {
@@ -749,6 +775,45 @@ __global__ __launch_bounds__(kFineThreads) void k_bin_fine(const float4 *tmp, co
     }
     if (e == n_ev - 1 && r == nr - 1 && threadIdx.x == 0) bin_off[(int64_t)n_ev * n_sens] = cpos[*nent];
     __syncthreads();
+    if (cnt <= kFineSrcCap) {
+        // ranks give, for every binned position, its source hit (LDS); the
+        // hits are then gathered into place with coalesced stores
+        for (int64_t jb = j0; jb < j1; jb += 64 * kFU) {
+            int kv[kFU];
+#pragma unroll
+            for (int u = 0; u < kFU; ++u) {
+                const int64_t j = jb + u * 64 + lane;
+                kv[u] = tsens[cs + (j < j1 ? j : j1 - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < kFU; ++u) kv[u] = jb + u * 64 + lane < j1 ? kv[u] - lo : -1;
+#pragma unroll
+            for (int u = 0; u < kFU; ++u) {
+                if (jb + u * 64 < j1) {              // wavefront-uniform
+                    const bool ok = kv[u] >= 0;
+                    const int p = wave_rank(s_wc[wv], ok ? kv[u] : 0, ok, nbits);
+                    if (ok) s_src[p] = (uint16_t)(jb + u * 64 + lane);
+                }
+            }
+        }
+        __syncthreads();
+        const int n = (int)cnt;
+        for (int pb = 0; pb < n; pb += kFineThreads * kFU) {
+            f32x4_t hv[kFU];
+#pragma unroll
+            for (int u = 0; u < kFU; ++u) {
+                const int p = pb + u * kFineThreads + threadIdx.x;
+                hv[u] = reinterpret_cast<const f32x4_t *>(tmp)[cs + s_src[p < n ? p : n - 1]];
+            }
+#pragma unroll
+            for (int u = 0; u < kFU; ++u) {
+                const int p = pb + u * kFineThreads + threadIdx.x;
+                if (p < n) reinterpret_cast<f32x4_t *>(bin_hit)[cs + p] = hv[u];
+            }
+        }
+        return;
+    }
+    // larger ranges: each hit is stored at its binned position directly
     for (int64_t jb = j0; jb < j1; jb += 64 * kFU) {
         int kv[kFU];
         f32x4_t hv[kFU];
@@ -792,6 +857,7 @@ struct MDStage {
     static constexpr bool kUnitCount = false;
     static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = false;
+    static constexpr bool kPhase2Rec = false;    // phase 2 produces the output record
     struct Rec { float4 a; float2 o; int hl, hu; };
     struct Mid {};
 
@@ -906,6 +972,7 @@ struct LSStage {
     static constexpr bool kUnitCount = false;
     static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = true;
+    static constexpr bool kPhase2Rec = false;    // phase 2 produces the output record
     struct Rec { int a, b; };
     struct Mid { int a, b; float cp; int bits; };   // bits: 1 bends positive, 2/4 direction cut on A/B
 
@@ -1004,7 +1071,7 @@ struct LSStage {
         return true;
     }
     // phase 2: the MD direction cut of the barrel MDs
-    __device__ bool eval2(const Mid &q) const {
+    __device__ bool eval2(const Mid &q, Rec &) const {
         const float sg = (q.bits & 1) ? 1.0f : -1.0f;
         if (q.bits & 2) {
             const float4 A = md_a[q.a];
@@ -1044,6 +1111,7 @@ struct T3Stage {
     static constexpr bool kUnitCount = false;
     static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = false;
+    static constexpr bool kPhase2Rec = false;    // phase 2 produces the output record
     struct Rec { int li, lo, A, B, C; };
     struct Mid {};
 
@@ -1089,6 +1157,11 @@ struct T3Stage {
 //  (b) anchor: one pre-candidate each; both fits, the chi2 cuts and, with a
 //      score threshold, the T5-DNN cut. T5 come out sorted by inner T3.
 
+// The quintuplet pre-cuts also screen the r-z chi2 in FP32: a candidate is
+// dropped only when its FP32 estimate exceeds the cut by a factor kScreen.
+// Where it is finite, the estimate agrees with the FP64 chi2 to well under one
+// percent, so every decision near the cut is left to the FP64 fits; a
+// degenerate estimate (NaN) drops nothing.
 struct T5PreStage {
     const int4 *t3_mds;
     const int64_t *t3i_off;
@@ -1104,6 +1177,8 @@ struct T5PreStage {
     static constexpr bool kUnitCount = false;
     static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = false;
+    static constexpr bool kPhase2Rec = false;    // phase 2 produces the output record
+    static constexpr float kScreen = 2.0f;
     struct Rec { int u, v; };
     struct Mid {};
 
@@ -1122,10 +1197,23 @@ struct T5PreStage {
     __device__ bool eval(int64_t u, int32_t local, const int32_t *f, const LDS &, Rec &r, Mid &) const {
         const int v = f[0] + local;
         r.u = (int)u; r.v = v;
-        const int E = t3_mds[v].z;
-        const float4 a = md_a[f[2]], e = md_a[E];
+        const int4 m2 = t3_mds[v];
+        const float4 a = md_a[f[2]], e = md_a[m2.z];
         float cv, sg;
-        return pair_pass_rq(p, P3{a.x, a.y, a.z}, md_rq[f[2]], P3{e.x, e.y, e.z}, md_rq[E], cv, sg);
+        if (!pair_pass_rq(p, P3{a.x, a.y, a.z}, md_rq[f[2]], P3{e.x, e.y, e.z}, md_rq[m2.z], cv, sg)) return false;
+        // FP32 screen of the r-z chi2 (see kScreen)
+        const int4 m1 = t3_mds[u];
+        const int ids[5] = {m1.x, m1.y, m1.z, m2.y, m2.z};
+        float x[5], y[5], z[5], rt[5];
+        bool en[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const float4 h = k == 0 ? a : k == 4 ? e : md_a[ids[k]];
+            const float2 rq = md_rq[ids[k]];
+            x[k] = h.x; y[k] = h.y; z[k] = h.z; rt[k] = rq.x;
+            en[k] = signbit(rq.y);
+        }
+        return !(t5_chi2rz_f32(p, x, y, z, rt, en) > kScreen * p.chi2rz);
     }
     __device__ void write(int64_t pos, const Rec &r) const { pre[pos] = make_int2(r.u, r.v); }
 };
@@ -1168,6 +1256,7 @@ struct T5FitStage {
     static constexpr bool kUnitCount = true;
     static constexpr int kMinBlocks = 3;       // resident blocks per CU the register budget must allow
     static constexpr bool kTwoPhase = false;
+    static constexpr bool kPhase2Rec = false;    // phase 2 produces the output record
     struct Rec { int u, v; float cr, cz; float fo[kNFitOut]; };
     struct Mid {};
 
@@ -1195,6 +1284,7 @@ struct T5FitStage {
         }
         return true;
     }
+    __device__ bool eval2(const Mid &, Rec &) const { return true; }
     __device__ void write(int64_t pos, const Rec &r) const {
         t5_t3[pos] = make_int2(r.u, r.v);
         chi2_rphi[pos] = r.cr;
