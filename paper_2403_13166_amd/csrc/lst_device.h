@@ -64,9 +64,27 @@ __device__ __forceinline__ float cross2(float ax, float ay, float bx, float by) 
     return kahan_det(ax, ay, bx, by);
 }
 
+// asin(x) / x for 0 <= x <= 0.8 as a degree-10 polynomial in t = x^2 (Horner),
+// relative error below 8e-8 in FP32; coefficients from csrc/fit_arc_poly.py
+__device__ __forceinline__ float asin_over_x_f(float t) {
+    float g = 6.152549386e-01f;
+    g = __builtin_fmaf(g, t, -1.530246854e+00f);
+    g = __builtin_fmaf(g, t, 1.748290539e+00f);
+    g = __builtin_fmaf(g, t, -1.095079780e+00f);
+    g = __builtin_fmaf(g, t, 4.514038861e-01f);
+    g = __builtin_fmaf(g, t, -8.377703279e-02f);
+    g = __builtin_fmaf(g, t, 4.629246891e-02f);
+    g = __builtin_fmaf(g, t, 4.326621071e-02f);
+    g = __builtin_fmaf(g, t, 7.506076992e-02f);
+    g = __builtin_fmaf(g, t, 1.666656137e-01f);
+    return __builtin_fmaf(g, t, 1.0f);
+}
+
+// arc length asin(c r) / c (half-curvature c >= 0): r * asin(x) / x below
+// x = c r = 0.8, which also covers c -> 0 without a division
 __device__ __forceinline__ float arc_len_f(float c, float r) {
     float x = c * r;
-    if (x < 1e-4f) return r * (1.0f + x * x * (1.0f / 6.0f));
+    if (x <= 0.8f) return r * asin_over_x_f(x * x);
     if (x >= 1.0f) x = 1.0f;
     return asinf(x) / c;
 }
@@ -152,22 +170,27 @@ __device__ __forceinline__ float2 make_md_rq(const CutParams &p, float x, float 
     return make_float2(r, endcap ? -q : q);
 }
 
-// pair_pass with the per-MD radii and resolution terms precomputed (md_rq).
-__device__ __forceinline__ bool pair_pass_rq(const CutParams &p, P3 X, float2 rqX, P3 Y, float2 rqY,
-                                             float &c_out, float &sgn_out) {
+// pair_pass with the per-MD radii and resolution terms precomputed (md_rq),
+// in two parts: the curvature cut, then the ordering and z0 cuts at the
+// clamped curvature cp = min(c, cmax).
+__device__ __forceinline__ bool pair_curv_pass(const CutParams &p, P3 X, float2 rqX, P3 Y, float2 rqY,
+                                               float &c_out, float &sgn_out) {
     const float rX = rqX.x, rY = rqY.x;
-    const bool endX = signbit(rqX.y), endY = signbit(rqY.y);
     float dx = Y.x - X.x, dy = Y.y - X.y;
     float dl = sqrtf(dx * dx + dy * dy);
     float cr = cross2(X.x, X.y, Y.x, Y.y);
     float c = fabsf(cr) / (rX * rY * dl);
-    float srX = endX ? p.sr : 0.0f, srY = endY ? p.sr : 0.0f;
-    float szX = endX ? 0.0f : p.sz, szY = endY ? 0.0f : p.sz;
     float sc = sqrtf(fabsf(rqX.y) + fabsf(rqY.y)) / dl;
     c_out = c;
     sgn_out = cr < 0.0f ? -1.0f : 1.0f;
-    if (!(c <= p.cmax + p.nsig * sc)) return false;
-    float cp = fminf(c, p.cmax);
+    return c <= p.cmax + p.nsig * sc;
+}
+
+__device__ __forceinline__ bool pair_z0_pass(const CutParams &p, P3 X, float2 rqX, P3 Y, float2 rqY, float cp) {
+    const float rX = rqX.x, rY = rqY.x;
+    const bool endX = signbit(rqX.y), endY = signbit(rqY.y);
+    float srX = endX ? p.sr : 0.0f, srY = endY ? p.sr : 0.0f;
+    float szX = endX ? 0.0f : p.sz, szY = endY ? 0.0f : p.sz;
     float sX = arc_len_f(cp, rX), sY = arc_len_f(cp, rY);
     if (!(sX < sY)) return false;
     float ds = sY - sX;
@@ -176,6 +199,12 @@ __device__ __forceinline__ bool pair_pass_rq(const CutParams &p, P3 X, float2 rq
     float a = sY * szX, b = sX * szY, e = sY * srX, f = sX * srY;
     float var = (a * a + b * b + k * k * (e * e + f * f)) / (ds * ds);
     return fabsf(z0) <= p.zlum + p.nsig * sqrtf(var);
+}
+
+__device__ __forceinline__ bool pair_pass_rq(const CutParams &p, P3 X, float2 rqX, P3 Y, float2 rqY,
+                                             float &c_out, float &sgn_out) {
+    if (!pair_curv_pass(p, X, rqX, Y, rqY, c_out, sgn_out)) return false;
+    return pair_z0_pass(p, X, rqX, Y, rqY, fminf(c_out, p.cmax));
 }
 
 // MD direction: the chord between the MD's hits follows the track direction at

@@ -202,21 +202,19 @@ struct TileLds {
 };
 
 // Two-phase stages split their cuts: phase 1 runs on every candidate, and the
-// survivors of each wavefront are queued in LDS so that phase 2 (the costly
-// remainder) runs on dense batches of 64 instead of wave-wide on every
-// sub-round; results return to the candidate's slot, so the outcome and the
-// output order are those of the single-phase evaluation.
+// survivors of each wavefront are queued in LDS, so that phase 2 (the costlier
+// remainder of the cuts) runs on dense batches of 64 instead of wave-wide on
+// every sub-round. Results return to the candidate's slot, so the outcome and
+// the output order are those of a single-phase evaluation.
 constexpr int kQCap = 128;            // queued survivors per wavefront (flushed at 64)
 
 template <class S, int kPer, bool kOn>
 struct PhaseQ { };
 template <class S, int kPer>
 struct PhaseQ<S, kPer, true> {
-    typename S::Mid e[kBlock / 64][kQCap];
+    typename S::Mid e[kBlock / 64][kQCap];     // phase-1 survivors
     uint16_t slot[kBlock / 64][kQCap];
-    uint8_t res[kBlock / 64][kPer * 64];
-    // stages whose phase 2 produces the output record keep it per slot
-    typename S::Rec rec[S::kPhase2Rec ? kBlock / 64 : 1][S::kPhase2Rec ? kPer * 64 : 1];
+    uint8_t res[kBlock / 64][kPer * 64];       // outcome of phase 2, per slot
 };
 
 // copy of a record of whole 32-bit words (keeps LDS <-> register copies out of
@@ -236,36 +234,21 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// run phase 2 on queue entries [0, n) (n <= 64), then move entries [64, qn) to the front
+// run phase 2 on queue entries [0, n) (n <= 64), then move entries [n, qn) to the front
 template <class S, class Q>
 __device__ __forceinline__ void phase2_flush(const S &st, Q &q, int wv, int lane, int n, int qn) {
     wave_sync_lds();
-    if (lane < n) {
-        const int sl = q.slot[wv][lane];
-        typename S::Rec r2;
-        const bool ok = st.eval2(q.e[wv][lane], r2);
-        q.res[wv][sl] = ok ? 1 : 0;
-        if constexpr (S::kPhase2Rec)
-            if (ok) copy_words(q.rec[wv][sl], r2);
-    }
+    if (lane < n) q.res[wv][q.slot[wv][lane]] = st.eval2(q.e[wv][lane]) ? 1 : 0;
     const int rest = qn - n;
     if (rest > 0) {                    // wavefront-uniform
-        // moved word by word: an aggregate copy between LDS and registers
-        // would be staged through private (scratch) memory
-        constexpr int kWords = sizeof(typename S::Mid) / 4;
-        static_assert(sizeof(typename S::Mid) % 4 == 0, "queue entries are whole words");
         wave_sync_lds();
         const int src = n + (lane < rest ? lane : 0);
-        uint32_t te[kWords];
-        const uint32_t *ps = reinterpret_cast<const uint32_t *>(&q.e[wv][src]);
-#pragma unroll
-        for (int k = 0; k < kWords; ++k) te[k] = ps[k];
+        typename S::Mid te;
+        copy_words(te, q.e[wv][src]);
         const uint16_t ts = q.slot[wv][src];
         wave_sync_lds();
         if (lane < rest) {
-            uint32_t *pd = reinterpret_cast<uint32_t *>(&q.e[wv][lane]);
-#pragma unroll
-            for (int k = 0; k < kWords; ++k) pd[k] = te[k];
+            copy_words(q.e[wv][lane], te);
             q.slot[wv][lane] = ts;
         }
     }
@@ -291,7 +274,9 @@ __global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, cons
     constexpr int kWin = S::kWin;
     __shared__ TileLds<S::kEnt, (S::kUnitCount ? 1 : S::kWin)> L;
     __shared__ int s_cnt[kSeg];
-    __shared__ PhaseQ<S, kPer, S::kTwoPhase> Q;
+    __shared__ PhaseQ<S, kPer, (S::kPhases > 1)> Q;
+    __shared__ uint16_t s_anc[S::kUnitCount ? 1 : kTileC];   // window anchor of each tile candidate
+    __shared__ int s_wmax[kWaves];
     const int64_t na = n_dev ? dev_count(n_dev, n_cap) : n_cap;
     // unit-count stages: candidate g is anchor g (no offsets, no decode)
     const int64_t total = S::kUnitCount ? na : cand_off[na];
@@ -311,19 +296,51 @@ __global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, cons
         const int64_t ahi = S::kUnitCount ? 0 : (tile + 1 < ntiles) ? (int64_t)tile_anchor[tile + 1] : na - 1;
         const int nw = (int)(ahi - alo + 1 < (int64_t)kWin + 1 ? ahi - alo + 1 : (int64_t)kWin + 1);
         const bool staged = !S::kUnitCount && nw <= kWin;
-        if (staged) {
-            for (int i = threadIdx.x; i <= nw; i += kBlock) {
-                L.off[i] = cand_off[alo + i];
-                if (i < nw) st.info(alo + i, L.info[i]);
+        if constexpr (!S::kUnitCount) {
+            if (staged) {
+                for (int i = threadIdx.x; i <= nw; i += kBlock) {
+                    L.off[i] = cand_off[alo + i];
+                    if (i < nw) st.info(alo + i, L.info[i]);
+                }
+                for (int q = threadIdx.x; q < kTileC; q += kBlock) s_anc[q] = 0;
+                __syncthreads();
+                // anchor map: each non-empty window anchor marks its first
+                // candidate in the tile; a running maximum then gives every
+                // candidate the last anchor that starts at or before it
+                const int64_t g0 = tile * kTileC;
+                for (int w = threadIdx.x; w < nw; w += kBlock) {
+                    const int64_t o = L.off[w];
+                    if (L.off[w + 1] > o && o > g0 && o < g0 + kTileC) s_anc[o - g0] = (uint16_t)w;
+                }
+                __syncthreads();
+                int v[kPer], m = 0;
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const int a = s_anc[threadIdx.x * kPer + k];
+                    m = a > m ? a : m;
+                    v[k] = m;
+                }
+                int incl = m;               // inclusive running maximum over the wavefront
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int o = __shfl_up(incl, d, 64);
+                    if (lane >= d && o > incl) incl = o;
+                }
+                if (lane == 63) s_wmax[wv] = incl;
+                int carry = __shfl_up(incl, 1, 64);
+                if (lane == 0) carry = 0;
+                __syncthreads();
+                for (int k = 0; k < wv; ++k) carry = s_wmax[k] > carry ? s_wmax[k] : carry;
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) s_anc[threadIdx.x * kPer + k] = (uint16_t)(v[k] > carry ? v[k] : carry);
+                __syncthreads();
+                st.prepare(L, alo, nw);
             }
-            __syncthreads();
-            st.prepare(L, alo, nw);
         }
         // candidate g = tile * kTileC + i * kBlock + tid: each sub-round i is a
         // contiguous run of kBlock candidates (coalesced reads)
         typename S::Rec rec[kPer];
         bool pass[kPer];
-        int wlo = 0;                 // window index (staged)
         int64_t glo = alo;           // anchor index (global search)
         int qn = 0;                  // queued phase-2 entries of this wavefront
 #pragma unroll
@@ -337,11 +354,7 @@ __global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, cons
                     st.info(g, f);
                     pass[i] = st.eval(g, 0, f, L, rec[i], mid_i);
                 } else if (staged) {
-                    int hi = nw;      // largest w in [wlo, nw) with off[w] <= g
-                    while (hi - wlo > 1) {
-                        int mid = (wlo + hi) >> 1;
-                        if (L.off[mid] <= g) wlo = mid; else hi = mid;
-                    }
+                    const int wlo = s_anc[i * kBlock + threadIdx.x];
                     pass[i] = st.eval(alo + wlo, (int32_t)(g - L.off[wlo]), L.info[wlo], L, rec[i], mid_i);
                 } else {
                     int64_t hi = ahi + 1;
@@ -355,11 +368,11 @@ __global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, cons
                     pass[i] = st.eval(glo, (int32_t)(g - cand_off[glo]), f, L, rec[i], mid_i);
                 }
             }
-            if constexpr (S::kTwoPhase) {
+            if constexpr (S::kPhases > 1) {
                 const unsigned long long m = __ballot(pass[i]);
                 const int rk = __popcll(m & ((1ull << lane) - 1ull));
                 if (pass[i]) {
-                    Q.e[wv][qn + rk] = mid_i;
+                    copy_words(Q.e[wv][qn + rk], mid_i);
                     Q.slot[wv][qn + rk] = (uint16_t)(i * 64 + lane);
                 }
                 qn += __popcll(m);
@@ -369,15 +382,11 @@ __global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, cons
                 }
             }
         }
-        if constexpr (S::kTwoPhase) {
+        if constexpr (S::kPhases > 1) {
             if (qn > 0) phase2_flush(st, Q, wv, lane, qn, qn);
 #pragma unroll
             for (int i = 0; i < kPer; ++i)
-                if (pass[i]) {
-                    pass[i] = Q.res[wv][i * 64 + lane] != 0;
-                    if constexpr (S::kPhase2Rec)
-                        if (pass[i]) copy_words(rec[i], Q.rec[wv][i * 64 + lane]);
-                }
+                if (pass[i]) pass[i] = Q.res[wv][i * 64 + lane] != 0;
         }
         int rank[kPer];
 #pragma unroll
@@ -856,8 +865,7 @@ struct MDStage {
     static constexpr int kWin = 512;             // anchors staged per tile
     static constexpr bool kUnitCount = false;
     static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
-    static constexpr bool kTwoPhase = false;
-    static constexpr bool kPhase2Rec = false;    // phase 2 produces the output record
+    static constexpr int kPhases = 1;            // cut phases (later ones on queued survivors)
     struct Rec { float4 a; float2 o; int hl, hu; };
     struct Mid {};
 
@@ -971,8 +979,7 @@ struct LSStage {
     static constexpr int kWin = 256;             // anchors staged per tile
     static constexpr bool kUnitCount = false;
     static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
-    static constexpr bool kTwoPhase = true;
-    static constexpr bool kPhase2Rec = false;    // phase 2 produces the output record
+    static constexpr int kPhases = 2;            // cut phases (later ones on queued survivors)
     struct Rec { int a, b; };
     struct Mid { int a, b; float cp; int bits; };   // bits: 1 bends positive, 2/4 direction cut on A/B
 
@@ -1071,7 +1078,7 @@ struct LSStage {
         return true;
     }
     // phase 2: the MD direction cut of the barrel MDs
-    __device__ bool eval2(const Mid &q, Rec &) const {
+    __device__ bool eval2(const Mid &q) const {
         const float sg = (q.bits & 1) ? 1.0f : -1.0f;
         if (q.bits & 2) {
             const float4 A = md_a[q.a];
@@ -1110,8 +1117,7 @@ struct T3Stage {
     static constexpr int kWin = 512;             // anchors staged per tile
     static constexpr bool kUnitCount = false;
     static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
-    static constexpr bool kTwoPhase = false;
-    static constexpr bool kPhase2Rec = false;    // phase 2 produces the output record
+    static constexpr int kPhases = 1;            // cut phases (later ones on queued survivors)
     struct Rec { int li, lo, A, B, C; };
     struct Mid {};
 
@@ -1176,8 +1182,7 @@ struct T5PreStage {
     static constexpr int kWin = 512;             // anchors staged per tile
     static constexpr bool kUnitCount = false;
     static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
-    static constexpr bool kTwoPhase = false;
-    static constexpr bool kPhase2Rec = false;    // phase 2 produces the output record
+    static constexpr int kPhases = 1;            // cut phases (later ones on queued survivors)
     static constexpr float kScreen = 2.0f;
     struct Rec { int u, v; };
     struct Mid {};
@@ -1255,8 +1260,7 @@ struct T5FitStage {
     static constexpr int kWin = 512;             // anchors staged per tile
     static constexpr bool kUnitCount = true;
     static constexpr int kMinBlocks = 3;       // resident blocks per CU the register budget must allow
-    static constexpr bool kTwoPhase = false;
-    static constexpr bool kPhase2Rec = false;    // phase 2 produces the output record
+    static constexpr int kPhases = 1;            // cut phases (later ones on queued survivors)
     struct Rec { int u, v; float cr, cz; float fo[kNFitOut]; };
     struct Mid {};
 
@@ -1284,7 +1288,6 @@ struct T5FitStage {
         }
         return true;
     }
-    __device__ bool eval2(const Mid &, Rec &) const { return true; }
     __device__ void write(int64_t pos, const Rec &r) const {
         t5_t3[pos] = make_int2(r.u, r.v);
         chi2_rphi[pos] = r.cr;
