@@ -88,12 +88,14 @@ def make_batch(n_events: int, batch_seed: int):
     return geo, evs
 
 
-def stage_bytes(c, n_hits, n_ev, n_mod, n_map, precision):
+def stage_bytes(c, n_hits, n_ev, n_mod, n_map):
     """Algorithmic HBM bytes per launch of each stage kernel: every input
     record read once and every output written once."""
     md, ls, t3, t5 = c[:4]
     em = n_ev * n_mod
-    score = 12 * t5 + 16 * t3 + 16 * md + (2 * 168 * t5 if precision == "bf16" else 0)
+    # features come from the T5's T3 pair, its MDs and the fit outputs, and
+    # stay on chip (LDS) until the score is written
+    score = (8 + 32 + 4) * t5 + 16 * t3 + 16 * md
     return {
         "md": 16 * n_hits + 24 * em + 32 * md,
         "ls": 36 * md + 4 * n_map * n_ev + 8 * em + 8 * ls,
@@ -330,7 +332,7 @@ def main():
     avg = {k: float(np.mean(v)) for k, v in stage_ms.items()}
     kern = {k: avg[k] for k in ("md", "ls", "t3", "t5", "score")}
     dom = max(kern, key=kern.get)
-    sb = stage_bytes(final, len(x), a.events, geo.n_modules, int(geo.map_tgt.shape[0]), a.precision)
+    sb = stage_bytes(final, len(x), a.events, geo.n_modules, int(geo.map_tgt.shape[0]))
     achieved = sb[dom] / (avg[dom] * 1e-3) / 1e9
     stage_idx = {"md": 0, "ls": 1, "t3": 2, "t5": 4}
     tile = tuned["tile_per"][stage_idx[dom]] if dom in stage_idx else None
