@@ -396,20 +396,23 @@ __global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, cons
             if (lane == 0) s_cnt[i * kWaves + wv] = __popcll(m);
         }
         __syncthreads();
+        // segment offsets: every wavefront scans the kSeg (<= 64) counts itself
+        static_assert(kSeg <= 64, "one wavefront scans the segment counts");
+        const int cseg = lane < kSeg ? s_cnt[lane] : 0;
+        int incl = cseg;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        const int excl = incl - cseg, tcnt = __shfl(incl, kSeg - 1, 64);
         typename S::Rec *slot = scratch + tile * kTileC;
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
-            if (pass[i]) {
-                int off = 0;
-                for (int k = 0; k < i * kWaves + wv; ++k) off += s_cnt[k];
-                slot[off + rank[i]] = rec[i];
-            }
+            const int off = __shfl(excl, i * kWaves + wv, 64);
+            if (pass[i]) slot[off + rank[i]] = rec[i];
         }
-        if (threadIdx.x == 0) {
-            int tcnt = 0;
-            for (int k = 0; k < kSeg; ++k) tcnt += s_cnt[k];
-            tile_cnt[tile] = tcnt;
-        }
+        if (threadIdx.x == 0) tile_cnt[tile] = tcnt;
         __syncthreads();
     }
 }
