@@ -206,8 +206,8 @@ lst_status lst_gnn_score(lst_ctx *ctx, const float *x_dev, int64_t n_nodes, cons
  *   tile_per[s]  candidates per thread of a 256-thread compaction tile, for
  *                stage s = 0 MD {2,4,8}, 1 LS {2,4,8}, 2 T3 {1,2,4},
  *                3 T5 FP32 pre-cuts {1,2,4}, 4 T5 FP64 fits {1,2};
- *   eval_blocks  persistent blocks of the compaction kernels (256..8192).
- * Defaults: {4, {4, 4, 2, 2, 1}, 4096}. lst_set_tuning(ctx, NULL) restores
+ *   eval_blocks  blocks of the compaction kernels (256..8192).
+ * Defaults: {4, {4, 8, 2, 2, 1}, 8192}. lst_set_tuning(ctx, NULL) restores
  * them; an unsupported value gives LST_E_INVAL and leaves the tuning as it
  * was. The tuning in force when a build is enqueued (or captured) is used. */
 typedef struct {

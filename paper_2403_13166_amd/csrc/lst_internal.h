@@ -12,7 +12,7 @@ namespace lst {
 // on data, so a whole build can be captured into a HIP graph.
 constexpr int kBlock = 256;
 constexpr int kScanBlocks = 1024;
-constexpr int kEvalBlocks = 4096;     // persistent compaction blocks (256 CUs x 16)
+constexpr int kEvalBlocks = 8192;     // compaction blocks (256 CUs x 32), default
 constexpr int kMaxStride = 8192;      // grid cap of grid-stride kernels
 constexpr int kMaxRecBytes = 48;      // largest per-candidate record a stage compacts
 constexpr int kBinRangesMax = 1024;   // sensor ranges per event in hit binning, at most
@@ -29,7 +29,7 @@ struct Tuning {
     int32_t per[kStages];
     int32_t eval_blocks;              // persistent blocks of the compaction kernels
 };
-constexpr Tuning kDefaultTuning = {4, {4, 4, 2, 2, 1}, kEvalBlocks};
+constexpr Tuning kDefaultTuning = {4, {4, 8, 2, 2, 1}, kEvalBlocks};
 inline bool tuning_valid(const Tuning &t) {
     if (t.bin_split < 1 || t.bin_split > 64) return false;
     if (t.eval_blocks < 256 || t.eval_blocks > kMaxStride) return false;
