@@ -1,29 +1,17 @@
 // T5-DNN scoring (paper Sec. 2: 42 inputs -> 32 -> 32 -> 1, ReLU hidden
-// layers, sigmoid output) over dense feature rows.
+// layers, sigmoid output) over dense feature rows given by the caller.
 //
-// BF16 path: a block stages a tile of 256 contiguous rows in LDS with 16-byte
-// coalesced loads; one wavefront then scores 64 of them on the matrix cores with
-// v_mfma_f32_16x16x32_bf16, computing the transposed products
-//   H1^T [32 x 64] = W1 [32 x 64(K, 42 padded)] . Xs^T [64 x 64]
-//   H2^T [32 x 64] = W2 [32 x 32]               . relu(H1^T)
-// so that each lane's accumulator rows of layer 1 are exactly the B operand
-// of layer 2 once the K index of W2 is permuted accordingly (K is a summed
-// index, so any consistent permutation is exact): no LDS round trip between
-// the layers. Inputs are standardised in FP32 and rounded to BF16 (RNE);
-// accumulation is FP32; the 32 -> 1 layer and the sigmoid run on the VALU.
-//
-// MFMA 16x16x32 lane layout (wave64, l = lane, g = l / 16):
-//   A (16 x 32):  lane l holds A[l % 16][8 g + i], i = 0..7
-//   B (32 x 16):  lane l holds B[8 g + i][l % 16], i = 0..7
-//   D (16 x 16):  lane l holds D[4 g + j][l % 16], j = 0..3
+// BF16 path: a block stages a tile of 256 contiguous rows with 16-byte
+// coalesced loads, standardising each value in FP32 and storing it as BF16
+// (round to nearest even) in an LDS tile; the tile is then scored on the
+// matrix cores (lst_mlp_tile.h, shared with the fused scoring of the build).
+// FP32 path: one row per thread on the vector ALU.
 #include <hip/hip_runtime.h>
 
 #include "lst_internal.h"
+#include "lst_mlp_tile.h"
 
 namespace lst {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
@@ -49,130 +37,60 @@ __global__ __launch_bounds__(256) void k_score_f32(ModelDev m, const void *X, co
     }
 }
 
-// Hidden unit carried by B-operand slot i of lane group g in layer 2.
-__device__ __forceinline__ int perm_unit(int g, int i) { return i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4); }
-
-constexpr int kScoreTile = 256;   // rows per block tile (4 wavefronts x 64 rows)
-
-// One block tile of rows is a contiguous chunk of X (256 x 42 features); the
-// block copies it to LDS with 16-byte coalesced loads (converting BF16 input
-// to FP32), then every wavefront builds its MFMA operands from LDS.
+// Stage rows [row0, row0 + nrows) of X (row-major, kNFeat values per row) into
+// the tile, standardised and rounded to BF16. Thread t takes the 16-byte
+// chunks t, t + 256, ...; a chunk's values may straddle two rows.
 template <int DT>
-__device__ __forceinline__ void stage_rows(float *sx, const void *X, int64_t row0, int nrows) {
+__device__ __forceinline__ void stage_rows_bf16(uint16_t *tile, const float *s_mu, const float *s_isd,
+                                                const void *X, int64_t row0, int nrows) {
     const int nel = nrows * kNFeat;
-    if (DT == 0) {
-        const float *src = (const float *)X + row0 * kNFeat;
-        const bool vec = ((uintptr_t)src & 15) == 0;
-        const int n4 = vec ? nel / 4 : 0;
-        for (int i = threadIdx.x; i < n4; i += 256)
-            reinterpret_cast<float4 *>(sx)[i] = reinterpret_cast<const float4 *>(src)[i];
-        for (int i = 4 * n4 + threadIdx.x; i < nel; i += 256) sx[i] = src[i];
-    } else {
-        const uint16_t *src = (const uint16_t *)X + row0 * kNFeat;
-        const bool vec = ((uintptr_t)src & 15) == 0;
-        const int n8 = vec ? nel / 8 : 0;
-        for (int i = threadIdx.x; i < n8; i += 256) {
-            const uint4 u = reinterpret_cast<const uint4 *>(src)[i];
-            const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+    constexpr int kPerChunk = DT == 0 ? 4 : 8;
+    const uint8_t *src = (const uint8_t *)X + row0 * kNFeat * (DT == 0 ? 4 : 2);
+    const bool vec = ((uintptr_t)src & 15) == 0;
+    const int nch = vec ? nel / kPerChunk : 0;
+    auto put = [&](int idx, float x) {
+        const int r = (idx * 24967) >> 20;           // idx / 42, exact for idx < 2^14
+        const int k = idx - r * kNFeat;
+        const __bf16 v = (__bf16)((x - s_mu[k]) * s_isd[k]);
+        tile[r * kRowStride + k] = __builtin_bit_cast(uint16_t, v);
+    };
+    for (int c = threadIdx.x; c < nch; c += kTileRows) {
+        const uint4 u = reinterpret_cast<const uint4 *>(src)[c];
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+        if (DT == 0) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                sx[8 * i + 2 * k] = __uint_as_float(w[k] << 16);
-                sx[8 * i + 2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
-            }
-        }
-        for (int i = 8 * n8 + threadIdx.x; i < nel; i += 256) sx[i] = bf16_to_f32(src[i]);
-    }
-}
-
-template <int DT>
-__global__ __launch_bounds__(256) void k_score_mfma(ModelDev m, const void *X, const int64_t *n_dev,
-                                                    int64_t n_cap, float *out) {
-    __shared__ float sx[kScoreTile * kNFeat];
-    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15, wv = threadIdx.x >> 6;
-    const int64_t n = n_dev ? (*n_dev < n_cap ? *n_dev : n_cap) : n_cap;
-    // weights as A operands (kept in registers for the whole kernel)
-    bf16x8 w1[2][2], w2[2];
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                int k = ks * 32 + 8 * g + i;
-                w1[mb][ks][i] = (__bf16)(k < kNFeat ? m.W1[(mb * 16 + c) * kNFeat + k] : 0.0f);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) w2[mb][i] = (__bf16)m.W2[(mb * 16 + c) * kH1 + perm_unit(g, i)];
-    }
-    // per-lane standardisation constants of the features this lane loads
-    float mu[2][8], isd[2][8];
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            int k = ks * 32 + 8 * g + i;
-            mu[ks][i] = k < kNFeat ? m.mu[k] : 0.0f;
-            isd[ks][i] = k < kNFeat ? 1.0f / m.sd[k] : 0.0f;
-        }
-    float b1v[2][4], b2v[2][4], w3v[2][4];
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            b1v[mb][j] = m.b1[mb * 16 + 4 * g + j];
-            b2v[mb][j] = m.b2[mb * 16 + 4 * g + j];
-            w3v[mb][j] = m.w3[mb * 16 + 4 * g + j];
-        }
-    for (int64_t row0 = (int64_t)blockIdx.x * kScoreTile; row0 < n; row0 += (int64_t)gridDim.x * kScoreTile) {
-        const int nrows = n - row0 < kScoreTile ? (int)(n - row0) : kScoreTile;
-        __syncthreads();                                   // the previous tile is consumed
-        stage_rows<DT>(sx, X, row0, nrows);
-        __syncthreads();
-        const int base = wv * 64;                          // this wavefront's rows in the tile
-        f32x4 acc1[2][4];
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb) acc1[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            const int r = base + nb * 16 + c;
-            const bool ok = r < nrows;
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                bf16x8 xb;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    int k = ks * 32 + 8 * g + i;
-                    float v = (ok && k < kNFeat) ? (sx[r * kNFeat + k] - mu[ks][i]) * isd[ks][i] : 0.0f;
-                    xb[i] = (__bf16)v;
-                }
-#pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
-                    acc1[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[mb][ks], xb, acc1[mb][nb], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            bf16x8 hb;
+            for (int j = 0; j < 4; ++j) put(4 * c + j, __uint_as_float(w[j]));
+        } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                hb[j] = (__bf16)fmaxf(acc1[0][nb][j] + b1v[0][j], 0.0f);
-                hb[4 + j] = (__bf16)fmaxf(acc1[1][nb][j] + b1v[1][j], 0.0f);
+                put(8 * c + 2 * j, __uint_as_float(w[j] << 16));
+                put(8 * c + 2 * j + 1, __uint_as_float(w[j] & 0xffff0000u));
             }
-            float part = 0.0f;
-#pragma unroll
-            for (int mb = 0; mb < 2; ++mb) {
-                f32x4 a2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[mb], hb, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) part = __builtin_fmaf(w3v[mb][j], fmaxf(a2[j] + b2v[mb][j], 0.0f), part);
-            }
-            part += __shfl_xor(part, 16, 64);
-            part += __shfl_xor(part, 32, 64);
-            const int r = base + nb * 16 + c;
-            if (g == 0 && r < nrows) out[row0 + r] = 1.0f / (1.0f + expf(-(part + m.b3)));
         }
+    }
+    for (int i = kPerChunk * nch + threadIdx.x; i < nel; i += kTileRows) put(i, load_x<DT>(X, row0 * kNFeat + i));
+}
+
+static_assert(kTileRows * kNFeat < (1 << 14), "row index by multiply-shift");
+
+template <int DT>
+__global__ __launch_bounds__(kTileRows) void k_score_mfma(ModelDev m, const void *X, const int64_t *n_dev,
+                                                          int64_t n_cap, float *out) {
+    __shared__ __align__(16) uint16_t tile[kTileRows * kRowStride];
+    __shared__ MlpFrags fr;
+    __shared__ float s_mu[kNFeat], s_isd[kNFeat];
+    mlp_tile_init(&fr, tile, m);
+    if (threadIdx.x < kNFeat) {
+        s_mu[threadIdx.x] = m.mu[threadIdx.x];
+        s_isd[threadIdx.x] = 1.0f / m.sd[threadIdx.x];
+    }
+    const int64_t n = n_dev ? (*n_dev < n_cap ? *n_dev : n_cap) : n_cap;
+    for (int64_t row0 = (int64_t)blockIdx.x * kTileRows; row0 < n; row0 += (int64_t)gridDim.x * kTileRows) {
+        const int nrows = n - row0 < kTileRows ? (int)(n - row0) : kTileRows;
+        __syncthreads();                                   // the previous tile is consumed
+        stage_rows_bf16<DT>(tile, s_mu, s_isd, X, row0, nrows);
+        __syncthreads();
+        mlp_tile_score(tile, &fr, nrows, m, out + row0);
     }
 }
 
