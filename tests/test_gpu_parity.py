@@ -229,6 +229,25 @@ def test_edge_cases(builder_f, geo_f):
     assert np.array_equal(out.t5_t3, ref.t5_t3) and np.array_equal(out.md_hits, ref.md_hits)
 
 
+def test_dense_sensor_range_parity(builder_f, geo_f, mdl):
+    """A PU200-like event plus 40k noise hits on the first sensor-id range:
+    that range holds ~53k hits, more than one fine-binning block gathers
+    through LDS, so its hits take the direct-store path."""
+    ev = E.make_event(geo_f, E.PU200, (1, 7))
+    rng = np.random.default_rng(11)
+    x, y, z, s = E._noise_hits(geo_f, 1_500_000, rng)
+    keep = s < 999
+    dense = E.Event(np.concatenate([ev.x, x[keep].astype(np.float32)]),
+                    np.concatenate([ev.y, y[keep].astype(np.float32)]),
+                    np.concatenate([ev.z, z[keep].astype(np.float32)]),
+                    np.concatenate([ev.sensor, s[keep].astype(np.int32)]),
+                    np.concatenate([ev.truth, np.full(int(keep.sum()), -1, np.int32)]), ev.tracks)
+    assert np.sum(dense.sensor < 999) > 40_000
+    _say(f"dense range event: {dense.n} hits, {int(np.sum(dense.sensor < 999))} in sensors 0..998")
+    gh = run_gpu(builder_f, dense)
+    check_parity(geo_f, mdl, dense, gh, label="dense range")
+
+
 def test_tunings_change_nothing_but_speed(builder_f, geo_f):
     from paper_2403_13166_amd import binding as B
     ev = E.make_event(geo_f, E.PU200, (1, 1))
