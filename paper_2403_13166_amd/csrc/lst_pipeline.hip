@@ -197,8 +197,7 @@ struct TileLds {
     int32_t ebase[kEnt > 0 ? kWin : 1];   // first table entry of each window anchor
     int32_t ek0[kEnt > 0 ? kWin : 1];     // its first module-map entry
     int32_t ent_rp[kEnt > 0 ? kEnt : 1];
-    int32_t ent_md[kEnt > 0 ? kEnt : 1];
-    int32_t ent_mod[kEnt > 0 ? kEnt : 1];
+    int32_t ent_md[kEnt > 0 ? kEnt : 1];  // first MD of the entry's target, bit 31: endcap target
 };
 
 // Two-phase stages split their cuts: phase 1 runs on every candidate, and the
@@ -981,7 +980,7 @@ struct LSStage {
     static constexpr int kStage = 1;
     static constexpr int kWin = 256;             // anchors staged per tile
     static constexpr bool kUnitCount = false;
-    static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
+    static constexpr int kMinBlocks = 5;       // resident blocks per CU the register budget must allow
     static constexpr int kPhases = 2;            // cut phases (later ones on queued survivors)
     struct Rec { int a, b; };
     struct Mid { int a, b; float cp; int bits; };   // bits: 1 bends positive, 2/4 direction cut on A/B
@@ -1028,8 +1027,7 @@ struct LSStage {
                 const int32_t k = L.ek0[lo] + (q - L.ebase[lo]);
                 const int32_t tg = map_tgt[k];
                 L.ent_rp[q] = rpref[e * n_map + k];
-                L.ent_md[q] = (int32_t)md_mod_off[e * n_mod + tg];
-                L.ent_mod[q] = tg | (mod[tg].kind != 0 ? (1 << 30) : 0);   // bit 30: endcap
+                L.ent_md[q] = (int32_t)md_mod_off[e * n_mod + tg] | (mod[tg].kind != 0 ? INT32_MIN : 0);
             }
         }
         __syncthreads();
@@ -1046,7 +1044,6 @@ struct LSStage {
         const int64_t a = f[0] + l;
         const bool eA = (f[3] >> 16) & 1;
         int64_t b;
-        int mb;
         bool eB;
         if (f[2] >= 0) {
             int lo = f[2], hi = f[2] + (f[3] & 0xffff);   // largest entry with ent_rp <= rr
@@ -1054,10 +1051,9 @@ struct LSStage {
                 int mid = (lo + hi) >> 1;
                 if (L.ent_rp[mid] <= rr) lo = mid; else hi = mid;
             }
-            b = L.ent_md[lo] + (rr - L.ent_rp[lo]);
-            const int em = L.ent_mod[lo];
-            mb = em & 0x3fffffff;
-            eB = (em >> 30) & 1;
+            const int32_t em = L.ent_md[lo];
+            b = (em & INT32_MAX) + (rr - L.ent_rp[lo]);
+            eB = em < 0;
         } else {
             const int64_t e = gm / n_mod, m = gm - e * n_mod;
             const int32_t *rp = rpref + e * n_map;
@@ -1066,7 +1062,7 @@ struct LSStage {
                 int mid = (lo + hi) >> 1;
                 if (rp[mid] <= rr) lo = mid; else hi = mid;
             }
-            mb = map_tgt[lo];
+            const int mb = map_tgt[lo];
             b = md_mod_off[e * n_mod + mb] + (rr - rp[lo]);
             eB = mod[mb].kind != 0;
         }
