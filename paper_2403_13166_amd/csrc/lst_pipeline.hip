@@ -1115,7 +1115,7 @@ struct T3Stage {
     static constexpr int kStage = 2;
     static constexpr int kWin = 512;             // anchors staged per tile
     static constexpr bool kUnitCount = false;
-    static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
+    static constexpr int kMinBlocks = 8;       // resident blocks per CU the register budget must allow
     static constexpr int kPhases = 1;            // cut phases (later ones on queued survivors)
     struct Rec { int li, lo, A, B, C; };
     struct Mid {};
@@ -1180,7 +1180,7 @@ struct T5PreStage {
     static constexpr int kStage = 3;
     static constexpr int kWin = 512;             // anchors staged per tile
     static constexpr bool kUnitCount = false;
-    static constexpr int kMinBlocks = 1;       // resident blocks per CU the register budget must allow
+    static constexpr int kMinBlocks = 6;       // resident blocks per CU the register budget must allow
     static constexpr int kPhases = 1;            // cut phases (later ones on queued survivors)
     static constexpr float kScreen = 2.0f;
     struct Rec { int u, v; };
