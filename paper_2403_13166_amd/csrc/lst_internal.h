@@ -16,7 +16,7 @@ constexpr int kEvalBlocks = 8192;     // compaction blocks (256 CUs x 32), defau
 constexpr int kMaxStride = 8192;      // grid cap of grid-stride kernels
 constexpr int kMaxRecBytes = 48;      // largest per-candidate record a stage compacts
 constexpr int kBinRangesMax = 1024;   // sensor ranges per event in hit binning, at most
-constexpr int kBinTileHits = 4096;     // hits of one binning tile
+constexpr int kBinTileHits = 2048;     // hits of one binning tile
 
 // Launch shapes (never change results: outputs are in candidate order for any
 // tiling). Stage order: MD, LS, T3, T5 pre-cuts, T5 fit.
