@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # elementwise kernel), kept with the hash of the kernel sources they were
 # taken on: a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("ls stage", 8): {"bytes": 210906908.7, "source_sha1": "65f05551e7d3fe91202458ec5ff3920e7d238cb5"},
+    ("ls stage", 8): {"bytes": 233860738.4, "source_sha1": "99ffd6ce3feda0da5401c4170efdc364703f7002"},
 }
 KERNEL_SOURCES = ("paper_2403_13166_amd/csrc/lst_pipeline.hip", "paper_2403_13166_amd/csrc/lst_device.h",
                   "paper_2403_13166_amd/csrc/lst_internal.h")
