@@ -538,25 +538,32 @@ __device__ inline void t5_features(const CutParams &p, const double *x, const do
 
 // T5-DNN forward pass, FP32 vector ALU (weights read with wave-uniform
 // addresses, i.e. through the scalar cache).
+// Read-only load through the constant address space: with a wavefront-uniform
+// address it becomes a scalar load
+__device__ __forceinline__ float ld_uniform(const float *p) {
+    return *(const __attribute__((address_space(4))) float *)p;
+}
+
 __device__ inline float mlp_f32(const ModelDev &m, const float *x) {
+    // weights read as uniform constants (scalar loads)
     float xs[kNFeat];
 #pragma unroll
-    for (int k = 0; k < kNFeat; ++k) xs[k] = (x[k] - m.mu[k]) / m.sd[k];
+    for (int k = 0; k < kNFeat; ++k) xs[k] = (x[k] - ld_uniform(m.mu + k)) / ld_uniform(m.sd + k);
     float h1[kH1];
 #pragma unroll 4
     for (int j = 0; j < kH1; ++j) {
-        float a = m.b1[j];
+        float a = ld_uniform(m.b1 + j);
 #pragma unroll
-        for (int k = 0; k < kNFeat; ++k) a = __builtin_fmaf(m.W1[j * kNFeat + k], xs[k], a);
+        for (int k = 0; k < kNFeat; ++k) a = __builtin_fmaf(ld_uniform(m.W1 + j * kNFeat + k), xs[k], a);
         h1[j] = fmaxf(a, 0.0f);
     }
     float o = m.b3;
 #pragma unroll 4
     for (int j = 0; j < kH2; ++j) {
-        float a = m.b2[j];
+        float a = ld_uniform(m.b2 + j);
 #pragma unroll
-        for (int k = 0; k < kH1; ++k) a = __builtin_fmaf(m.W2[j * kH1 + k], h1[k], a);
-        o = __builtin_fmaf(m.w3[j], fmaxf(a, 0.0f), o);
+        for (int k = 0; k < kH1; ++k) a = __builtin_fmaf(ld_uniform(m.W2 + j * kH1 + k), h1[k], a);
+        o = __builtin_fmaf(ld_uniform(m.w3 + j), fmaxf(a, 0.0f), o);
     }
     return 1.0f / (1.0f + expf(-o));
 }
