@@ -290,9 +290,19 @@ __global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, cons
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const TileWalk walk(ntiles);
+    // a tile's first and last anchors, read as uniform scalar loads (the tile
+    // anchors are read-only here); the next tile's are fetched a tile ahead
+    auto tile_lo = [&](int64_t t) -> int64_t {
+        return *(const __attribute__((address_space(4))) int32_t *)(tile_anchor + t);
+    };
+    auto tile_hi = [&](int64_t t) -> int64_t { return t + 1 < ntiles ? tile_lo(t + 1) : na - 1; };
+    int64_t alo_n = 0, ahi_n = 0;
+    if constexpr (!S::kUnitCount)
+        if (walk.first < walk.end) { alo_n = tile_lo(walk.first); ahi_n = tile_hi(walk.first); }
     for (int64_t tile = walk.first; tile < walk.end; tile += walk.step) {
-        const int64_t alo = S::kUnitCount ? 0 : tile_anchor[tile];
-        const int64_t ahi = S::kUnitCount ? 0 : (tile + 1 < ntiles) ? (int64_t)tile_anchor[tile + 1] : na - 1;
+        const int64_t alo = alo_n, ahi = ahi_n;
+        if constexpr (!S::kUnitCount)
+            if (tile + walk.step < walk.end) { alo_n = tile_lo(tile + walk.step); ahi_n = tile_hi(tile + walk.step); }
         const int nw = (int)(ahi - alo + 1 < (int64_t)kWin + 1 ? ahi - alo + 1 : (int64_t)kWin + 1);
         const bool staged = !S::kUnitCount && nw <= kWin;
         if constexpr (!S::kUnitCount) {
