@@ -435,9 +435,18 @@ __global__ __launch_bounds__(kBlock) void k_stage_copy(S st, const typename S::R
     const int64_t ntiles = *ntiles_dev;
     if (blockIdx.x == 0 && threadIdx.x == 0) *out_count = tile_pre[ntiles];
     const TileWalk walk(ntiles);
+    // a tile's count and output base as uniform scalar loads, one tile ahead
+    auto cnt_of = [&](int64_t t) -> int { return *(const __attribute__((address_space(4))) int32_t *)(tile_cnt + t); };
+    auto pre_of = [&](int64_t t) -> int64_t {
+        return *(const __attribute__((address_space(4))) int64_t *)(tile_pre + t);
+    };
+    int n_n = 0;
+    int64_t base_n = 0;
+    if (walk.first < walk.end) { n_n = cnt_of(walk.first); base_n = pre_of(walk.first); }
     for (int64_t tile = walk.first; tile < walk.end; tile += walk.step) {
-        const int n = tile_cnt[tile];
-        const int64_t base = tile_pre[tile];
+        const int n = n_n;
+        const int64_t base = base_n;
+        if (tile + walk.step < walk.end) { n_n = cnt_of(tile + walk.step); base_n = pre_of(tile + walk.step); }
         const typename S::Rec *slot = scratch + tile * kTileC;
         for (int i = threadIdx.x; i < n; i += kBlock) {
             const int64_t pos = base + i;
