@@ -52,6 +52,12 @@ struct GeomDev {
 
 // ------------------------------------------------------------ small helpers
 
+// Read-only value at a wavefront-uniform address, through the constant
+// address space so that it is a scalar load (for data written by an earlier
+// launch, or by the host, and not written by the reading kernel).
+template <class T>
+__device__ __forceinline__ T ld_scalar(const T *p) { return *(const __attribute__((address_space(4))) T *)p; }
+
 __device__ __forceinline__ float kahan_det(float a, float b, float c, float d) {
     // a*d - b*c with Kahan's FMA compensation (error ~1 ulp of the result)
     float w = b * c;
@@ -538,32 +544,27 @@ __device__ inline void t5_features(const CutParams &p, const double *x, const do
 
 // T5-DNN forward pass, FP32 vector ALU (weights read with wave-uniform
 // addresses, i.e. through the scalar cache).
-// Read-only load through the constant address space: with a wavefront-uniform
-// address it becomes a scalar load
-__device__ __forceinline__ float ld_uniform(const float *p) {
-    return *(const __attribute__((address_space(4))) float *)p;
-}
 
 __device__ inline float mlp_f32(const ModelDev &m, const float *x) {
     // weights read as uniform constants (scalar loads)
     float xs[kNFeat];
 #pragma unroll
-    for (int k = 0; k < kNFeat; ++k) xs[k] = (x[k] - ld_uniform(m.mu + k)) / ld_uniform(m.sd + k);
+    for (int k = 0; k < kNFeat; ++k) xs[k] = (x[k] - ld_scalar(m.mu + k)) / ld_scalar(m.sd + k);
     float h1[kH1];
 #pragma unroll 4
     for (int j = 0; j < kH1; ++j) {
-        float a = ld_uniform(m.b1 + j);
+        float a = ld_scalar(m.b1 + j);
 #pragma unroll
-        for (int k = 0; k < kNFeat; ++k) a = __builtin_fmaf(ld_uniform(m.W1 + j * kNFeat + k), xs[k], a);
+        for (int k = 0; k < kNFeat; ++k) a = __builtin_fmaf(ld_scalar(m.W1 + j * kNFeat + k), xs[k], a);
         h1[j] = fmaxf(a, 0.0f);
     }
     float o = m.b3;
 #pragma unroll 4
     for (int j = 0; j < kH2; ++j) {
-        float a = ld_uniform(m.b2 + j);
+        float a = ld_scalar(m.b2 + j);
 #pragma unroll
-        for (int k = 0; k < kH1; ++k) a = __builtin_fmaf(ld_uniform(m.W2 + j * kH1 + k), h1[k], a);
-        o = __builtin_fmaf(ld_uniform(m.w3 + j), fmaxf(a, 0.0f), o);
+        for (int k = 0; k < kH1; ++k) a = __builtin_fmaf(ld_scalar(m.W2 + j * kH1 + k), h1[k], a);
+        o = __builtin_fmaf(ld_scalar(m.w3 + j), fmaxf(a, 0.0f), o);
     }
     return 1.0f / (1.0f + expf(-o));
 }

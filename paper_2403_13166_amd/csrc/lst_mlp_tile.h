@@ -70,8 +70,8 @@ __device__ __forceinline__ void mlp_tile_store_row(uint16_t *tile, int r, const 
     uint32_t *dst = reinterpret_cast<uint32_t *>(tile + r * kRowStride);
 #pragma unroll
     for (int k = 0; k < kNFeat; k += 2) {
-        const __bf16 lo = (__bf16)((ft[k] - ld_uniform(m.mu + k)) * (1.0f / ld_uniform(m.sd + k)));
-        const __bf16 hi = (__bf16)((ft[k + 1] - ld_uniform(m.mu + k + 1)) * (1.0f / ld_uniform(m.sd + k + 1)));
+        const __bf16 lo = (__bf16)((ft[k] - ld_scalar(m.mu + k)) * (1.0f / ld_scalar(m.sd + k)));
+        const __bf16 hi = (__bf16)((ft[k + 1] - ld_scalar(m.mu + k + 1)) * (1.0f / ld_scalar(m.sd + k + 1)));
         dst[k / 2] = (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
     }
 }

@@ -292,9 +292,7 @@ __global__ __launch_bounds__(kBlock, S::kMinBlocks) void k_stage_eval(S st, cons
     const TileWalk walk(ntiles);
     // a tile's first and last anchors, read as uniform scalar loads (the tile
     // anchors are read-only here); the next tile's are fetched a tile ahead
-    auto tile_lo = [&](int64_t t) -> int64_t {
-        return *(const __attribute__((address_space(4))) int32_t *)(tile_anchor + t);
-    };
+    auto tile_lo = [&](int64_t t) -> int64_t { return ld_scalar(tile_anchor + t); };
     auto tile_hi = [&](int64_t t) -> int64_t { return t + 1 < ntiles ? tile_lo(t + 1) : na - 1; };
     int64_t alo_n = 0, ahi_n = 0;
     if constexpr (!S::kUnitCount)
@@ -436,10 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_copy(S st, const typename S::R
     if (blockIdx.x == 0 && threadIdx.x == 0) *out_count = tile_pre[ntiles];
     const TileWalk walk(ntiles);
     // a tile's count and output base as uniform scalar loads, one tile ahead
-    auto cnt_of = [&](int64_t t) -> int { return *(const __attribute__((address_space(4))) int32_t *)(tile_cnt + t); };
-    auto pre_of = [&](int64_t t) -> int64_t {
-        return *(const __attribute__((address_space(4))) int64_t *)(tile_pre + t);
-    };
+    auto cnt_of = [&](int64_t t) -> int { return ld_scalar(tile_cnt + t); };
+    auto pre_of = [&](int64_t t) -> int64_t { return ld_scalar(tile_pre + t); };
     int n_n = 0;
     int64_t base_n = 0;
     if (walk.first < walk.end) { n_n = cnt_of(walk.first); base_n = pre_of(walk.first); }
@@ -564,15 +560,16 @@ __global__ __launch_bounds__(1024) void k_bin_tiles(const int64_t *ev_off, int n
 // block -> (event, tile of that event); false past the last tile
 __device__ __forceinline__ bool bin_tile_of(const int64_t *tbase, int n_ev, int &e, int64_t &t, int64_t &nt) {
     const int64_t b = blockIdx.x;
-    if (b >= tbase[n_ev]) return false;
+    if (b >= ld_scalar(tbase + n_ev)) return false;
     int lo = 0, hi = n_ev;                       // largest e with tbase[e] <= b
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (tbase[mid] <= b) lo = mid; else hi = mid;
+        if (ld_scalar(tbase + mid) <= b) lo = mid; else hi = mid;
     }
     e = lo;
-    t = b - tbase[e];
-    nt = tbase[e + 1] - tbase[e];
+    const int64_t t0 = ld_scalar(tbase + e);
+    t = b - t0;
+    nt = ld_scalar(tbase + e + 1) - t0;
     return true;
 }
 
@@ -583,8 +580,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const int32_t *sensor
     int e;
     int64_t t, nt;
     if (!bin_tile_of(tbase, n_ev, e, t, nt)) return;
-    const int64_t h0 = ev_off[e] + t * kBinTile;
-    const int64_t h1 = h0 + kBinTile < ev_off[e + 1] ? h0 + kBinTile : ev_off[e + 1];
+    const int64_t h0 = ld_scalar(ev_off + e) + t * kBinTile, he = ld_scalar(ev_off + e + 1);
+    const int64_t h1 = h0 + kBinTile < he ? h0 + kBinTile : he;
     for (int r = threadIdx.x; r < nr; r += kBinThreads) s_c[r] = 0;
     __syncthreads();
     const float inv = 1.0f / (float)rw;
@@ -662,8 +659,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const float *x, con
     int e;
     int64_t t, nt;
     if (!bin_tile_of(tbase, n_ev, e, t, nt)) return;
-    const int64_t h0 = ev_off[e] + t * kBinTile;
-    const int64_t h1 = h0 + kBinTile < ev_off[e + 1] ? h0 + kBinTile : ev_off[e + 1];
+    const int64_t h0 = ld_scalar(ev_off + e) + t * kBinTile, he = ld_scalar(ev_off + e + 1);
+    const int64_t h1 = h0 + kBinTile < he ? h0 + kBinTile : he;
     const int64_t ebase = tbase[e] * nr + t;
     for (int r = threadIdx.x; r < nr; r += kBinThreads) {
         s_base[r] = cpos[ebase + (int64_t)r * nt];
@@ -740,8 +737,8 @@ __global__ __launch_bounds__(kFineThreads) void k_bin_fine(const float4 *tmp, co
         e = blockIdx.x / nr;
         r = blockIdx.x - e * nr;
     }
-    const int64_t nt = tbase[e + 1] - tbase[e];
-    const int64_t cs = cpos[tbase[e] * nr + (int64_t)r * nt], ce = cpos[tbase[e] * nr + (int64_t)(r + 1) * nt];
+    const int64_t tb = ld_scalar(tbase + e), nt = ld_scalar(tbase + e + 1) - tb;
+    const int64_t cs = ld_scalar(cpos + tb * nr + (int64_t)r * nt), ce = ld_scalar(cpos + tb * nr + (int64_t)(r + 1) * nt);
     const int64_t cnt = ce - cs;
     const int lo = r * rw < n_sens ? r * rw : n_sens;
     const int hi = lo + rw < n_sens ? lo + rw : n_sens;
