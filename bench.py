@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # elementwise kernel), kept with the hash of the kernel sources they were
 # taken on: a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("ls stage", 8): {"bytes": 233860738.4, "source_sha1": "99ffd6ce3feda0da5401c4170efdc364703f7002"},
+    ("ls stage", 8): {"bytes": 234077169.5, "source_sha1": "0ed9f8f9b9bd9cf8f0769003f0c218e8c57550af"},
 }
 KERNEL_SOURCES = ("paper_2403_13166_amd/csrc/lst_pipeline.hip", "paper_2403_13166_amd/csrc/lst_device.h",
                   "paper_2403_13166_amd/csrc/lst_internal.h")
