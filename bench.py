@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # elementwise kernel), kept with the hash of the kernel sources they were
 # taken on: a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("ls stage", 8): {"bytes": 234077169.5, "source_sha1": "0ed9f8f9b9bd9cf8f0769003f0c218e8c57550af"},
+    ("ls stage", 8): {"bytes": 234097599.5, "source_sha1": "824af0f6a5c4dcfd8ba219a934d01a021eb66e8f"},
 }
 KERNEL_SOURCES = ("paper_2403_13166_amd/csrc/lst_pipeline.hip", "paper_2403_13166_amd/csrc/lst_device.h",
                   "paper_2403_13166_amd/csrc/lst_internal.h")
@@ -161,6 +161,39 @@ def measure_extras(b, dx, dy, dz, ds, doff, stream, prec):
         B.lst_set_timing(b.ctx, False)
         out["t5_stage_by_mode"] = t5
     return out
+
+
+def measure_end_to_end(b, step, dev_hits, host_hits, counts, stream, reps):
+    """The batch with its PCIe transfers: hits copied host -> device from
+    pinned memory, the same build, then every object array and the T5
+    scores and chi2 values copied back to pinned host memory, one batch at a
+    time with a host sync per batch (no overlap between batches)."""
+    import torch
+    pinned = [torch.from_numpy(np.ascontiguousarray(h)).pin_memory() for h in host_hits]
+    n_md, n_ls, n_t3, n_t5 = counts[:4]
+    buf = b._buf
+    srcs = [buf["md_hits"][:n_md], buf["ls_md"][:n_ls], buf["t3_ls"][:n_t3], buf["t5_t3"][:n_t5],
+            buf["t5_score"][:n_t5], buf["t5_chi2_rphi"][:n_t5], buf["t5_chi2_rz"][:n_t5], buf["counts"]]
+    outs = [torch.empty(t.shape, dtype=t.dtype, pin_memory=True) for t in srcs]
+    h2d = sum(t.numel() * t.element_size() for t in pinned)
+    d2h = sum(t.numel() * t.element_size() for t in srcs)
+    ts = []
+    with torch.cuda.stream(stream):
+        for i in range(reps + 1):
+            t0 = time.perf_counter()
+            for d, h in zip(dev_hits, pinned):
+                d.copy_(h, non_blocking=True)
+            step()
+            for h, d in zip(outs, srcs):
+                h.copy_(d, non_blocking=True)
+            stream.synchronize()
+            if i:
+                ts.append((time.perf_counter() - t0) * 1e3)
+    got = outs[-1].tolist()[:4]
+    assert got == list(counts[:4]), (got, counts[:4])
+    ms = float(np.median(ts))
+    return {"ms_per_batch": ms, "h2d_bytes": h2d, "d2h_bytes": d2h,
+            "pcie_gb_per_s": (h2d + d2h) / (ms * 1e-3) / 1e9, "batches": reps}
 
 
 def cpu_baseline(geo, evs, seconds):
@@ -302,7 +335,10 @@ def main():
     # ---------------- other rows of the path, each timed with HIP events on its stream
     extras = None
     if not a.skip_extras:
+        e2e = measure_end_to_end(b, step, (dx, dy, dz, ds), (x, y, z, s), final, stream, 10)
+        e2e["events_per_s"] = a.events / (e2e["ms_per_batch"] * 1e-3)
         extras = measure_extras(b, dx, dy, dz, ds, doff, stream, prec)
+        extras["batched_with_pcie"] = e2e
 
     # ---------------- served path: Poisson streams of PU-varying events with
     # continuous batching over HBM-budgeted slots (latency = arrival -> objects on host)

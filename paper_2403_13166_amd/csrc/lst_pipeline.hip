@@ -920,23 +920,41 @@ struct MDStage {
     }
 };
 
-// CSR offsets from a sorted key column: off[k] = first i with key(i) >= k,
-// for k in [0, K]; every entry written exactly once.
-// off[k] = first i < n with key(i) >= k (n if none), for k = 0..K, over keys
-// sorted ascending: one lower-bound search per k, so empty key ranges of any
-// length (modules without MDs, events without hits) cost nothing extra.
+// CSR offsets from a key column sorted ascending: off[k] = first i < n with
+// key(i) >= k (n if none), for k = 0..K. Element i owns the run of keys
+// key(i-1) < k <= key(i) (with key(-1) = -1 and key(n) = K), so the runs
+// partition 0..K, every entry is written once and the key column is read
+// once, coalesced. A lane writes a short run itself; runs longer than
+// kRunLane (modules or events without objects) are written by the whole
+// wavefront, 64 entries a step.
+constexpr int kRunLane = 8;
+
 template <class KF>
-__global__ void k_fill_offsets(KF key, const int64_t *n_dev, int64_t n_cap, const int64_t *K_dev,
-                               int64_t K_cap, int64_t *off) {
+__global__ __launch_bounds__(kBlock) void k_fill_offsets(KF key, const int64_t *n_dev, int64_t n_cap,
+                                                         const int64_t *K_dev, int64_t K_cap, int64_t *off) {
     const int64_t n = n_dev ? dev_count(n_dev, n_cap) : n_cap;
     const int64_t K = K_dev ? dev_count(K_dev, K_cap) : K_cap;
-    for (int64_t k = grid_tid(); k <= K; k += grid_stride()) {
-        int64_t lo = 0, hi = n;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if ((int64_t)key(mid) < k) lo = mid + 1; else hi = mid;
+    const int lane = threadIdx.x & 63;
+    // base is uniform per wavefront, so whole wavefronts run the loop
+    for (int64_t base = grid_tid() - lane; base <= n; base += grid_stride()) {
+        const int64_t i = base + lane;
+        int64_t lo = 1, hi = 0;   // empty run
+        if (i <= n) {
+            const int64_t kp = i > 0 ? (int64_t)key(i - 1) : -1;
+            const int64_t kc = i < n ? (int64_t)key(i) : K;
+            lo = kp < 0 ? 0 : (kp < K ? kp : K) + 1;
+            hi = kc < K ? kc : K;
         }
-        off[k] = lo;
+        const bool wide = hi - lo >= kRunLane;
+        if (!wide)
+            for (int64_t k = lo; k <= hi; ++k) off[k] = i;
+        unsigned long long m = __ballot(wide);
+        while (m) {
+            const int l = __ffsll(m) - 1;
+            m &= m - 1;
+            const int64_t rlo = __shfl(lo, l, 64), rhi = __shfl(hi, l, 64);
+            for (int64_t k = rlo + lane; k <= rhi; k += 64) off[k] = base + l;
+        }
     }
 }
 
@@ -1455,7 +1473,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     // a2: mini-doublets, anchored on (event, module)
     MDStage md{w.bin_off, w.bin_hit, a.g.mod, a.p, n_mod, n_sens, o.md_hits, w.md_a, w.md_o, w.md_rq};
     run_stage(md, nullptr, ngm, w, cnt + LST_COUNT_MD, w.cap_md, cnt, st, ev, 2, a.tune);
-    hipLaunchKernelGGL(k_fill_offsets<GmKey>, dim3(grid_for(ngm + 1)), dim3(kBlock), 0, st, GmKey{w.md_a},
+    hipLaunchKernelGGL(k_fill_offsets<GmKey>, dim3(grid_for(w.cap_md + 1)), dim3(kBlock), 0, st, GmKey{w.md_a},
                        cnt + LST_COUNT_MD, w.cap_md, nullptr, ngm, w.md_mod_off);
     hipLaunchKernelGGL(k_ls_prefix, dim3(grid_for(ngm * kPrefSeg)), dim3(kBlock), 0, st, a.g.map_off, a.g.map_tgt, n_mod,
                        n_map, a.n_ev, w.md_mod_off, w.rsum, w.rpref);
@@ -1465,13 +1483,13 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     LSStage ls{w.md_a, w.md_o, w.md_rq, w.md_mod_off, w.rsum, w.rpref, a.g.map_off, a.g.map_tgt, a.g.mod, a.p,
                n_mod, n_map, o.ls_md};
     run_stage(ls, nullptr, ngm, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st, ev, 3, a.tune);
-    hipLaunchKernelGGL(k_fill_offsets<LsInKey>, dim3(grid_for(w.cap_md + 1)), dim3(kBlock), 0, st, LsInKey{o.ls_md},
+    hipLaunchKernelGGL(k_fill_offsets<LsInKey>, dim3(grid_for(w.cap_ls + 1)), dim3(kBlock), 0, st, LsInKey{o.ls_md},
                        cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w.ls_off);
 
     // a4: triplets, anchored on the inner LS
     T3Stage t3{o.ls_md, w.ls_off, w.md_a, w.md_o, w.md_rq, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
     run_stage(t3, cnt + LST_COUNT_LS, w.cap_ls, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st, ev, 4, a.tune);
-    hipLaunchKernelGGL(k_fill_offsets<T3InKey>, dim3(grid_for(w.cap_md + 1)), dim3(kBlock), 0, st, T3InKey{w.t3_mds},
+    hipLaunchKernelGGL(k_fill_offsets<T3InKey>, dim3(grid_for(w.cap_t3 + 1)), dim3(kBlock), 0, st, T3InKey{w.t3_mds},
                        cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w.t3i_off);
 
     // a5: quintuplets, anchored on the inner T3: FP32 beam-line cuts, then the
