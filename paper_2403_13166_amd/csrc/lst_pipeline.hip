@@ -959,10 +959,12 @@ __global__ __launch_bounds__(kBlock) void k_fill_offsets(KF key, const int64_t *
 }
 
 // Per (event, module): rsum = MDs in the module's mapped modules, and for each
-// map entry the exclusive prefix of those counts along the module's row. One
-// 16-lane segment per (event, module) takes the row 16 entries at a time with
-// a segmented scan, so the row's reads and writes are coalesced.
+// map entry the exclusive prefix of those counts along the module's row. A
+// 16-lane segment takes a row 16 entries at a time with a segmented scan, so
+// the row's reads and writes are coalesced; it works on kPrefRows rows at
+// once, whose dependent loads (row bounds, entry, MD offsets) overlap.
 constexpr int kPrefSeg = 16;
+constexpr int kPrefRows = 2;   // rows a segment works on at once, for independent loads in flight
 
 __global__ __launch_bounds__(kBlock) void k_ls_prefix(const int32_t *map_off, const int32_t *map_tgt,
                                                       int32_t n_mod, int32_t n_map, int32_t n_ev,
@@ -970,27 +972,51 @@ __global__ __launch_bounds__(kBlock) void k_ls_prefix(const int32_t *map_off, co
     const int64_t N = (int64_t)n_ev * n_mod;
     const int sl = threadIdx.x & (kPrefSeg - 1);
     const int64_t nseg = grid_stride() / kPrefSeg;
-    for (int64_t gm = grid_tid() / kPrefSeg; gm < N; gm += nseg) {
-        const int64_t e = gm / n_mod, m = gm - e * n_mod;
-        const int32_t k0 = map_off[m], k1 = map_off[m + 1];
-        int32_t acc = 0;
-        for (int32_t kb = k0; kb < k1; kb += kPrefSeg) {
-            const int32_t k = kb + sl;
-            int32_t c = 0;
-            if (k < k1) {
-                const int64_t t = e * n_mod + map_tgt[k];
-                c = (int32_t)(md_mod_off[t + 1] - md_mod_off[t]);
-            }
-            int32_t v = c;
+    const bool small = N <= (int64_t)UINT32_MAX;   // 32-bit division suffices
+    for (int64_t g0 = grid_tid() / kPrefSeg; g0 < N; g0 += kPrefRows * nseg) {
+        int64_t ev[kPrefRows];
+        int32_t k0[kPrefRows], k1[kPrefRows], acc[kPrefRows];
+        int32_t len = 0;
 #pragma unroll
-            for (int d = 1; d < kPrefSeg; d <<= 1) {
-                const int32_t o = __shfl_up(v, d, kPrefSeg);
-                if (sl >= d) v += o;
-            }
-            if (k < k1) rpref[e * n_map + k] = acc + v - c;
-            acc += __shfl(v, kPrefSeg - 1, kPrefSeg);
+        for (int j = 0; j < kPrefRows; ++j) {
+            const int64_t gm = g0 + j * nseg;
+            const bool ok = gm < N;
+            const int64_t gc = ok ? gm : 0;
+            ev[j] = small ? (int64_t)((uint32_t)gc / (uint32_t)n_mod) : gc / n_mod;
+            const int64_t m = gc - ev[j] * n_mod;
+            k0[j] = map_off[m];
+            k1[j] = map_off[m + 1];
+            if (!ok) k1[j] = k0[j];
+            acc[j] = 0;
+            len = k1[j] - k0[j] > len ? k1[j] - k0[j] : len;
         }
-        if (sl == 0) rsum[gm] = acc;
+        for (int32_t kb = 0; kb < len; kb += kPrefSeg) {
+            // every row's loads first, from clamped indices (entry 0 when
+            // the row has ended: len > 0 means some row has an entry)
+            int32_t c[kPrefRows];
+#pragma unroll
+            for (int j = 0; j < kPrefRows; ++j) {
+                const int32_t k = k0[j] + kb + sl;
+                const int64_t t = ev[j] * n_mod + map_tgt[k < k1[j] ? k : 0];
+                c[j] = (int32_t)(md_mod_off[t + 1] - md_mod_off[t]);
+            }
+#pragma unroll
+            for (int j = 0; j < kPrefRows; ++j) {
+                const int32_t k = k0[j] + kb + sl;
+                const int32_t cj = k < k1[j] ? c[j] : 0;
+                int32_t v = cj;
+#pragma unroll
+                for (int d = 1; d < kPrefSeg; d <<= 1) {
+                    const int32_t o = __shfl_up(v, d, kPrefSeg);
+                    if (sl >= d) v += o;
+                }
+                if (k < k1[j]) rpref[ev[j] * n_map + k] = acc[j] + v - cj;
+                acc[j] += __shfl(v, kPrefSeg - 1, kPrefSeg);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kPrefRows; ++j)
+            if (sl == 0 && g0 + j * nseg < N) rsum[g0 + j * nseg] = acc[j];
     }
 }
 
@@ -1475,7 +1501,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     run_stage(md, nullptr, ngm, w, cnt + LST_COUNT_MD, w.cap_md, cnt, st, ev, 2, a.tune);
     hipLaunchKernelGGL(k_fill_offsets<GmKey>, dim3(grid_for(w.cap_md + 1)), dim3(kBlock), 0, st, GmKey{w.md_a},
                        cnt + LST_COUNT_MD, w.cap_md, nullptr, ngm, w.md_mod_off);
-    hipLaunchKernelGGL(k_ls_prefix, dim3(grid_for(ngm * kPrefSeg)), dim3(kBlock), 0, st, a.g.map_off, a.g.map_tgt, n_mod,
+    hipLaunchKernelGGL(k_ls_prefix, dim3(grid_for((ngm + kPrefRows - 1) / kPrefRows * kPrefSeg)), dim3(kBlock), 0, st, a.g.map_off, a.g.map_tgt, n_mod,
                        n_map, a.n_ev, w.md_mod_off, w.rsum, w.rpref);
 
     // a3: line segments, anchored on (event, module): the module's MDs against
