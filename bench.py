@@ -203,14 +203,16 @@ def cpu_baseline(geo, evs, seconds):
     om = O.Model(M.make_model().to_blob())
     t0 = time.perf_counter()
     n = 0
-    for ev in evs:
+    # the batch's events in order, again from the first while time is left
+    # (at most three passes)
+    while n < 3 * len(evs) and time.perf_counter() - t0 <= seconds:
+        ev = evs[n % len(evs)]
         O.build_objects(og, om, ev.x, ev.y, ev.z, ev.sensor, mode=0)
         n += 1
-        if time.perf_counter() - t0 > seconds:
-            break
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} of the {len(evs)} batch events, FP64 C oracle, one thread, {dt:.1f} s"}
+            "sample": f"{n} builds of the {len(evs)} batch events taken in order (cycling), "
+                      f"FP64 C oracle, one thread, {dt:.1f} s"}
 
 
 def main():
