@@ -1414,10 +1414,15 @@ __global__ __launch_bounds__(kTileRows, 3) void k_t5_score_mfma(T5FitStage<false
     }
 }
 
+// One resident wave of blocks (3 per CU on 256 CUs) that walk the tiles, so
+// each block stages the weights once for several tiles and no second round of
+// blocks waits behind the first.
+constexpr int kScoreGrid = 3 * 256;
+
 static inline int grid_for_tiles(int64_t n) {
     int64_t g = (n + kTileRows - 1) / kTileRows;
     if (g < 1) g = 1;
-    if (g > 4096) g = 4096;
+    if (g > kScoreGrid) g = kScoreGrid;
     return (int)g;
 }
 
