@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # elementwise kernel), kept with the hash of the kernel sources they were
 # taken on: a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("ls stage", 8): {"bytes": 234101714.2, "source_sha1": "83cc33b8a973e10964fe7b9cfb1d8479cee18359"},
+    ("ls stage", 8): {"bytes": 234035314.1, "source_sha1": "271eda82f324af414d58440acac96e9cfa6cc28a"},
 }
 KERNEL_SOURCES = ("paper_2403_13166_amd/csrc/lst_pipeline.hip", "paper_2403_13166_amd/csrc/lst_device.h",
                   "paper_2403_13166_amd/csrc/lst_internal.h")

@@ -1429,26 +1429,48 @@ static inline int grid_for_tiles(int64_t n) {
 // ---------------------------------------------------- per-event offsets
 
 // Per-event first indices: MD from the module offsets, LS from the LS CSR by
-// inner MD, T3 from the T3 CSR by inner MD (T3 are sorted by it), T5 by one
+// inner MD, T3 from the T3 CSR by inner MD (T3 are sorted by it), T5 by a
 // search over their inner T3 (T5 are sorted by it).
-__global__ void k_event_offsets(const int64_t *md_mod_off, const int64_t *ls_off, const int64_t *t3i_off,
-                                const int2 *t5_t3, const int64_t *counts, int64_t cap_md, int64_t cap_t5,
-                                int32_t n_mod, int32_t n_ev, int64_t *out) {
-    int e = threadIdx.x + blockIdx.x * blockDim.x;
-    if (e > n_ev) return;
-    int64_t nmd = dev_count(counts + 0, cap_md), nt5 = dev_count(counts + 3, cap_t5);
+__global__ __launch_bounds__(64) void k_event_offsets(const int64_t *md_mod_off, const int64_t *ls_off,
+                                                      const int64_t *t3i_off, const int2 *t5_t3,
+                                                      const int64_t *counts, int64_t cap_md, int64_t cap_t5,
+                                                      int32_t n_mod, int32_t n_ev, int64_t *out) {
+    // one wavefront per event boundary e = 0..n_ev
+    const int e = blockIdx.x, lane = threadIdx.x;
+    const int64_t nmd = dev_count(counts + 0, cap_md), nt5 = dev_count(counts + 3, cap_t5);
     int64_t md0 = md_mod_off[(int64_t)e * n_mod];
     if (md0 > nmd) md0 = nmd;
     const int64_t ls0 = ls_off[md0], t30 = t3i_off[md0];
+    // first T5 whose inner T3 is >= t30, by a 64-way search: the answer
+    // stays in [lo, hi]; each step probes 64 evenly spaced entries and keeps
+    // the gap between the last probe below t30 and the first one not below
     int64_t lo = 0, hi = nt5;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (t5_t3[mid].x < t30) lo = mid + 1; else hi = mid;
+    while (hi - lo > 64) {
+        const int64_t step = (hi - lo + 63) / 64;
+        const int64_t p = lo + lane * step;
+        const bool below = p < hi && t5_t3[p].x < t30;
+        const int c = __popcll(__ballot(below));   // the probes below t30 are a prefix
+        const int64_t l0 = lo;
+        if (c == 0) {
+            hi = lo;
+        } else {
+            lo = l0 + (int64_t)(c - 1) * step + 1;
+            const int64_t pc = l0 + (int64_t)c * step;
+            if (pc < hi) hi = pc;
+        }
     }
-    out[0 * (n_ev + 1) + e] = md0;
-    out[1 * (n_ev + 1) + e] = ls0;
-    out[2 * (n_ev + 1) + e] = t30;
-    out[3 * (n_ev + 1) + e] = lo;
+    int64_t t50 = lo;
+    if (hi > lo) {
+        const int64_t q = lo + lane;
+        const bool below = q < hi && t5_t3[q].x < t30;
+        t50 = lo + __popcll(__ballot(below));
+    }
+    if (lane == 0) {
+        out[0 * (n_ev + 1) + e] = md0;
+        out[1 * (n_ev + 1) + e] = ls0;
+        out[2 * (n_ev + 1) + e] = t30;
+        out[3 * (n_ev + 1) + e] = t50;
+    }
 }
 
 // ------------------------------------------------------------- pipeline
@@ -1552,7 +1574,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
                            cnt + LST_COUNT_T5, w.cap_t5, o.t5_score, o.t5_feat, 1);
     mark(ev, 13, st);
     if (a.ev_obj_off) {
-        hipLaunchKernelGGL(k_event_offsets, dim3((a.n_ev + 64) / 64), dim3(64), 0, st, w.md_mod_off, w.ls_off,
+        hipLaunchKernelGGL(k_event_offsets, dim3(a.n_ev + 1), dim3(64), 0, st, w.md_mod_off, w.ls_off,
                            w.t3i_off, o.t5_t3, cnt, w.cap_md, w.cap_t5, n_mod, a.n_ev, a.ev_obj_off);
     }
     mark(ev, 1, st);
