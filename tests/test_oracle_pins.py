@@ -356,6 +356,176 @@ def test_resolution_terms_keep_one_sigma_fraction():
     assert abs(np.mean(acc["chi2_rz"]) - 3.0) < 0.3
 
 
+def _hits_by_track(g, tracks, sigma, rng):
+    xs, ys, zs, sens, tid = E._track_hits(g, *(tracks[:, i] for i in range(5)), sigma, rng)
+    by_track = {}
+    for k in range(len(xs)):
+        by_track.setdefault(int(tid[k]), []).append((xs[k], ys[k], zs[k], int(sens[k])))
+    return by_track
+
+
+def test_endcap_radial_terms_at_the_curvature_limit():
+    """Tracks exactly at pT = pT_min (c = c_max), z_v on the edge of the
+    luminous region on their own side, with sigma_rphi = 0 (no azimuthal
+    smearing and no sigma_rphi term in any tolerance) and n_sigma = 1. Only
+    the endcap radius is smeared, so what remains of each tolerance is its
+    sigma_r term, and the true value sits on the envelope:
+    * MD-E1: the bend g asin(c r)/|z - z_v| is exact, the envelope is taken
+      at the measured radius; the cut passes iff dr >= -sigma_r to first
+      order, a one-sided fraction Phi(1) = 0.841 (without the term: 0.5);
+    * LS1 on endcap-endcap and barrel-endcap pairs: a radial shift of an
+      endcap anchor moves the beam-line curvature by c_max dr / |B - A| to
+      first order, which is the c_max^2 sigma_r^2 term; one-sided again."""
+    g, og = _geo_variant(sigma_rphi=0.0, n_sigma=1.0, md_e2_slack=0.0, ls3_slack=0.0)
+    Z, pmin = g.params["z_lum"], g.params["pt_min"]
+    rng = np.random.default_rng(5)
+    n = 2500
+    eta = rng.uniform(1.3, 2.4, n) * np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    tracks = np.stack([np.where(rng.random(n) < 0.5, -1.0, 1.0), np.full(n, pmin), eta,
+                       rng.uniform(0, 2 * math.pi, n), np.sign(eta) * Z], axis=1)
+    acc = {"MD-E1": [], "LS1 endcap-endcap": [], "LS1 barrel-endcap": []}
+    for hl in _hits_by_track(g, tracks, 1.0, rng).values():
+        pairs = H.md_pairs(g, hl)
+        for (lay, a, o) in pairs:
+            if g.kind[a[3] // 2] == 1:
+                acc["MD-E1"].append(_cv(og, None, [a, o], 1).passes()[0])
+        for (la, a, a2), (lb, b, b2) in zip(pairs, pairs[1:]):
+            ka, kb = g.kind[a[3] // 2], g.kind[b[3] // 2]
+            if ka == 0 and kb == 0:
+                continue
+            key = "LS1 endcap-endcap" if ka and kb else "LS1 barrel-endcap"
+            acc[key].append(_cv(og, None, [a, a2, b, b2], 2).passes()[1])
+    target = 0.5 * (1 + math.erf(1 / math.sqrt(2)))
+    for k, v in acc.items():
+        assert len(v) > 1500, k
+        assert abs(float(np.mean(v)) - target) < 0.035, (k, float(np.mean(v)))
+
+
+def test_endcap_resolution_terms_keep_one_sigma_fraction():
+    """Envelope terms off (pT_min -> inf, Z -> 0), n_sigma = 1, straight
+    smeared tracks from the origin: LS1 and LS2 keep ~68.3 % of endcap-endcap
+    and barrel-endcap pairs. In LS2 the endcap anchor contributes through the
+    slope k times its arc-length error, weighted by the other anchor's arc
+    length (dz0/ds_A = -s_B k / (s_B - s_A)), so exchanging the two anchors'
+    radial terms, or giving an endcap anchor a z resolution, moves the
+    barrel-endcap fraction away from 68.3 %."""
+    g, og = _geo_variant(pt_min=1e7, z_lum=0.0, n_sigma=1.0, md_e2_slack=0.0, ls3_slack=0.0)
+    rng = np.random.default_rng(23)
+    n = 4000
+    # |eta| <= 1.8: slopes small enough that a z resolution wrongly given to
+    # an endcap anchor would add a visible share of the z0 variance
+    tracks = np.stack([np.ones(n), np.full(n, 1e9), rng.uniform(0.9, 1.8, n) * np.where(rng.random(n) < 0.5, -1, 1),
+                       rng.uniform(0, 2 * math.pi, n), np.zeros(n)], axis=1)
+    acc = {k: [] for k in ("LS1 ee", "LS2 ee", "LS1 be", "LS2 be")}
+    for hl in _hits_by_track(g, tracks, 1.0, rng).values():
+        pairs = H.md_pairs(g, hl)
+        for (la, a, a2), (lb, b, b2) in zip(pairs, pairs[1:]):
+            ka, kb = g.kind[a[3] // 2], g.kind[b[3] // 2]
+            if ka == 0 and kb == 0:
+                continue
+            key = "ee" if ka and kb else "be"
+            p = _cv(og, None, [a, a2, b, b2], 2).passes()
+            acc["LS1 " + key].append(p[1]); acc["LS2 " + key].append(p[3])
+    target = math.erf(1 / math.sqrt(2))
+    for k, v in acc.items():
+        assert len(v) > 1500, k
+        assert abs(float(np.mean(v)) - target) < 0.035, (k, float(np.mean(v)))
+
+
+def test_endcap_fit_weights_give_chi2_dof():
+    """Same envelope-free smeared straight tracks; quintuplets whose five
+    anchors are all endcap (|eta| >= 1.8) or mixed. An endcap anchor has an
+    exact z and a radius smeared by sigma_r, so its r-z residual is
+    |k| sigma_r with k the r-z slope: with those weights chi2_rz follows
+    chi2(3), mean 3 (without the |k| factor the mean would be 3 k^2 >= 10).
+    The circle fit weights endcap anchors by sigma_r; on a straight track a
+    radial shift moves a point along the line, so only the azimuthal
+    smearing is left and the mean chi2_rphi is 2 (sigma_rphi / sigma_r)^2."""
+    g, og = _geo_variant(pt_min=1e7, z_lum=0.0, n_sigma=1.0, md_e2_slack=0.0, ls3_slack=0.0)
+    rng = np.random.default_rng(29)
+    out = {"endcap": ([], []), "mixed": ([], [])}
+    for lo, hi, n in ((1.8, 2.4, 5000), (0.9, 1.5, 1500)):
+        tracks = np.stack([np.ones(n), np.full(n, 1e9), rng.uniform(lo, hi, n) * np.where(rng.random(n) < 0.5, -1, 1),
+                           rng.uniform(0, 2 * math.pi, n), np.zeros(n)], axis=1)
+        for hl in _hits_by_track(g, tracks, 1.0, rng).values():
+            pairs = H.md_pairs(g, hl)
+            if len(pairs) < 5:
+                continue
+            kinds = [int(g.kind[pp[1][3] // 2]) for pp in pairs[:5]]
+            if not any(kinds):
+                continue
+            hl5 = []
+            for (_, a, a2) in pairs[:5]:
+                hl5 += [a, a2]
+            cv = _cv(og, None, hl5, 4, mode=1)
+            key = "endcap" if all(kinds) else "mixed"
+            out[key][0].append(cv.detail[0]); out[key][1].append(cv.detail[1])
+    ratio = 2.0 * (g.params["sigma_rphi"] / g.params["sigma_r"]) ** 2
+    for key in ("endcap", "mixed"):
+        rphi, rz = out[key]
+        assert len(rz) > 500, (key, len(rz))
+        # chi2(3): standard deviation of the mean is sqrt(6 / n)
+        assert abs(np.mean(rz) - 3.0) < 4 * math.sqrt(6.0 / len(rz)), (key, np.mean(rz))
+    assert abs(np.mean(out["endcap"][0]) / ratio - 1.0) < 0.2, np.mean(out["endcap"][0])
+
+
+def _anchor_closed_forms(g, q, pt, eta, phi0, zv, a):
+    """Anchor features of a noise-free beam-line track at crossing a, from the
+    helix alone: radius, polar angle, z, pseudorapidity of the point, logical
+    layer (barrel index of the cylinder + 1, or 7 + index of the disk) and
+    the endcap flag."""
+    c = H.half_curvature(g, pt)
+    x, y, z, sens = a
+    r = math.hypot(x, y)
+    for li, rk in enumerate(G.BARREL_RADII):
+        if abs(r - rk) < 1e-6:
+            s = math.asin(c * rk) / c
+            return [rk, phi0 - q * math.asin(c * rk), zv + s * math.sinh(eta),
+                    math.asinh((zv + s * math.sinh(eta)) / rk), li + 1, 0]
+    for di, zd in enumerate(G.DISK_Z):
+        if abs(abs(z) - zd) < 1e-9:
+            s = (z - zv) / math.sinh(eta)
+            rr = math.sin(c * s) / c
+            return [rr, phi0 - q * c * s, z, math.asinh(z / rr), 7 + di, 1]
+    raise AssertionError("crossing on no anchor surface")
+
+
+def test_anchor_features_and_chi2_features_closed_forms(geo_full, og_full, om):
+    """Features 0-29 of a noise-free quintuplet equal the helix closed forms
+    of its five anchors; features 38-39 are log1p of the two fit chi2 values
+    (checked on smeared tracks, where the chi2 are not zero)."""
+    g = geo_full
+    rng = np.random.default_rng(31)
+    n_done = n_end = 0
+    for _ in range(300):
+        q = rng.choice([-1.0, 1.0]); pt = rng.uniform(0.9, 30); eta = rng.uniform(-2.3, 2.3)
+        phi0 = rng.uniform(0, 2 * math.pi); zv = rng.uniform(-12, 12)
+        pairs = _track_pairs(g, q, pt, eta, phi0, zv)
+        if len(pairs) < 5:
+            continue
+        hl = []
+        for (_, a, a2) in pairs[:5]:
+            hl += [a, a2]
+        f = _cv(og_full, om, hl, 4, mode=1).feat
+        for i, (_, a, _a2) in enumerate(pairs[:5]):
+            exp = _anchor_closed_forms(g, q, pt, eta, phi0, zv, a)
+            got = f[6 * i:6 * i + 6]
+            assert abs(got[0] - exp[0]) < 1e-9 * exp[0], (i, got, exp)
+            assert abs(math.remainder(got[1] - exp[1], 2 * math.pi)) < 1e-9, (i, got, exp)
+            assert abs(got[2] - exp[2]) < 1e-8 and abs(got[3] - exp[3]) < 1e-9, (i, got, exp)
+            assert got[4] == exp[4] and got[5] == exp[5], (i, got, exp)
+            n_end += exp[5]
+        n_done += 1
+    assert n_done > 100 and n_end > 100
+    # chi2 features on smeared tracks
+    ev = E.make_event_from_tracks(g, E.make_tracks(E.PU200, rng, 400), 0, 1.0, rng, shuffle=False)
+    r = O.build_objects(og_full, om, ev.x, ev.y, ev.z, ev.sensor)
+    assert len(r.t5) > 200
+    assert np.max(np.abs(r.feat[:, 38] - np.log1p(r.chi2_rphi))) < 1e-12
+    assert np.max(np.abs(r.feat[:, 39] - np.log1p(r.chi2_rz))) < 1e-12
+    assert np.max(r.chi2_rz) > 1.0 and np.max(r.chi2_rphi) > 1.0
+
+
 # ----------------------------------------------------------------- fits and MLP
 
 def _taubin_pencil(x, y, sig):
