@@ -12,7 +12,11 @@ Also measured (reported beside the headline, never as `value`):
     after each event (events/s, p50/p99 latency);
   * per-stage kernel durations from HIP events recorded on the launch stream
     inside the timed region, and the roofline of the dominant kernel;
-  * the FP64 oracle on a bounded sample of the same events, single thread.
+  * per-stage windows of the eval kernels and of the whole stages (scans,
+    copies and CSR fills included), with compulsory bytes per stage;
+  * the plain and served paths on the same Poisson arrivals (PCIe included);
+  * the FP64 oracle on a bounded sample of the same events, on one thread and
+    on one thread per usable host core (host CPU model stated).
 """
 from __future__ import annotations
 
@@ -66,10 +70,10 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=None,
                     help='fixed launch shapes as JSON {"bin_split", "tile_per": [5], "eval_blocks"} (no autotuning)')
-    ap.add_argument("--plain-events", type=int, default=16)
+    ap.add_argument("--plain-events", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-events", type=int, default=2000,
+    ap.add_argument("--serve-events", type=int, default=5000,
                     help="events per served stream (0: skip the serving measurement)")
     ap.add_argument("--serve-rates", default="500,20000",
                     help="Poisson arrival rates (events/s) of the served streams; the largest saturates the GPU")
@@ -88,21 +92,34 @@ def make_batch(n_events: int, batch_seed: int):
     return geo, evs
 
 
-def stage_bytes(c, n_hits, n_ev, n_mod, n_map):
-    """Algorithmic HBM bytes per launch of each stage kernel: every input
-    record read once and every output written once."""
+def stage_bytes(c, n_hits, n_ev, n_mod, n_sens):
+    """Compulsory (algorithmic) HBM bytes of each stage per launch: every
+    input record read once and every output record written once, at the
+    record sizes of the object layouts (hits 16 B; an MD 32 B: two hit
+    indices, anchor position, chord; an LS 12 B: two MD indices and its
+    curvature; a T3 12 B; a T5 20 B: two T3 indices, two chi2, score), plus
+    the CSR offsets (8 B per entry) a stage reads or writes. The same bytes
+    are used for a stage's eval kernel and for the whole stage."""
     md, ls, t3, t5 = c[:4]
     em = n_ev * n_mod
     # features come from the T5's T3 pair, its MDs and the fit outputs, and
     # stay on chip (LDS) until the score is written
     score = (8 + 32 + 4) * t5 + 16 * t3 + 16 * md
     return {
-        "md": 16 * n_hits + 24 * em + 32 * md,
-        "ls": 36 * md + 4 * n_map * n_ev + 8 * em + 8 * ls,
-        "t3": 12 * ls + 48 * md + 24 * t3,
-        "t5": 24 * t3 + 40 * md + 16 * t5,
+        "bin": 16 * n_hits + 16 * n_hits + 8 * n_ev * n_sens,
+        "md": 16 * n_hits + 32 * md,
+        "ls": 32 * md + 12 * ls + 8 * em,
+        "t3": 12 * ls + 32 * md + 8 * md + 12 * t3,
+        "t5": 12 * t3 + 32 * md + 20 * t5,
         "score": score,
     }
+
+
+def implementation_bytes(n_ev, n_map):
+    """Bytes the build moves beyond the compulsory ones: the LS stage's
+    per-(event, map entry) prefix table of target-MD counts (written once by
+    the prefix kernel and read back by the eval kernel's staging)."""
+    return {"ls_entry_prefix_table": 2 * 4 * n_map * n_ev}
 
 
 def _time_ms(fn, stream, reps=10):
@@ -196,23 +213,56 @@ def measure_end_to_end(b, step, dev_hits, host_hits, counts, stream, reps):
             "pcie_gb_per_s": (h2d + d2h) / (ms * 1e-3) / 1e9, "batches": reps}
 
 
+def host_cpu():
+    """Model name and logical CPU count of this host, and the CPUs this
+    process may run on (the CPU share of a GPU machine)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count(), "usable": usable}
+
+
 def cpu_baseline(geo, evs, seconds):
+    """The FP64 oracle on the batch's events, in order and cycling, for a
+    bounded time: once on one thread, once on one thread per usable core
+    (events distributed over threads; the oracle call releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
     from paper_2403_13166_amd.synth import model as M
     og = O.Geom(geo.to_blob())
     om = O.Model(M.make_model().to_blob())
-    t0 = time.perf_counter()
-    n = 0
-    # the batch's events in order, again from the first while time is left
-    # (at most three passes)
-    while n < 3 * len(evs) and time.perf_counter() - t0 <= seconds:
-        ev = evs[n % len(evs)]
-        O.build_objects(og, om, ev.x, ev.y, ev.z, ev.sensor, mode=0)
-        n += 1
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} builds of the {len(evs)} batch events taken in order (cycling), "
-                      f"FP64 C oracle, one thread, {dt:.1f} s"}
+    build = lambda ev: O.build_objects(og, om, ev.x, ev.y, ev.z, ev.sensor, mode=0)
+    cpu = host_cpu()
+    # at most 16 threads: the CPU share of one GPU
+    nthr = max(1, min(cpu["usable"], 16))
+
+    def leg(threads, budget):
+        t0 = time.perf_counter()
+        n = 0
+        with ThreadPoolExecutor(threads) as pool:
+            while n < 3 * len(evs) and time.perf_counter() - t0 <= budget:
+                chunk = [evs[(n + k) % len(evs)] for k in range(threads)]
+                list(pool.map(build, chunk))
+                n += threads
+        return n, time.perf_counter() - t0
+
+    n1, dt1 = leg(1, seconds / 2)
+    nn, dtn = leg(nthr, seconds / 2)
+    return {"value": nn / dtn, "unit": "events/s", "cores": nthr, "kind": "oracle",
+            "sample": f"{nn} builds of the {len(evs)} batch events taken in order (cycling), FP64 C oracle, "
+                      f"{nthr} threads over events, {dtn:.1f} s; single thread: {n1} builds in {dt1:.1f} s",
+            "single_thread_events_per_s": n1 / dt1, "host_cpu": cpu["model"], "nproc": cpu["nproc"],
+            "usable_cpus": cpu["usable"]}
 
 
 def main():
@@ -351,12 +401,19 @@ def main():
         slots = [(250_000, 1), (4_800_000, 48), (4_800_000, 48), (4_800_000, 48)]
         served = {"pool": "32 events, PU ~ U[50, 200], 30 tracks + 500 noise hits per unit PU",
                   "slots": slots, "budget_gib": 64, "streams": []}
+        keys = ("rate", "events", "events_per_s", "p50_ms", "p99_ms", "mean_batch", "max_batch", "max_inflight")
         for rate in [float(r) for r in a.serve_rates.split(",")]:
             st = S.serve_stream(sgeo, pool, rate, a.serve_events, slots, 64 << 30, mode=mode, precision=prec)
-            served["streams"].append({k: st[k] for k in ("rate", "events", "events_per_s", "p50_ms", "p99_ms",
-                                                         "mean_batch", "max_batch", "max_inflight")})
-            print(f"served stream at {rate:.0f} ev/s: {st['events_per_s']:.1f} ev/s, p50 {st['p50_ms']:.2f} ms, "
-                  f"p99 {st['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+            row = {k: st[k] for k in keys}
+            # the plain path on the same arrivals: one single-event slot, one
+            # eager build per event (PCIe included on both paths)
+            pl = S.serve_stream(sgeo, pool, rate, a.serve_events, [(max(e.n for e in pool), 1)], 64 << 30,
+                                mode=mode, precision=prec, use_graph=False)
+            row["plain"] = {k: pl[k] for k in ("events_per_s", "p50_ms", "p99_ms")}
+            served["streams"].append(row)
+            print(f"stream at {rate:.0f} ev/s: served {st['events_per_s']:.1f} ev/s, p50 {st['p50_ms']:.2f} ms, "
+                  f"p99 {st['p99_ms']:.2f} ms; plain {pl['events_per_s']:.1f} ev/s, p50 {pl['p50_ms']:.2f} ms, "
+                  f"p99 {pl['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
 
     if a.copy_calibration_mb > 0:
         # one plain elementwise kernel that reads and writes exactly this many
@@ -370,14 +427,19 @@ def main():
     avg = {k: float(np.mean(v)) for k, v in stage_ms.items()}
     kern = {k: avg[k] for k in ("md", "ls", "t3", "t5", "score")}
     dom = max(kern, key=kern.get)
-    sb = stage_bytes(final, len(x), a.events, geo.n_modules, int(geo.map_tgt.shape[0]))
+    sb = stage_bytes(final, len(x), a.events, geo.n_modules, geo.n_sensors)
     achieved = sb[dom] / (avg[dom] * 1e-3) / 1e9
     stage_idx = {"md": 0, "ls": 1, "t3": 2, "t5": 4}
     tile = tuned["tile_per"][stage_idx[dom]] if dom in stage_idx else None
-    roofline = {"bound": "hbm", "kernel": f"{dom} stage", "achieved": achieved, "peak": HBM_PEAK_GBS,
+    roofline = {"bound": "hbm", "kernel": f"{dom} stage eval kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"{dom} stage", tile),
                 "algorithmic_bytes_per_launch": sb[dom], "avg_launch_ms": avg[dom]}
     stage_gbs = {k: sb[k] / (avg[k] * 1e-3) / 1e9 for k in kern}
+    # whole stages: count scan, eval, tile scan, copy, CSR fill (LS: and its map prefix)
+    whole = {"bin": avg["bin"], "md": avg["md_all"], "ls": avg["ls_all"], "t3": avg["t3_all"], "t5": avg["t5"],
+             "score": avg["score"]}
+    stage_whole = {k: {"ms": v, "gb_per_s": sb[k] / (v * 1e-3) / 1e9,
+                       "frac_hbm": sb[k] / (v * 1e-3) / 1e9 / HBM_PEAK_GBS} for k, v in whole.items()}
 
     cpu = None
     if not a.skip_cpu_baseline:
@@ -398,7 +460,8 @@ def main():
                   "p99_ms": float(np.percentile(plain_lat, 99))},
         "batch_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "speedup_batched_vs_plain": value / plain_rate,
-        "stage_ms": avg, "stage_gbs": stage_gbs,
+        "stage_ms": avg, "stage_gbs": stage_gbs, "stage_whole": stage_whole,
+        "algorithmic_bytes": sb, "implementation_bytes": implementation_bytes(a.events, int(geo.map_tgt.shape[0])),
         "objects_per_event": {"md": per_ev[0], "ls": per_ev[1], "t3": per_ev[2], "t5": per_ev[3]},
         "max_candidates_per_stage": int(final[5]), "t5_pre_candidates": int(final[6]),
         "served": served, "extras": extras,

@@ -189,7 +189,9 @@ def lst_score(ctx, X_dev: int, x_dtype: int, n: int, scores_dev: int, precision:
            "lst_score")
 
 
-STAGE_WINDOWS = ("build", "bin", "md", "ls", "t3", "t5", "score")
+# eval-only windows of the MD, LS and T3 stages ("md", "ls", "t3") and the
+# whole stages ("md_all", "ls_all", "t3_all")
+STAGE_WINDOWS = ("build", "bin", "md", "ls", "t3", "t5", "score", "md_all", "ls_all", "t3_all")
 
 
 def lst_set_timing(ctx, enable: bool) -> None:

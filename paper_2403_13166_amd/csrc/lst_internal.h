@@ -104,8 +104,11 @@ struct RunArgs {
 };
 
 // Timing windows (pairs of events): 0 whole build, 1 binning, 2 MD, 3 LS,
-// 4 T3, 5 T5 compaction kernels, 6 T5 features + DNN scoring.
-constexpr int kTimingWindows = 7;
+// 4 T3 (2-4: the stage's eval kernel alone), 5 T5 compaction kernels, 6 T5
+// features + DNN scoring, then the whole MD, LS and T3 stages (7, 8, 9):
+// candidate-count scan, eval, tile-count scan, copy and CSR fill, for LS
+// also the per-entry prefix of the module map.
+constexpr int kTimingWindows = 10;
 constexpr int kTimingEvents = 2 * kTimingWindows;
 
 // Edge classifier: layers in model-blob order; all but the last are run on

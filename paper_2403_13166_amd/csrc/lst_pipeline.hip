@@ -1525,9 +1525,12 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
 
     // a2: mini-doublets, anchored on (event, module)
     MDStage md{w.bin_off, w.bin_hit, a.g.mod, a.p, n_mod, n_sens, o.md_hits, w.md_a, w.md_o, w.md_rq};
+    mark(ev, 14, st);
     run_stage(md, nullptr, ngm, w, cnt + LST_COUNT_MD, w.cap_md, cnt, st, ev, 2, a.tune);
     hipLaunchKernelGGL(k_fill_offsets<GmKey>, dim3(grid_for(w.cap_md + 1)), dim3(kBlock), 0, st, GmKey{w.md_a},
                        cnt + LST_COUNT_MD, w.cap_md, nullptr, ngm, w.md_mod_off);
+    mark(ev, 15, st);
+    mark(ev, 16, st);
     hipLaunchKernelGGL(k_ls_prefix, dim3(grid_for((ngm + kPrefRows - 1) / kPrefRows * kPrefSeg)), dim3(kBlock), 0, st, a.g.map_off, a.g.map_tgt, n_mod,
                        n_map, a.n_ev, w.md_mod_off, w.rsum, w.rpref);
 
@@ -1538,12 +1541,15 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     run_stage(ls, nullptr, ngm, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st, ev, 3, a.tune);
     hipLaunchKernelGGL(k_fill_offsets<LsInKey>, dim3(grid_for(w.cap_ls + 1)), dim3(kBlock), 0, st, LsInKey{o.ls_md},
                        cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w.ls_off);
+    mark(ev, 17, st);
 
     // a4: triplets, anchored on the inner LS
     T3Stage t3{o.ls_md, w.ls_off, w.md_a, w.md_o, w.md_rq, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
+    mark(ev, 18, st);
     run_stage(t3, cnt + LST_COUNT_LS, w.cap_ls, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st, ev, 4, a.tune);
     hipLaunchKernelGGL(k_fill_offsets<T3InKey>, dim3(grid_for(w.cap_t3 + 1)), dim3(kBlock), 0, st, T3InKey{w.t3_mds},
                        cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w.t3i_off);
+    mark(ev, 19, st);
 
     // a5: quintuplets, anchored on the inner T3: FP32 beam-line cuts, then the
     // FP64 fits on the dense list of pre-candidates

@@ -118,15 +118,20 @@ def score_errors(gpu_host, orc: O.Result):
     return dict(n_common=n, score=f(ds), chi2_rphi_rel=f(dr), chi2_rz_rel=f(dz))
 
 
-def feature_errors(gpu_host, orc: O.Result):
+def feature_errors(gpu_host, orc: O.Result, angle_cols=()):
+    """Per feature column: max |f_gpu - f_oracle| / max(1, |f_oracle|) over the
+    common T5s; columns in angle_cols are compared modulo 2 pi."""
     g = gpu_keys(gpu_host)[3]
     o = oracle_keys(orc)[3]
     oi = {k: i for i, k in enumerate(o)}
-    worst = np.zeros(42)
-    for i, k in enumerate(g):
-        j = oi.get(k)
-        if j is None:
-            continue
-        d = np.abs(gpu_host.t5_feat[i].astype(np.float64) - orc.feat[j]) / np.maximum(1.0, np.abs(orc.feat[j]))
-        worst = np.maximum(worst, d)
-    return worst
+    pairs = [(i, oi[k]) for i, k in enumerate(g) if k in oi]
+    if not pairs:
+        return np.zeros(42)
+    gi, oj = (np.array(v) for v in zip(*pairs))
+    a = gpu_host.t5_feat[gi].astype(np.float64)
+    b = orc.feat[oj]
+    d = a - b
+    ang = list(angle_cols)
+    if ang:
+        d[:, ang] = np.remainder(d[:, ang] + np.pi, 2 * np.pi) - np.pi
+    return np.max(np.abs(d) / np.maximum(1.0, np.abs(b)), axis=0)

@@ -22,6 +22,7 @@ import pytest
 from oracle import oracle as O
 from paper_2403_13166_amd.synth import geometry as G, events as E
 from tests import compare as CMP
+from tests.helix import threshold_event
 
 
 @dataclass
@@ -38,35 +39,6 @@ class KeyObjects:
 
     def t5_mds(self):
         return self.t5
-
-
-def threshold_event(geo, seed):
-    """Noise-free tracks at pT_min with z_v = +-Z (on the envelope), tracks
-    at high pT from the origin (far from every threshold), and noise hits on
-    the sensors those tracks cross (candidates far outside the cuts)."""
-    rng = np.random.default_rng(seed)
-    Z, pmin = geo.params["z_lum"], geo.params["pt_min"]
-    n1, n2 = 300, 60
-    eta1 = rng.uniform(-2.3, 2.3, n1)
-    t1 = np.stack([np.where(rng.random(n1) < 0.5, -1.0, 1.0), np.full(n1, pmin), eta1,
-                   rng.uniform(0, 2 * math.pi, n1), np.where(eta1 >= 0, Z, -Z)], axis=1)
-    t2 = np.stack([np.where(rng.random(n2) < 0.5, -1.0, 1.0), rng.uniform(5.0, 20.0, n2),
-                   rng.uniform(-2.3, 2.3, n2), rng.uniform(0, 2 * math.pi, n2), np.zeros(n2)], axis=1)
-    ev = E.make_event_from_tracks(geo, np.concatenate([t1, t2]), 0, 0.0, rng, shuffle=False)
-    # noise on the other sensor of modules with a track hit
-    mods = np.unique(ev.sensor // 2)
-    nm = rng.choice(mods, 400)
-    p = geo.p[nm]
-    phi = rng.uniform(p[:, 4], p[:, 5])
-    bar = geo.kind[nm] == 0
-    r = np.where(bar, p[:, 1], rng.uniform(p[:, 2], p[:, 3]))
-    zz = np.where(bar, rng.uniform(p[:, 2], p[:, 3]), p[:, 1])
-    x = np.concatenate([ev.x, (r * np.cos(phi)).astype(np.float32)])
-    y = np.concatenate([ev.y, (r * np.sin(phi)).astype(np.float32)])
-    z = np.concatenate([ev.z, zz.astype(np.float32)])
-    s = np.concatenate([ev.sensor, (2 * nm + 1).astype(np.int32)])
-    tr = np.concatenate([ev.truth, np.full(400, -1, np.int32)])
-    return E.Event(x, y, z, s, tr, ev.tracks)
 
 
 def _rel(cv):

@@ -120,3 +120,27 @@ def test_served_capacity_overflow_recovers(setup):
     for i in range(3):
         _check(ex.results[10 + i], ref[i], f"after overflow request {i}")
     ex.close()
+
+
+def test_served_equals_alone_at_serving_occupancy():
+    """The serving workload's occupancy (PU ~ U[50, 200]: 30 tracks and 500
+    noise hits per unit) on the benchmark's slot shapes, a single-event slot
+    and two 48-event slots of 4.8M hits: a burst fills a large batch while
+    later arrivals go to the other slots, overlapping on the device. Every
+    served event equals the event built alone."""
+    from paper_2403_13166_amd.serve import GpuExecutor, Request, make_pool, pinned_event, run_loop, slot_caps
+    geo, pool = make_pool(56, seed=5)
+    mdl = M.make_model()
+    ref = _alone(geo, mdl, pool, 1)
+    caps = [slot_caps(250_000, 1), slot_caps(4_800_000, 48), slot_caps(4_800_000, 48)]
+    ex = GpuExecutor(geo.to_blob(), mdl.to_blob(), 3, caps, precision=1, use_graph=True, keep_results=True)
+    pins = [pinned_event(e) for e in pool]
+    arr = [0.0] * 44 + [0.0005 * k for k in range(1, 13)]
+    reqs = [Request(i, a, pool[i].n, pins[i]) for i, a in enumerate(arr)]
+    done, st = run_loop(reqs, ex)
+    _say("serving occupancy", st, "hits", [e.n for e in pool[:8]], "...", "slots used", sorted({d.slot for d in done}))
+    assert st["events"] == len(reqs)
+    assert st["max_batch"] >= 30 and st["max_inflight"] >= 2
+    for i in range(len(reqs)):
+        _check(ex.results[i], ref[i], f"request {i}")
+    ex.close()
