@@ -138,6 +138,20 @@ lst_status lst_build_objects(lst_ctx *ctx, const lst_hits *hits, const lst_optio
                              const lst_caps *caps, lst_objects *out, void *workspace,
                              size_t ws_bytes, void *stream);
 
+/* lst_build_objects without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Scratch is a static array of
+ * LST_NOALLOC_SCRATCH_MIB MiB per GPU, allocated with the library's code
+ * object and held until the process ends; the call itself allocates nothing.
+ * Capacities whose workspace (lst_workspace_size) exceeds that size give
+ * LST_E_INVAL with the required size in lst_last_error. All calls on one GPU
+ * share its array: calls that overlap on one GPU (any contexts, any streams)
+ * race and must be ordered by the caller. Results, errors and LST_ASYNC are
+ * as for lst_build_objects. */
+#define LST_NOALLOC_SCRATCH_MIB 128
+lst_status lst_build_objects_noalloc(lst_ctx *ctx, const lst_hits *hits, const lst_options *opt,
+                                     const lst_caps *caps, lst_objects *out, void *stream);
+
 /* Same for a batch of n_events events whose hits are concatenated:
  * event e owns hits [event_offsets_dev[e], event_offsets_dev[e + 1]) (int64,
  * device, n_events + 1 entries, event_offsets_dev[0] = 0, last = hits->n).

@@ -27,12 +27,13 @@ LST_ASYNC = 1
 LST_DTYPE_F32 = 0
 LST_DTYPE_BF16 = 1
 LST_COUNTS_LEN = 8
+LST_NOALLOC_SCRATCH_MIB = 128   # static scratch of lst_build_objects_noalloc (include/lst.h)
 LST_COUNT_ERR = 4
 LST_COUNT_MAXCAND = 5
 N_FEATURES = 42
 
 EXPORTED = ("lst_create", "lst_destroy", "lst_load_geometry", "lst_load_model", "lst_workspace_size",
-            "lst_build_objects", "lst_build_objects_batched", "lst_score", "lst_status_string",
+            "lst_build_objects", "lst_build_objects_noalloc", "lst_build_objects_batched", "lst_score", "lst_status_string",
             "lst_last_error", "lst_set_timing", "lst_stage_times", "lst_get_tuning", "lst_set_tuning",
             "lst_load_gnn", "lst_gnn_workspace_size", "lst_gnn_score")
 
@@ -106,6 +107,9 @@ def lib():
         L.lst_build_objects.argtypes = [vp, C.POINTER(LstHits), C.POINTER(LstOptions), C.POINTER(LstCaps),
                                         C.POINTER(LstObjects), vp, C.c_size_t, vp]
         L.lst_build_objects.restype = i32
+        L.lst_build_objects_noalloc.argtypes = [vp, C.POINTER(LstHits), C.POINTER(LstOptions),
+                                                C.POINTER(LstCaps), C.POINTER(LstObjects), vp]
+        L.lst_build_objects_noalloc.restype = i32
         L.lst_build_objects_batched.argtypes = [vp, C.POINTER(LstHits), vp, i32, C.POINTER(LstOptions),
                                                 C.POINTER(LstCaps), C.POINTER(LstObjects), vp, vp,
                                                 C.c_size_t, vp]
@@ -170,6 +174,14 @@ def lst_build_objects(ctx, hits: LstHits, opts: LstOptions, caps: LstCaps, out: 
                                  ws_bytes, stream)
     if check:
         _check(ctx, st, "lst_build_objects")
+    return st
+
+
+def lst_build_objects_noalloc(ctx, hits: LstHits, opts: LstOptions, caps: LstCaps, out: LstObjects,
+                              stream: int, check: bool = True) -> int:
+    st = lib().lst_build_objects_noalloc(ctx, C.byref(hits), C.byref(opts), C.byref(caps), C.byref(out), stream)
+    if check:
+        _check(ctx, st, "lst_build_objects_noalloc")
     return st
 
 

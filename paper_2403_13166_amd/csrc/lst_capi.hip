@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -13,6 +14,30 @@
 #include "lst_internal.h"
 
 using namespace lst;
+
+// Device scratch of the allocation-free build (lst_build_objects_noalloc):
+// one copy per GPU, allocated with the library's code object and held until
+// the process ends. Host code never passes `scratch` itself to a kernel: its
+// device address on each GPU comes from hipGetSymbolAddress, taken once per
+// device when a context is created there.
+constexpr size_t kNoAllocScratchBytes = (size_t)LST_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device `device` (null on failure).
+static hipError_t scratch_address(int device, void **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 struct lst_ctx {
     int device = 0;
@@ -36,6 +61,8 @@ struct lst_ctx {
     bool gnn_loaded = false;
     void *d_gnn = nullptr;
     GnnDev gnn{};
+    // this device's address of the static scratch of lst_build_objects_noalloc
+    void *noalloc_ws = nullptr;
 };
 
 static lst_status fail(lst_ctx *c, lst_status s, const char *fmt, ...) {
@@ -77,9 +104,14 @@ lst_status lst_create(int device, lst_ctx **out) {
     *out = nullptr;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LST_E_INVAL;
+    if (device >= kMaxDevices) return LST_E_INVAL;
     if (hipSetDevice(device) != hipSuccess) return LST_E_HIP;
     lst_ctx *c = new lst_ctx();
     c->device = device;
+    if (scratch_address(device, &c->noalloc_ws) != hipSuccess) {
+        delete c;
+        return LST_E_HIP;
+    }
     *out = c;
     return LST_OK;
 }
@@ -374,6 +406,24 @@ lst_status lst_build_objects_batched(lst_ctx *c, const lst_hits *h, const int64_
                                      const lst_options *opt, const lst_caps *k, lst_objects *out,
                                      int64_t *ev_obj_off, void *ws, size_t ws_bytes, void *stream) {
     return build_common(c, h, ev_off, n_ev, opt, k, out, ev_obj_off, ws, ws_bytes, stream, false);
+}
+
+// lst_build_objects with the static per-device scratch as its workspace: the
+// same kernels, no allocation. Every stage initialises what it reads of the
+// workspace, so the previous call's contents do no harm.
+lst_status lst_build_objects_noalloc(lst_ctx *c, const lst_hits *h, const lst_options *opt, const lst_caps *k,
+                                     lst_objects *out, void *stream) {
+    if (!c) return LST_E_INVAL;
+    if (!c->geom_loaded) return fail(c, LST_E_STATE, "load geometry and model first");
+    lst_status s = check_caps(c, k);
+    if (s != LST_OK) return s;
+    const size_t need = layout(c, k, nullptr, nullptr);
+    if (need > kNoAllocScratchBytes)
+        return fail(c, LST_E_INVAL, "these capacities need %zu bytes of workspace; the allocation-free build "
+                    "has %zu (LST_NOALLOC_SCRATCH_MIB MiB): use lst_build_objects with a workspace",
+                    need, kNoAllocScratchBytes);
+    if (!c->noalloc_ws) return fail(c, LST_E_STATE, "no static scratch address on this device");
+    return build_common(c, h, nullptr, 1, opt, k, out, nullptr, c->noalloc_ws, kNoAllocScratchBytes, stream, true);
 }
 
 lst_status lst_set_timing(lst_ctx *c, int32_t enable) {
