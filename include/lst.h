@@ -35,7 +35,7 @@ extern "C" {
 
 typedef int32_t lst_status;
 #define LST_OK 0
-#define LST_E_INVAL (-1)     /* bad argument, bad blob, or sensor id out of range */
+#define LST_E_INVAL (-1)     /* bad argument, bad blob, sensor id out of range, or a hit off its sensor */
 #define LST_E_STATE (-2)     /* geometry / model not loaded */
 #define LST_E_CAPACITY (-3)  /* an output or candidate capacity was too small */
 #define LST_E_HIP (-4)       /* a HIP runtime call failed */
@@ -58,9 +58,11 @@ typedef int32_t lst_status;
 #define LST_COUNT_LS 1
 #define LST_COUNT_T3 2
 #define LST_COUNT_T5 3
-#define LST_COUNT_ERR 4      /* bit 0 bad sensor id, bit 1 candidate cap, bit 2 object cap */
+#define LST_COUNT_ERR 4      /* bit 0 bad sensor id, bit 1 candidate cap, bit 2 object cap,
+                                bit 3 an MD anchor hit off its sensor */
 #define LST_COUNT_MAXCAND 5  /* largest candidate count of any stage (required cand cap) */
 #define LST_COUNT_T5PRE 6    /* T3 pairs passing the quintuplet's FP32 cuts (bounded by cand cap) */
+#define LST_COUNT_LSCAND 7   /* MD pairs the line-segment stage evaluated (after its windows) */
 #define LST_COUNTS_LEN 8
 
 #define LST_N_FEATURES 42
@@ -132,8 +134,11 @@ lst_status lst_workspace_size(const lst_ctx *ctx, const lst_caps *caps, size_t *
 /* Build MD, LS, T3, T5 and T5 scores for ONE event (Table 1 steps 1-4 and the
  * Sec. 2 T5-DNN). Returns LST_E_CAPACITY (after a sync) when any count
  * exceeds its capacity: out->n_* / counts_dev then hold the required counts
- * and the output contents are unspecified. With LST_ASYNC nothing is checked
- * on the host; read counts_dev after the stream completes. */
+ * and the output contents are unspecified. Hits must lie on their sensor
+ * (within 2e-3 cm of its surface and extent and 2e-5 rad of its phi range):
+ * an MD whose anchor hit does not gives LST_E_INVAL (error bit 3). With
+ * LST_ASYNC nothing is checked on the host; read counts_dev after the stream
+ * completes. */
 lst_status lst_build_objects(lst_ctx *ctx, const lst_hits *hits, const lst_options *opt,
                              const lst_caps *caps, lst_objects *out, void *workspace,
                              size_t ws_bytes, void *stream);
@@ -220,8 +225,10 @@ lst_status lst_gnn_score(lst_ctx *ctx, const float *x_dev, int64_t n_nodes, cons
  *                block in LDS (1..64; raised at launch to the number of ranges
  *                of at most 1024 sensor ids that cover the geometry);
  *   tile_per[s]  candidates per thread of a 256-thread compaction tile, for
- *                stage s = 0 MD {2,4,8}, 1 LS {2,4,8}, 2 T3 {1,2,4},
- *                3 T5 FP32 pre-cuts {1,2,4}, 4 T5 FP64 fits {1,2};
+ *                stage s = 0 MD {2,4,8}, 2 T3 {1,2,4}, 3 T5 FP32 pre-cuts
+ *                {1,2,4}, 4 T5 FP64 fits {1,2}; entry 1 is accepted with
+ *                {2,4,8} and has no effect (the line-segment stage runs one
+ *                inner MD per lane, without compaction tiles);
  *   eval_blocks  blocks of the compaction kernels (256..8192).
  * Defaults: {4, {4, 8, 2, 2, 1}, 8192}. lst_set_tuning(ctx, NULL) restores
  * them; an unsupported value gives LST_E_INVAL and leaves the tuning as it

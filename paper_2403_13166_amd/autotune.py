@@ -3,9 +3,10 @@
 Knobs (all exposed through lst_set_tuning; none changes a result):
   * bin_split: sensor-id ranges per event in hit binning, each sorted by one
     block in LDS (the module-bin size);
-  * tile_per[s]: candidates per thread of each stage's 256-thread compaction
-    tile (the LDS tile: the tile's anchor window and, for line segments, its
-    module-map entries are staged in LDS);
+  * tile_per[s]: candidates per thread of each compaction stage's 256-thread
+    tile (the LDS tile holds the tile's anchor window); the line-segment stage
+    has no compaction tiles (one inner MD per lane), so tile_per[1] is not
+    searched;
   * eval_blocks: persistent blocks of the compaction kernels.
 
 Search: coordinate descent. Each knob is timed on the stage window it governs
@@ -26,7 +27,6 @@ EVAL_BLOCKS = (1024, 2048, 4096, 8192)
 KNOBS = (
     ("bin_split", None, BIN_SPLITS, "bin"),
     ("tile_per", 0, B.TILE_CHOICES[0], "md"),
-    ("tile_per", 1, B.TILE_CHOICES[1], "ls"),
     ("tile_per", 2, B.TILE_CHOICES[2], "t3"),
     ("tile_per", 3, B.TILE_CHOICES[3], "t5"),
     ("tile_per", 4, B.TILE_CHOICES[4], "t5"),

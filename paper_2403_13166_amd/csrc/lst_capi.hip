@@ -6,6 +6,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <array>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -48,6 +51,11 @@ struct lst_ctx {
     CutParams cp{};
     ModConst *d_mod = nullptr;
     int32_t *d_map_off = nullptr, *d_map_tgt = nullptr;
+    ModBox *d_box = nullptr;
+    int32_t *d_run_off = nullptr;
+    RunRec *d_runs = nullptr;
+    RowConst *d_rows = nullptr;
+    int32_t n_runs = 0, n_rows = 0;
     // model
     bool model_loaded = false;
     float *d_model = nullptr;
@@ -120,7 +128,12 @@ static void free_geom(lst_ctx *c) {
     if (c->d_mod) (void)hipFree(c->d_mod);
     if (c->d_map_off) (void)hipFree(c->d_map_off);
     if (c->d_map_tgt) (void)hipFree(c->d_map_tgt);
+    if (c->d_box) (void)hipFree(c->d_box);
+    if (c->d_run_off) (void)hipFree(c->d_run_off);
+    if (c->d_runs) (void)hipFree(c->d_runs);
+    if (c->d_rows) (void)hipFree(c->d_rows);
     c->d_mod = nullptr; c->d_map_off = c->d_map_tgt = nullptr;
+    c->d_box = nullptr; c->d_run_off = nullptr; c->d_runs = nullptr; c->d_rows = nullptr;
     c->geom_loaded = false;
 }
 
@@ -147,6 +160,120 @@ static double arc_len(double c, double r) {
     if (x < 1e-4) return r * (1.0 + x * x / 6.0);
     if (x >= 1.0) x = 1.0;
     return asin(x) / c;
+}
+
+// Tolerances of the on-sensor check of MD anchor hits, which every window of
+// the line-segment stage builds on (FP32 rounding of hit coordinates is a few
+// 1e-6 cm and 1e-7 rad).
+constexpr double kTolPos = 2e-3;   // cm
+constexpr double kTolPhi = 2e-5;   // rad
+constexpr double kTwoPi = 6.283185307179586;
+constexpr double kPi = 3.141592653589793;
+// Largest phi separation at which the line-segment stage trims a run: a pair
+// whose curvature passes the curvature cut lies either within the window
+// asin(c r_B) - asin(c r_A) of the near side of its circle, or beyond
+// pi - 2 asin(0.85) = 1.1096 rad on the far side (the device trims only while
+// c r_B < 0.85); runs that reach 1.10 rad from their source module are
+// therefore never trimmed in phi.
+constexpr double kFarSidePhi = 1.10;
+
+struct HostMod {
+    int32_t kind, layer, side, nphi;
+    double p[6];
+};
+
+// circular |u| in [0, pi]
+static double circ_abs(double u) {
+    double d = fmod(fabs(u), kTwoPi);
+    return d > kPi ? kTwoPi - d : d;
+}
+
+// Largest angular distance between a point of [a0, a1] and a point of
+// [b0, b1]: the differences x - y fill [a0 - b1, a1 - b0]; if that interval
+// holds pi (mod 2 pi) the answer is pi, otherwise the distance peaks at an end.
+static double max_phi_sep(double a0, double a1, double b0, double b1) {
+    const double lo = a0 - b1, hi = a1 - b0;
+    if (hi - lo >= kTwoPi) return kPi;
+    const double k = ceil((lo - kPi) / kTwoPi);
+    if (kPi + k * kTwoPi <= hi) return kPi;
+    return std::max(circ_abs(lo), circ_abs(hi));
+}
+
+static ModBox module_box(const HostMod &m) {
+    ModBox b{};
+    if (m.kind == 0) {
+        b.r_lo = (float)(m.p[0] - kTolPos); b.r_hi = (float)(m.p[0] + kTolPos);
+        b.z_lo = (float)(m.p[2] - kTolPos); b.z_hi = (float)(m.p[3] + kTolPos);
+    } else {
+        b.r_lo = (float)(m.p[2] - kTolPos); b.r_hi = (float)(m.p[3] + kTolPos);
+        b.z_lo = (float)(m.p[0] - kTolPos); b.z_hi = (float)(m.p[0] + kTolPos);
+    }
+    b.phi_lo = (float)(m.p[4] - kTolPhi); b.phi_hi = (float)(m.p[5] + kTolPhi);
+    return b;
+}
+
+// Runs of every module's map row (sorted, duplicates removed): maximal
+// sequences of consecutive target ids that lie in one detector row and are
+// adjacent in phi. Rows are keyed by module type, layer, side, phi count,
+// anchor surface and extent.
+static void build_runs(const std::vector<HostMod> &mods, const std::vector<int32_t> &moff,
+                       const std::vector<int32_t> &mtgt, double cmax, double srphi, double sr,
+                       std::vector<int32_t> &run_off, std::vector<RunRec> &runs, std::vector<RowConst> &rows) {
+    const size_t nm = mods.size();
+    std::map<std::array<double, 7>, int32_t> row_of_key;
+    std::vector<int32_t> row_id(nm);
+    for (size_t m = 0; m < nm; ++m) {
+        const HostMod &h = mods[m];
+        const std::array<double, 7> key{(double)h.kind, (double)h.layer, (double)h.side, (double)h.nphi,
+                                        h.p[0], h.p[2], h.p[3]};
+        auto it = row_of_key.find(key);
+        if (it == row_of_key.end()) {
+            const ModBox b = module_box(h);
+            RowConst rc{};
+            rc.r_lo = b.r_lo; rc.r_hi = b.r_hi; rc.z_lo = b.z_lo; rc.z_hi = b.z_hi;
+            const double w = h.p[5] - h.p[4];
+            rc.dphi = (float)w;
+            rc.inv_dphi = (float)(1.0 / w);
+            const double rl = h.kind == 0 ? h.p[0] - kTolPos : h.p[2] - kTolPos;
+            double q = srphi * srphi / (rl * rl);
+            if (h.kind != 0) q += cmax * cmax * sr * sr;
+            rc.qb_max = (float)(q * (1.0 + 1e-6));
+            rc.kind = h.kind;
+            it = row_of_key.emplace(key, (int32_t)rows.size()).first;
+            rows.push_back(rc);
+        }
+        row_id[m] = it->second;
+    }
+    run_off.assign(nm + 1, 0);
+    std::vector<int32_t> row;
+    for (size_t m = 0; m < nm; ++m) {
+        row.assign(mtgt.begin() + moff[m], mtgt.begin() + moff[m + 1]);
+        std::sort(row.begin(), row.end());
+        row.erase(std::unique(row.begin(), row.end()), row.end());
+        const HostMod &src = mods[m];
+        size_t i = 0;
+        while (i < row.size()) {
+            size_t k = i + 1;
+            while (k < row.size()) {
+                const HostMod &a = mods[row[k - 1]], &b = mods[row[k]];
+                const bool adj = row[k] == row[k - 1] + 1 && row_id[row[k]] == row_id[row[k - 1]] &&
+                                 fabs(b.p[4] - a.p[5]) < 1e-9 && fabs((b.p[5] - b.p[4]) - (a.p[5] - a.p[4])) < 1e-9;
+                if (!adj) break;
+                ++k;
+            }
+            RunRec rr{};
+            rr.t_first = row[i];
+            rr.n = (int32_t)(k - i);
+            rr.row = row_id[row[i]];
+            rr.phi_start = (float)mods[row[i]].p[4];
+            const double sep = max_phi_sep(src.p[4] - kTolPhi, src.p[5] + kTolPhi,
+                                           mods[row[i]].p[4] - kTolPhi, mods[row[k - 1]].p[5] + kTolPhi);
+            if (sep >= kFarSidePhi) rr.row |= kRunNoTrim;
+            runs.push_back(rr);
+            i = k;
+        }
+        run_off[m + 1] = (int32_t)runs.size();
+    }
 }
 
 lst_status lst_load_geometry(lst_ctx *c, const void *blob, size_t nbytes) {
@@ -177,6 +304,8 @@ lst_status lst_load_geometry(lst_ctx *c, const void *blob, size_t nbytes) {
         return fail(c, LST_E_INVAL, "geometry blob: resolutions must be positive");
     p.isrphi_d = 1.0 / srphi; p.isr_d = 1.0 / prm[6]; p.isz_d = 1.0 / prm[5];
     std::vector<ModConst> mods(nm);
+    std::vector<HostMod> hmods(nm);
+    std::vector<ModBox> boxes(nm);
     const unsigned char *r = b + 152;
     for (uint32_t m = 0; m < nm; ++m, r += 64) {
         int32_t kind, layer;
@@ -184,6 +313,14 @@ lst_status lst_load_geometry(lst_ctx *c, const void *blob, size_t nbytes) {
         memcpy(&kind, r, 4);
         memcpy(&layer, r + 4, 4);
         memcpy(pp, r + 16, 48);
+        HostMod &hm = hmods[m];
+        hm.kind = kind; hm.layer = layer;
+        memcpy(&hm.side, r + 8, 4);
+        memcpy(&hm.nphi, r + 12, 4);
+        memcpy(hm.p, pp, sizeof(pp));
+        if (!(pp[4] >= 0.0 && pp[5] > pp[4] && pp[5] <= kTwoPi + 1e-9))
+            return fail(c, LST_E_INVAL, "geometry blob: module %u phi range outside [0, 2 pi]", m);
+        boxes[m] = module_box(hm);
         ModConst mc{};
         mc.kind = kind; mc.layer = layer;
         mc.gap = (float)fabs(pp[1] - pp[0]);
@@ -211,17 +348,32 @@ lst_status lst_load_geometry(lst_ctx *c, const void *blob, size_t nbytes) {
     if ((uint32_t)moff[nm] != nmap) return fail(c, LST_E_INVAL, "module map offsets inconsistent");
     for (uint32_t i = 0; i < nm; ++i)
         if (moff[i + 1] < moff[i]) return fail(c, LST_E_INVAL, "module map offsets not monotone");
+    std::vector<int32_t> run_off;
+    std::vector<RunRec> runs;
+    std::vector<RowConst> rows;
+    build_runs(hmods, moff, mtgt, cmax, srphi, prm[6], run_off, runs, rows);
+    if (runs.empty()) runs.push_back(RunRec{});
     HIP_TRY(c, hipSetDevice(c->device));
     free_geom(c);
     if (hipMalloc(&c->d_mod, sizeof(ModConst) * nm) != hipSuccess ||
         hipMalloc(&c->d_map_off, sizeof(int32_t) * (nm + 1)) != hipSuccess ||
-        hipMalloc(&c->d_map_tgt, sizeof(int32_t) * mtgt.size()) != hipSuccess) {
+        hipMalloc(&c->d_map_tgt, sizeof(int32_t) * mtgt.size()) != hipSuccess ||
+        hipMalloc(&c->d_box, sizeof(ModBox) * nm) != hipSuccess ||
+        hipMalloc(&c->d_run_off, sizeof(int32_t) * (nm + 1)) != hipSuccess ||
+        hipMalloc(&c->d_runs, sizeof(RunRec) * runs.size()) != hipSuccess ||
+        hipMalloc(&c->d_rows, sizeof(RowConst) * rows.size()) != hipSuccess) {
         free_geom(c);
         return fail(c, LST_E_NOMEM, "geometry tables");
     }
     HIP_TRY(c, hipMemcpy(c->d_mod, mods.data(), sizeof(ModConst) * nm, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->d_map_off, moff.data(), sizeof(int32_t) * (nm + 1), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->d_map_tgt, mtgt.data(), sizeof(int32_t) * mtgt.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_box, boxes.data(), sizeof(ModBox) * nm, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_run_off, run_off.data(), sizeof(int32_t) * (nm + 1), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_runs, runs.data(), sizeof(RunRec) * runs.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_rows, rows.data(), sizeof(RowConst) * rows.size(), hipMemcpyHostToDevice));
+    c->n_runs = (int32_t)run_off[nm];
+    c->n_rows = (int32_t)rows.size();
     c->n_mod = (int32_t)nm; c->n_barrel = (int32_t)nb; c->n_map = (int32_t)nmap;
     c->cp = p;
     c->geom_loaded = true;
@@ -305,9 +457,11 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     x.md_o = (float2 *)take(8 * md);
     x.md_rq = (float2 *)take(8 * md);
     x.md_mod_off = (int64_t *)take(8 * (ev * nmod + 1));
-    x.rsum = (int32_t *)take(4 * ev * nmod);
-    x.rpref = (int32_t *)take(4 * ev * (c->n_map > 0 ? c->n_map : 1));
     x.ls_off = (int64_t *)take(8 * (md + 1));
+    x.ls_cnt = (int32_t *)take(4 * md);
+    x.ls_chunk = (int2 *)take(8 * (k->ls > 0 ? k->ls : 1));
+    x.ls_wave = (int64_t *)take(8 * (md / 64 + 2));
+    x.ls_top = (unsigned long long *)take(8);
     x.t3_mds = (int4 *)take(16 * (k->t3 > 0 ? k->t3 : 1));
     x.t3i_off = (int64_t *)take(8 * (md + 1));
     x.cap_t5pre = k->cand;
@@ -369,6 +523,7 @@ static lst_status build_common(lst_ctx *c, const lst_hits *h, const int64_t *ev_
     }
     RunArgs a{};
     a.g.mod = c->d_mod; a.g.map_off = c->d_map_off; a.g.map_tgt = c->d_map_tgt;
+    a.g.box = c->d_box; a.g.run_off = c->d_run_off; a.g.runs = c->d_runs; a.g.rows = c->d_rows;
     a.g.n_mod = c->n_mod; a.g.n_sens = 2 * c->n_mod; a.g.n_map = c->n_map;
     a.p = c->cp; a.m = c->md;
     a.x = h->x; a.y = h->y; a.z = h->z; a.sensor = h->sensor; a.n_hits = h->n;
@@ -388,6 +543,7 @@ static lst_status build_common(lst_ctx *c, const lst_hits *h, const int64_t *ev_
     HIP_TRY(c, hipStreamSynchronize(st));
     out->n_md = cnt[0]; out->n_ls = cnt[1]; out->n_t3 = cnt[2]; out->n_t5 = cnt[3];
     if (cnt[LST_COUNT_ERR] & 1) return fail(c, LST_E_INVAL, "sensor id out of range in the hits");
+    if (cnt[LST_COUNT_ERR] & 8) return fail(c, LST_E_INVAL, "a mini-doublet's anchor hit lies off its sensor");
     if ((cnt[LST_COUNT_ERR] & 2) || cnt[0] > k->md || cnt[1] > k->ls || cnt[2] > k->t3 || cnt[3] > k->t5 ||
         cnt[LST_COUNT_T5PRE] > k->cand)
         return fail(c, LST_E_CAPACITY, "capacity exceeded: md %lld/%lld ls %lld/%lld t3 %lld/%lld t5 %lld/%lld cand %lld/%lld",

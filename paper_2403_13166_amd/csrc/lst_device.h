@@ -42,11 +42,43 @@ struct ModelDev {
     float b3;
 };
 
+// Where a module's anchor hits lie (nominal sensor extent widened by a small
+// tolerance): transverse radius, z and azimuth ranges (phi in [0, 2 pi)).
+// Hits off their sensor are rejected as invalid input, so these boxes bound
+// every MD anchor of the module.
+struct ModBox {
+    float r_lo, r_hi, z_lo, z_hi, phi_lo, phi_hi, pad0, pad1;
+};
+
+// A row of the detector: modules of one layer (barrel z tile or endcap
+// ring) side by side in phi, all of one phi width.
+struct RowConst {
+    float r_lo, r_hi, z_lo, z_hi;   // anchor extent of the row's modules (ModBox)
+    float dphi, inv_dphi;           // phi width of a module and its inverse
+    float qb_max;                   // largest per-MD resolution term q of an anchor in the row
+    int32_t kind;                   // 0 barrel, 1 endcap
+};
+
+// A run of a module's map row: n consecutive target modules t_first ..
+// t_first + n - 1 of one detector row, adjacent in phi from phi_start.
+// row: index into the row table; bit 30: no phi trimming (the run reaches
+// phi separations where a circle through the beam line could pass the
+// curvature cut on its far side).
+struct RunRec {
+    int32_t t_first, n, row;
+    float phi_start;
+};
+constexpr int32_t kRunNoTrim = 1 << 30;
+
 // Batch-wide geometry handles.
 struct GeomDev {
     const ModConst *mod;
     const int32_t *map_off;   // [n_mod + 1]
     const int32_t *map_tgt;   // [n_map]
+    const ModBox *box;        // [n_mod]
+    const int32_t *run_off;   // [n_mod + 1] runs of each module's map row
+    const RunRec *runs;       // [n_runs]
+    const RowConst *rows;     // [n_rows]
     int32_t n_mod, n_sens, n_map;
 };
 

@@ -67,10 +67,12 @@ struct Work {
     float2 *md_o;                     // [cap_md] other hit x, y
     float2 *md_rq;                    // [cap_md] radius and resolution term (sign: endcap) for the pair cuts
     int64_t *md_mod_off;              // [cap_ev * n_mod + 1]
-    int32_t *rsum;                    // [cap_ev * n_mod] MDs in the mapped modules
-    int32_t *rpref;                   // [cap_ev * n_map] exclusive prefix over map entries
     // LS
-    int64_t *ls_off;                  // [cap_md + 1] CSR by inner MD
+    int64_t *ls_off;                  // [cap_md + 1] CSR by inner MD (exclusive scan of ls_cnt)
+    int32_t *ls_cnt;                  // [cap_md] LS per inner MD
+    int2 *ls_chunk;                   // [cap_ls] (A, B) of each wavefront's segments before placement
+    int64_t *ls_wave;                 // [cap_md / 64 + 1] chunk start of each wavefront (-1: recompute)
+    unsigned long long *ls_top;       // [1] chunk allocator
     // T3
     int4 *t3_mds;                     // [cap_t3] MDs (A, B, C)
     int64_t *t3i_off;                 // [cap_md + 1] T3 by inner MD (they are sorted by it)

@@ -872,6 +872,8 @@ struct MDStage {
     const int64_t *bin_off;
     const float4 *bin_hit;
     const ModConst *mod;
+    const ModBox *box;
+    int64_t *counts;
     CutParams p;
     int32_t n_mod, n_sens;
     int2 *md_hits;
@@ -913,10 +915,20 @@ struct MDStage {
         return ok;
     }
     __device__ void write(int64_t pos, const Rec &r) const {
+        const int m = __float_as_int(r.a.w) % n_mod;
         md_hits[pos] = make_int2(r.hl, r.hu);
         md_a[pos] = r.a;
         md_o[pos] = r.o;
-        md_rq[pos] = make_md_rq(p, r.a.x, r.a.y, mod[__float_as_int(r.a.w) % n_mod].kind != 0);
+        const float2 rq = make_md_rq(p, r.a.x, r.a.y, mod[m].kind != 0);
+        md_rq[pos] = rq;
+        // the anchor must lie on its sensor: the line-segment windows rely on it
+        const ModBox bx = box[m];
+        float ph = atan2f(r.a.y, r.a.x);
+        if (ph < 0.0f) ph += 6.2831853f;
+        const bool phi_ok = (ph >= bx.phi_lo && ph <= bx.phi_hi) || ph + 6.2831853f <= bx.phi_hi ||
+                            ph - 6.2831853f >= bx.phi_lo;
+        const bool on = rq.x >= bx.r_lo && rq.x <= bx.r_hi && r.a.z >= bx.z_lo && r.a.z <= bx.z_hi && phi_ok;
+        if (!on) atomicOr((unsigned long long *)&counts[LST_COUNT_ERR], 8ull);
     }
 };
 
@@ -958,201 +970,481 @@ __global__ __launch_bounds__(kBlock) void k_fill_offsets(KF key, const int64_t *
     }
 }
 
-// Per (event, module): rsum = MDs in the module's mapped modules, and for each
-// map entry the exclusive prefix of those counts along the module's row. A
-// 16-lane segment takes a row 16 entries at a time with a segmented scan, so
-// the row's reads and writes are coalesced; it works on kPrefRows rows at
-// once, whose dependent loads (row bounds, entry, MD offsets) overlap.
-constexpr int kPrefSeg = 16;
-constexpr int kPrefRows = 2;   // rows a segment works on at once, for independent loads in flight
-
-__global__ __launch_bounds__(kBlock) void k_ls_prefix(const int32_t *map_off, const int32_t *map_tgt,
-                                                      int32_t n_mod, int32_t n_map, int32_t n_ev,
-                                                      const int64_t *md_mod_off, int32_t *rsum, int32_t *rpref) {
-    const int64_t N = (int64_t)n_ev * n_mod;
-    const int sl = threadIdx.x & (kPrefSeg - 1);
-    const int64_t nseg = grid_stride() / kPrefSeg;
-    const bool small = N <= (int64_t)UINT32_MAX;   // 32-bit division suffices
-    for (int64_t g0 = grid_tid() / kPrefSeg; g0 < N; g0 += kPrefRows * nseg) {
-        int64_t ev[kPrefRows];
-        int32_t k0[kPrefRows], k1[kPrefRows], acc[kPrefRows];
-        int32_t len = 0;
-#pragma unroll
-        for (int j = 0; j < kPrefRows; ++j) {
-            const int64_t gm = g0 + j * nseg;
-            const bool ok = gm < N;
-            const int64_t gc = ok ? gm : 0;
-            ev[j] = small ? (int64_t)((uint32_t)gc / (uint32_t)n_mod) : gc / n_mod;
-            const int64_t m = gc - ev[j] * n_mod;
-            k0[j] = map_off[m];
-            k1[j] = map_off[m + 1];
-            if (!ok) k1[j] = k0[j];
-            acc[j] = 0;
-            len = k1[j] - k0[j] > len ? k1[j] - k0[j] : len;
-        }
-        for (int32_t kb = 0; kb < len; kb += kPrefSeg) {
-            // every row's loads first, from clamped indices (entry 0 when
-            // the row has ended: len > 0 means some row has an entry)
-            int32_t c[kPrefRows];
-#pragma unroll
-            for (int j = 0; j < kPrefRows; ++j) {
-                const int32_t k = k0[j] + kb + sl;
-                const int64_t t = ev[j] * n_mod + map_tgt[k < k1[j] ? k : 0];
-                c[j] = (int32_t)(md_mod_off[t + 1] - md_mod_off[t]);
-            }
-#pragma unroll
-            for (int j = 0; j < kPrefRows; ++j) {
-                const int32_t k = k0[j] + kb + sl;
-                const int32_t cj = k < k1[j] ? c[j] : 0;
-                int32_t v = cj;
-#pragma unroll
-                for (int d = 1; d < kPrefSeg; d <<= 1) {
-                    const int32_t o = __shfl_up(v, d, kPrefSeg);
-                    if (sl >= d) v += o;
-                }
-                if (k < k1[j]) rpref[ev[j] * n_map + k] = acc[j] + v - cj;
-                acc[j] += __shfl(v, kPrefSeg - 1, kPrefSeg);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < kPrefRows; ++j)
-            if (sl == 0 && g0 + j * nseg < N) rsum[g0 + j * nseg] = acc[j];
-    }
-}
-
 // ------------------------------------------------------------ LS stage
-// Anchor: (event, module). Left = the module's MDs, right = the MDs of every
-// module in its map entry list, concatenated in map order. info = {first left
-// MD, n right, LDS base of the map-entry table (-1: not staged), n entries}.
+// Line segments (Table 1 step 2): pairs of MDs (A, B) with B on a module of
+// A's module-map row (LS0), passing the curvature (LS1), z0 (LS2) and, for
+// barrel MDs, direction (LS3) cuts.
+//
+// One lane per inner MD A: a wavefront takes 64 consecutive MDs (sorted by
+// event and module) and each lane walks its own candidates B, in ascending B,
+// so no candidate is ever decoded from a flat index. A's map row is stored as
+// runs (consecutive target modules of one detector row, adjacent in phi), and
+// every run is first trimmed for this A to the modules the cuts can accept:
+//  * s ordering: LS2 needs s_B > s_A, i.e. r_B > r_A, so a run whose rows lie
+//    below r_A is skipped;
+//  * curvature: LS1 accepts c = |A x B| / (r_A r_B |B - A|) <= c_lim, and on a
+//    circle through the beam line with half-curvature c the points at radii
+//    r_A < r_B are asin(c r_B) - asin(c r_A) apart in phi; with |B - A| >=
+//    r_B,min - r_A and the largest resolution term of the row, this bounds
+//    |phi_B - phi_A| and keeps only the run's modules inside that window;
+//  * z0, barrel to barrel: z_B = z_A + (z_A - z0) rho with
+//    rho = s_B / s_A - 1 between its values at c = 0 and c_max and
+//    |z0| <= z_lum + n_sigma sigma_z0, which bounds z_B; runs outside are
+//    skipped, and each candidate is tested against the same window.
+// Every bound is widened well beyond FP32 rounding, and anchors are known to
+// lie on their sensors (checked when MDs are written), so trimming never
+// removes a pair that the cuts would accept.
+//
+// Candidates that pass LS1 are queued in LDS; LS2 runs on dense batches of
+// 64 queue entries, and its survivors are queued again for LS3. A survivor
+// gets its rank among the survivors of its A (queues keep each A's candidate
+// order). At the end the wavefront knows its per-A counts, claims a chunk of
+// a scratch array with one atomic add, and writes its segments there in
+// (A, B) order. A scan of the per-A counts gives the CSR offsets of LS by
+// inner MD, and a placement kernel copies every wavefront's chunk to its
+// final position. A wavefront whose survivors do not fit its LDS list is
+// recomputed by the placement kernel, one A per lane, writing directly.
 
-struct LSStage {
+constexpr int kLsWaves = kBlock / 64;
+constexpr int kLsRunsPerRound = 6;      // trimmed runs staged per lane at a time
+constexpr int kLsQCap = 128;            // LS1 / LS2 queue entries per wavefront
+constexpr int kLsOutCap = 256;          // survivors kept per wavefront in LDS
+constexpr int kLsBlocks = 1024;         // persistent blocks of the eval and placement kernels
+// queue entry tag: bits 0-5 owner lane, 6 bends positive, 7 / 8 direction cut
+// on A / on B (barrel MDs)
+constexpr int kTagPos = 64, kTagDirA = 128, kTagDirB = 256;
+
+struct LsLds {
+    int2 rng[kLsWaves][kLsRunsPerRound][64];   // trimmed MD ranges [j, je) of each lane
+    int q1b[kLsWaves][kLsQCap];
+    float q1c[kLsWaves][kLsQCap];
+    int q1t[kLsWaves][kLsQCap];
+    int q2b[kLsWaves][kLsQCap];
+    float q2c[kLsWaves][kLsQCap];
+    int q2t[kLsWaves][kLsQCap];
+    int ob[kLsWaves][kLsOutCap];               // survivors: B
+    int ot[kLsWaves][kLsOutCap];               // owner lane | rank among the owner's survivors << 6
+    int cnt[kLsWaves][64];                     // survivors per owner lane
+};
+
+struct LsArgs {
     const float4 *md_a;
     const float2 *md_o;
     const float2 *md_rq;
     const int64_t *md_mod_off;
-    const int32_t *rsum, *rpref;
-    const int32_t *map_off, *map_tgt;
-    const ModConst *mod;
+    GeomDev g;
     CutParams p;
-    int32_t n_mod, n_map;
-    int2 *ls_md;
-    static constexpr int kEnt = 1024;
-    static constexpr int kStage = 1;
-    static constexpr int kWin = 256;             // anchors staged per tile
-    static constexpr bool kUnitCount = false;
-    static constexpr int kMinBlocks = 5;       // resident blocks per CU the register budget must allow
-    static constexpr int kPhases = 2;            // cut phases (later ones on queued survivors)
-    struct Rec { int a, b; };
-    struct Mid { int a, b; float cp; int bits; };   // bits: 1 bends positive, 2/4 direction cut on A/B
-
-    __device__ int64_t count(int64_t gm) const {
-        return (md_mod_off[gm + 1] - md_mod_off[gm]) * (int64_t)rsum[gm];
-    }
-    // f[3]: map entries of the module (low 16 bits), bit 16: the module is an endcap module
-    __device__ void info(int64_t gm, int32_t *f) const {
-        int64_t e = gm / n_mod, m = gm - e * n_mod;
-        f[0] = (int32_t)md_mod_off[gm];
-        f[1] = rsum[gm];
-        f[2] = -1;
-        f[3] = (map_off[m + 1] - map_off[m]) | (mod[m].kind != 0 ? (1 << 16) : 0);
-    }
-    // stage the map-entry tables of the window's non-empty modules: one entry
-    // per thread, so the dependent loads of all entries overlap
-    template <class LDS>
-    __device__ void prepare(LDS &L, int64_t alo, int nw) const {
-        // thread t owns window anchors 2t and 2t+1 (nw <= 2 * kBlock)
-        const int i0 = 2 * threadIdx.x, i1 = i0 + 1;
-        const int d0 = (i0 < nw && L.off[i0 + 1] > L.off[i0]) ? (L.info[i0][3] & 0xffff) : 0;
-        const int d1 = (i1 < nw && L.off[i1 + 1] > L.off[i1]) ? (L.info[i1][3] & 0xffff) : 0;
-        int64_t tot;
-        const int64_t inc = block_incl_scan((int64_t)(d0 + d1), &tot);
-        const int base0 = (int)(inc - d0 - d1), base1 = base0 + d0;
-        const bool fits = tot <= kEnt;
-        if (fits) {
-            if (i0 < nw) { L.ebase[i0] = base0; L.ek0[i0] = d0 ? map_off[(alo + i0) % n_mod] : 0; }
-            if (i1 < nw) { L.ebase[i1] = base1; L.ek0[i1] = d1 ? map_off[(alo + i1) % n_mod] : 0; }
-            if (d0) L.info[i0][2] = base0;
-            if (d1) L.info[i1][2] = base1;
-        }
-        __syncthreads();
-        if (fits) {
-            for (int q = threadIdx.x; q < (int)tot; q += kBlock) {
-                int lo = 0, hi = nw;      // window anchor owning entry q
-                while (hi - lo > 1) {
-                    int mid = (lo + hi) >> 1;
-                    if (L.ebase[mid] <= q) lo = mid; else hi = mid;
-                }
-                const int64_t gm = alo + lo;
-                const int64_t e = gm / n_mod;
-                const int32_t k = L.ek0[lo] + (q - L.ebase[lo]);
-                const int32_t tg = map_tgt[k];
-                L.ent_rp[q] = rpref[e * n_map + k];
-                L.ent_md[q] = (int32_t)md_mod_off[e * n_mod + tg] | (mod[tg].kind != 0 ? INT32_MIN : 0);
-            }
-        }
-        __syncthreads();
-    }
-    template <class LDS>
-    // phase 1: decode the candidate and apply the pair cuts
-    __device__ bool eval(int64_t gm, int32_t local, const int32_t *f, const LDS &L, Rec &r, Mid &q) const {
-        const int nR = f[1];
-        // local = l * nR + rr: quotient from the FP32 reciprocal, then made exact
-        int l = (int)((float)local * __builtin_amdgcn_rcpf((float)nR));
-        int rr = local - l * nR;
-        while (rr < 0) { --l; rr += nR; }
-        while (rr >= nR) { ++l; rr -= nR; }
-        const int64_t a = f[0] + l;
-        const bool eA = (f[3] >> 16) & 1;
-        int64_t b;
-        bool eB;
-        if (f[2] >= 0) {
-            int lo = f[2], hi = f[2] + (f[3] & 0xffff);   // largest entry with ent_rp <= rr
-            while (hi - lo > 1) {
-                int mid = (lo + hi) >> 1;
-                if (L.ent_rp[mid] <= rr) lo = mid; else hi = mid;
-            }
-            const int32_t em = L.ent_md[lo];
-            b = (em & INT32_MAX) + (rr - L.ent_rp[lo]);
-            eB = em < 0;
-        } else {
-            const int64_t e = gm / n_mod, m = gm - e * n_mod;
-            const int32_t *rp = rpref + e * n_map;
-            int lo = map_off[m], hi = map_off[m + 1];
-            while (hi - lo > 1) {
-                int mid = (lo + hi) >> 1;
-                if (rp[mid] <= rr) lo = mid; else hi = mid;
-            }
-            const int mb = map_tgt[lo];
-            b = md_mod_off[e * n_mod + mb] + (rr - rp[lo]);
-            eB = mod[mb].kind != 0;
-        }
-        const float4 A = md_a[a], B = md_a[b];
-        const float2 qa = md_rq[a], qb = md_rq[b];
-        r.a = (int)a; r.b = (int)b;
-        float c, sg;
-        if (!pair_pass_rq(p, P3{A.x, A.y, A.z}, qa, P3{B.x, B.y, B.z}, qb, c, sg)) return false;
-        q.a = (int)a; q.b = (int)b;
-        q.cp = fminf(c, p.cmax);
-        q.bits = (sg > 0.0f ? 1 : 0) | (eA ? 0 : 2) | (eB ? 0 : 4);
-        return true;
-    }
-    // phase 2: the MD direction cut of the barrel MDs
-    __device__ bool eval2(const Mid &q) const {
-        const float sg = (q.bits & 1) ? 1.0f : -1.0f;
-        if (q.bits & 2) {
-            const float4 A = md_a[q.a];
-            const float2 o = md_o[q.a];
-            if (!md_dir_pass(p, P3{A.x, A.y, A.z}, o.x, o.y, q.cp, sg)) return false;
-        }
-        if (q.bits & 4) {
-            const float4 B = md_a[q.b];
-            const float2 o = md_o[q.b];
-            if (!md_dir_pass(p, P3{B.x, B.y, B.z}, o.x, o.y, q.cp, sg)) return false;
-        }
-        return true;
-    }
-    __device__ void write(int64_t pos, const Rec &r) const { ls_md[pos] = make_int2(r.a, r.b); }
+    int32_t *ls_cnt;                 // [cap_md] LS per inner MD
+    int2 *chunk;                     // [cap_chunk] (A, B) of every wavefront's segments
+    int64_t cap_chunk;
+    int64_t *wave_base;              // [cap_md / 64 + 1] chunk start of each wavefront, -1: recompute
+    unsigned long long *top;         // chunk allocator (zeroed before the eval kernel)
+    int64_t *counts;
+    int64_t cap_md;
 };
+
+// The anchor MD of one lane.
+struct LsAnchor {
+    float x, y, z, r, q, phi;   // q: resolution term |rq.y|; phi in [0, 2 pi)
+    bool end;                   // endcap MD
+    int64_t ebase;              // event * n_mod
+    int32_t r0, r1;             // runs of the module's map row
+    // z window of barrel-to-barrel candidates (valid when zw_on)
+    float zw_lo, zw_hi, zw_r;
+    bool zw_on, zw_off;
+};
+
+__device__ __forceinline__ LsAnchor ls_anchor(const LsArgs &a, int64_t A) {
+    LsAnchor s;
+    const float4 p = a.md_a[A];
+    const float2 rq = a.md_rq[A];
+    const int32_t gm = __float_as_int(p.w);
+    const int32_t e = gm / a.g.n_mod, m = gm - e * a.g.n_mod;
+    s.x = p.x; s.y = p.y; s.z = p.z;
+    s.r = rq.x;
+    s.q = fabsf(rq.y);
+    s.end = signbit(rq.y);
+    float ph = atan2f(p.y, p.x);
+    s.phi = ph < 0.0f ? ph + 6.2831853f : ph;
+    s.ebase = (int64_t)e * a.g.n_mod;
+    s.r0 = a.g.run_off[m];
+    s.r1 = a.g.run_off[m + 1];
+    s.zw_on = s.zw_off = false;
+    s.zw_lo = s.zw_hi = s.zw_r = 0.0f;
+    return s;
+}
+
+// z window of barrel MDs at radii [r_lo, r_hi] for barrel anchor s (see the
+// stage comment): rho0 at c = 0 and r_B = r_lo, rho1 at c = c_max and
+// r_B = r_hi bound rho; sigma_z0 = sigma_z sqrt(1 + (1 + rho)^2) / rho is
+// bounded with rho1 above and rho0 below.
+__device__ __forceinline__ void ls_zwindow(const CutParams &p, float za, float ra, float r_lo, float r_hi,
+                                           float &lo, float &hi) {
+    const float rho0 = r_lo / ra - 1.0f;
+    const float rho1 = arc_len_f(p.cmax, r_hi) / arc_len_f(p.cmax, ra) - 1.0f;
+    const float zt = p.zlum + p.nsig * p.sz * sqrtf(1.0f + (1.0f + rho1) * (1.0f + rho1)) / rho0;
+    const float a0 = (za - zt) * rho0, a1 = (za - zt) * rho1;
+    const float b0 = (za + zt) * rho0, b1 = (za + zt) * rho1;
+    lo = za + fminf(a0, a1);
+    hi = za + fmaxf(b0, b1);
+    const float m = 1e-3f * (hi - lo) + 1e-2f;
+    lo -= m;
+    hi += m;
+}
+
+// Trimmed MD range [j, je) of run k for anchor s (empty when je <= j).
+// Updates the anchor's barrel z window on its first barrel-to-barrel run.
+__device__ __forceinline__ int2 ls_run_range(const LsArgs &a, LsAnchor &s, int32_t k) {
+    const RunRec rr = a.g.runs[k];
+    const int32_t row = rr.row & (kRunNoTrim - 1);
+    const RowConst R = a.g.rows[row];
+    int i0 = 0, i1 = rr.n - 1;
+    bool keep = true;
+    // s ordering: every anchor of the row is below r_A
+    if (R.r_hi * (1.0f + 2e-5f) < s.r) keep = false;
+    // barrel to barrel: z window, for the first barrel radius above r_A that
+    // the map reaches (a second radius switches the window off)
+    if (keep && !s.end && R.kind == 0) {
+        if (!s.zw_on && !s.zw_off) {
+            if (R.r_lo > s.r * 1.0001f) {
+                ls_zwindow(a.p, s.z, s.r, R.r_lo, R.r_hi, s.zw_lo, s.zw_hi);
+                s.zw_r = R.r_lo;
+                s.zw_on = true;
+            } else {
+                s.zw_off = true;
+            }
+        } else if (s.zw_on && s.zw_r != R.r_lo) {
+            s.zw_on = false;
+            s.zw_off = true;
+        }
+        if (s.zw_on && (R.z_hi < s.zw_lo || R.z_lo > s.zw_hi)) keep = false;
+    }
+    // curvature: phi window
+    if (keep && !(rr.row & kRunNoTrim)) {
+        const float dmin = R.r_lo - s.r * (1.0f + 1e-6f);
+        if (dmin > 0.05f) {
+            const float clim = 1.001f * (a.p.cmax + a.p.nsig * sqrtf(s.q + R.qb_max) / dmin);
+            const float xh = clim * R.r_hi;
+            if (xh < 0.85f) {
+                const float w = asinf(xh) - asinf(clim * s.r) + 1e-4f;
+                // window [phi - w, phi + w] against the run [phi_start, phi_start + n dphi],
+                // at shifts of -2 pi, 0, 2 pi; the hull of the overlaps is kept
+                int lo = rr.n, hi = -1;
+#pragma unroll
+                for (int sh = -1; sh <= 1; ++sh) {
+                    const float c = s.phi + (float)sh * 6.2831853f - rr.phi_start;
+                    const float u0 = (c - w) * R.inv_dphi - 1e-4f, u1 = (c + w) * R.inv_dphi + 1e-4f;
+                    if (u1 >= 0.0f && u0 < (float)rr.n) {
+                        const int v0 = u0 < 0.0f ? 0 : (int)u0;
+                        const int v1 = u1 >= (float)(rr.n - 1) ? rr.n - 1 : (int)u1;
+                        lo = v0 < lo ? v0 : lo;
+                        hi = v1 > hi ? v1 : hi;
+                    }
+                }
+                i0 = lo;
+                i1 = hi;
+            }
+        }
+    }
+    if (!keep || i1 < i0) return make_int2(0, 0);
+    const int64_t t0 = s.ebase + rr.t_first;
+    return make_int2((int)a.md_mod_off[t0 + i0], (int)a.md_mod_off[t0 + i1 + 1]);
+}
+
+// Barrel-to-barrel z window test of candidate B (conservative LS2 pre-test).
+__device__ __forceinline__ bool ls_zpass(const LsAnchor &s, float zb, float2 qb) {
+    if (!s.zw_on || signbit(qb.y) || s.end) return true;
+    return zb >= s.zw_lo && zb <= s.zw_hi;
+}
+
+// LS2 on queue entries [0, n) (n <= 64) of Q1, survivors appended to Q2
+// (LS3 runs on Q2 whenever it holds 64 entries). The remaining entries move
+// to the front.
+__device__ void ls_flush2(const LsArgs &a, LsLds &L, int wv, int lane, int64_t wbase, int n, int &q1n, int &q2n,
+                          int &outn);
+
+__device__ __forceinline__ unsigned long long lanes_below(int lane) { return (1ull << lane) - 1ull; }
+
+// LS3 on Q2 entries [0, n); survivors go to the output list with their rank
+// among their owner's survivors.
+__device__ void ls_flush3(const LsArgs &a, LsLds &L, int wv, int lane, int64_t wbase, int n, int &q2n, int &outn) {
+    wave_sync_lds();
+    bool ok = false;
+    int b = 0, owner = 0;
+    if (lane < n) {
+        b = L.q2b[wv][lane];
+        const float cp = L.q2c[wv][lane];
+        const int tg = L.q2t[wv][lane];
+        owner = tg & 63;
+        const float sg = (tg & kTagPos) ? 1.0f : -1.0f;
+        ok = true;
+        if (tg & kTagDirA) {
+            const int64_t A = wbase + owner;
+            const float4 P = a.md_a[A];
+            const float2 o = a.md_o[A];
+            ok = md_dir_pass(a.p, P3{P.x, P.y, P.z}, o.x, o.y, cp, sg);
+        }
+        if (ok && (tg & kTagDirB)) {
+            const float4 P = a.md_a[b];
+            const float2 o = a.md_o[b];
+            ok = md_dir_pass(a.p, P3{P.x, P.y, P.z}, o.x, o.y, cp, sg);
+        }
+    }
+    // move the unprocessed entries to the front
+    const int rest = q2n - n;
+    if (rest > 0) {
+        wave_sync_lds();
+        const int src = n + (lane < rest ? lane : 0);
+        const int tb = L.q2b[wv][src];
+        const float tc = L.q2c[wv][src];
+        const int tt = L.q2t[wv][src];
+        wave_sync_lds();
+        if (lane < rest) { L.q2b[wv][lane] = tb; L.q2c[wv][lane] = tc; L.q2t[wv][lane] = tt; }
+    }
+    q2n = rest;
+    // lanes of the same owner: equal in all six owner bits
+    unsigned long long same = __ballot(ok);
+#pragma unroll
+    for (int bit = 0; bit < 6; ++bit) {
+        const bool v = (owner >> bit) & 1;
+        const unsigned long long m = __ballot(ok && v);
+        same &= v ? m : ~m;
+    }
+    if (!ok) same = 0;
+    const int rank = __popcll(same & lanes_below(lane));
+    wave_sync_lds();
+    const int base = ok ? L.cnt[wv][owner] : 0;
+    wave_sync_lds();
+    if (ok && rank == 0) L.cnt[wv][owner] = base + __popcll(same);
+    const unsigned long long mo = __ballot(ok);
+    const int pos = outn + __popcll(mo & lanes_below(lane));
+    if (ok && pos < kLsOutCap) {
+        L.ob[wv][pos] = b;
+        L.ot[wv][pos] = owner | ((base + rank) << 6);
+    }
+    outn += __popcll(mo);
+    wave_sync_lds();
+}
+
+__device__ void ls_flush2(const LsArgs &a, LsLds &L, int wv, int lane, int64_t wbase, int n, int &q1n, int &q2n,
+                          int &outn) {
+    wave_sync_lds();
+    bool ok = false;
+    int b = 0, tg = 0;
+    float cp = 0.0f;
+    if (lane < n) {
+        b = L.q1b[wv][lane];
+        cp = fminf(L.q1c[wv][lane], a.p.cmax);
+        tg = L.q1t[wv][lane];
+        const int64_t A = wbase + (tg & 63);
+        const float4 PA = a.md_a[A], PB = a.md_a[b];
+        const float2 qa = a.md_rq[A], qb = a.md_rq[b];
+        ok = pair_z0_pass(a.p, P3{PA.x, PA.y, PA.z}, qa, P3{PB.x, PB.y, PB.z}, qb, cp);
+        tg |= (signbit(qa.y) ? 0 : kTagDirA) | (signbit(qb.y) ? 0 : kTagDirB);
+    }
+    const int rest = q1n - n;
+    if (rest > 0) {
+        wave_sync_lds();
+        const int src = n + (lane < rest ? lane : 0);
+        const int tb = L.q1b[wv][src];
+        const float tc = L.q1c[wv][src];
+        const int tt = L.q1t[wv][src];
+        wave_sync_lds();
+        if (lane < rest) { L.q1b[wv][lane] = tb; L.q1c[wv][lane] = tc; L.q1t[wv][lane] = tt; }
+    }
+    q1n = rest;
+    const unsigned long long m = __ballot(ok);
+    const int pos = q2n + __popcll(m & lanes_below(lane));
+    wave_sync_lds();
+    if (ok) { L.q2b[wv][pos] = b; L.q2c[wv][pos] = cp; L.q2t[wv][pos] = tg; }
+    q2n += __popcll(m);
+    if (q2n >= 64) ls_flush3(a, L, wv, lane, wbase, 64, q2n, outn);
+    wave_sync_lds();
+}
+
+// Stage a round of trimmed runs [rbeg, rbeg + kLsRunsPerRound) of each lane's
+// anchor into LDS; returns the number of non-empty ranges of this lane and
+// adds their candidates to *cands.
+__device__ __forceinline__ int ls_stage_round(const LsArgs &a, LsLds &L, int wv, int lane, LsAnchor &s, bool act,
+                                              int rbeg, int rmax, int &cands) {
+    int nr = 0;
+    for (int r = rbeg; r < rbeg + kLsRunsPerRound && r < rmax; ++r) {
+        int2 g = make_int2(0, 0);
+        if (act && s.r0 + r < s.r1) g = ls_run_range(a, s, s.r0 + r);
+        if (g.y > g.x) {
+            L.rng[wv][nr][lane] = g;
+            cands += g.y - g.x;
+            ++nr;
+        }
+    }
+    return nr;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ls_eval(LsArgs a) {
+    __shared__ LsLds L;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t n_md = dev_count(a.counts + LST_COUNT_MD, a.cap_md);
+    const int64_t nwaves = (n_md + 63) / 64;
+    const int64_t ntiles = (nwaves + kLsWaves - 1) / kLsWaves;
+    const TileWalk walk(ntiles);
+    for (int64_t tile = walk.first; tile < walk.end; tile += walk.step) {
+        const int64_t w = tile * kLsWaves + wv;
+        if (w >= nwaves) continue;             // wavefront-uniform
+        const int64_t wbase = w * 64, A = wbase + lane;
+        const bool act = A < n_md;
+        const int64_t a_safe = act ? A : n_md - 1;
+        LsAnchor s = ls_anchor(a, a_safe);
+        L.cnt[wv][lane] = 0;
+        int q1n = 0, q2n = 0, outn = 0, cands = 0;
+        // runs of the wavefront's longest map row
+        int nrun = act ? s.r1 - s.r0 : 0;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const int o = __shfl_xor(nrun, d, 64);
+            nrun = o > nrun ? o : nrun;
+        }
+        const P3 PA{s.x, s.y, s.z};
+        const float2 qa = make_float2(s.r, s.end ? -s.q : s.q);
+        for (int rbeg = 0; rbeg < nrun; rbeg += kLsRunsPerRound) {
+            const int nr = ls_stage_round(a, L, wv, lane, s, act, rbeg, nrun, cands);
+            wave_sync_lds();
+            int ri = 0, j = 0, je = 0;
+            bool on = nr > 0;
+            if (on) { const int2 g = L.rng[wv][0][lane]; j = g.x; je = g.y; }
+            // the next candidate's records are loaded one step ahead
+            int jn = on ? j : (int)a_safe;
+            float4 nb = a.md_a[jn];
+            float2 nq = a.md_rq[jn];
+            while (__ballot(on) != 0ull) {
+                const bool cur = on;
+                const int b = j;
+                const float4 PB = nb;
+                const float2 qb = nq;
+                if (on) {
+                    ++j;
+                    if (j >= je) {
+                        ++ri;
+                        if (ri < nr) { const int2 g = L.rng[wv][ri][lane]; j = g.x; je = g.y; }
+                        else on = false;
+                    }
+                }
+                jn = on ? j : (int)a_safe;
+                nb = a.md_a[jn];
+                nq = a.md_rq[jn];
+                bool pass = false;
+                float c = 0.0f, sg = 0.0f;
+                if (cur && ls_zpass(s, PB.z, qb))
+                    pass = pair_curv_pass(a.p, PA, qa, P3{PB.x, PB.y, PB.z}, qb, c, sg);
+                const unsigned long long m = __ballot(pass);
+                if (pass) {
+                    const int pos = q1n + __popcll(m & lanes_below(lane));
+                    L.q1b[wv][pos] = b;
+                    L.q1c[wv][pos] = c;
+                    L.q1t[wv][pos] = lane | (sg > 0.0f ? kTagPos : 0);
+                }
+                q1n += __popcll(m);
+                if (q1n >= 64) ls_flush2(a, L, wv, lane, wbase, 64, q1n, q2n, outn);
+            }
+        }
+        // drain the queues
+        if (q1n > 0) ls_flush2(a, L, wv, lane, wbase, q1n, q1n, q2n, outn);
+        while (q2n > 0) ls_flush3(a, L, wv, lane, wbase, q2n < 64 ? q2n : 64, q2n, outn);
+        wave_sync_lds();
+        // per-A counts, the wavefront's prefix over them, and its chunk
+        const int c = act ? L.cnt[wv][lane] : 0;
+        if (act) a.ls_cnt[A] = c;
+        int incl = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        const int tot = __shfl(incl, 63, 64);
+        wave_sync_lds();
+        L.cnt[wv][lane] = incl - c;            // exclusive prefix, by owner
+        wave_sync_lds();
+        bool ovf = outn > kLsOutCap;
+        long long base = 0;
+        if (!ovf && tot > 0) {
+            unsigned long long b0 = 0;
+            if (lane == 0) b0 = atomicAdd(a.top, (unsigned long long)tot);
+            base = (long long)__shfl((long long)b0, 0, 64);
+            if (base + tot > a.cap_chunk) ovf = true;
+        }
+        if (!ovf)
+            for (int i = lane; i < outn; i += 64) {
+                const int t = L.ot[wv][i];
+                const int owner = t & 63;
+                a.chunk[base + L.cnt[wv][owner] + (t >> 6)] = make_int2((int)(wbase + owner), L.ob[wv][i]);
+            }
+        int cs = cands;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) cs += __shfl_xor(cs, d, 64);
+        if (lane == 0) {
+            a.wave_base[w] = ovf ? -1 : base;
+            atomicAdd((unsigned long long *)&a.counts[LST_COUNT_LSCAND], (unsigned long long)cs);
+        }
+        wave_sync_lds();
+    }
+}
+
+// One A per lane, every candidate in order with all cuts, writing LS to
+// ls_md[k..] (the recompute path of a wavefront whose survivors overflowed
+// its list; identical cut code, so identical results).
+__device__ void ls_recompute(const LsArgs &a, int64_t A, int64_t k, int2 *ls_md, int64_t cap_ls) {
+    LsAnchor s = ls_anchor(a, A);
+    const P3 PA{s.x, s.y, s.z};
+    const float2 qa = make_float2(s.r, s.end ? -s.q : s.q);
+    const float2 oa = a.md_o[A];
+    for (int32_t r = s.r0; r < s.r1; ++r) {
+        const int2 g = ls_run_range(a, s, r);
+        for (int b = g.x; b < g.y; ++b) {
+            const float4 PB = a.md_a[b];
+            const float2 qb = a.md_rq[b];
+            if (!ls_zpass(s, PB.z, qb)) continue;
+            float c, sg;
+            if (!pair_curv_pass(a.p, PA, qa, P3{PB.x, PB.y, PB.z}, qb, c, sg)) continue;
+            const float cp = fminf(c, a.p.cmax);
+            if (!pair_z0_pass(a.p, PA, qa, P3{PB.x, PB.y, PB.z}, qb, cp)) continue;
+            const float sgn = sg > 0.0f ? 1.0f : -1.0f;
+            if (!s.end && !md_dir_pass(a.p, PA, oa.x, oa.y, cp, sgn)) continue;
+            if (!signbit(qb.y)) {
+                const float2 ob = a.md_o[b];
+                if (!md_dir_pass(a.p, P3{PB.x, PB.y, PB.z}, ob.x, ob.y, cp, sgn)) continue;
+            }
+            if (k < cap_ls) ls_md[k] = make_int2((int)A, b);
+            ++k;
+        }
+    }
+}
+
+// Place every wavefront's segments at their CSR offsets (ls_off = exclusive
+// scan of the per-A counts), or recompute the wavefronts that overflowed.
+__global__ __launch_bounds__(kBlock) void k_ls_place(LsArgs a, const int64_t *ls_off, int2 *ls_md, int64_t cap_ls) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t n_md = dev_count(a.counts + LST_COUNT_MD, a.cap_md);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.counts[LST_COUNT_LS] = ls_off[n_md];
+    const int64_t nwaves = (n_md + 63) / 64;
+    const int64_t ntiles = (nwaves + kLsWaves - 1) / kLsWaves;
+    const TileWalk walk(ntiles);
+    for (int64_t tile = walk.first; tile < walk.end; tile += walk.step) {
+        const int64_t w = tile * kLsWaves + wv;
+        if (w >= nwaves) continue;
+        const int64_t A0 = w * 64, A1 = A0 + 64 < n_md ? A0 + 64 : n_md;
+        const int64_t o0 = ls_off[A0], tot = ls_off[A1] - o0;
+        const int64_t wb = a.wave_base[w];
+        if (wb >= 0) {
+            for (int64_t i = lane; i < tot; i += 64)
+                if (o0 + i < cap_ls) ls_md[o0 + i] = a.chunk[wb + i];
+        } else if (A0 + lane < n_md) {
+            ls_recompute(a, A0 + lane, ls_off[A0 + lane], ls_md, cap_ls);
+        }
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+}
 
 // ------------------------------------------------------------ T3 stage
 // Anchor: the inner LS (A, B); candidates: every LS starting at B, which the
@@ -1162,7 +1454,8 @@ struct LSStage {
 
 struct T3Stage {
     const int2 *ls_md;
-    const int64_t *ls_off;
+    const int64_t *ls_off;        // CSR of LS by inner MD (entries may exceed cap_ls after an overflow)
+    int64_t cap_ls;
     const float4 *md_a;
     const float2 *md_o;
     const float2 *md_rq;
@@ -1180,14 +1473,18 @@ struct T3Stage {
     struct Rec { int li, lo, A, B, C; };
     struct Mid {};
 
+    __device__ int64_t lsoff(int64_t md) const {
+        const int64_t v = ls_off[md];
+        return v < cap_ls ? v : cap_ls;
+    }
     __device__ int64_t count(int64_t l1) const {
         const int B = ls_md[l1].y;
-        return ls_off[B + 1] - ls_off[B];
+        return lsoff(B + 1) - lsoff(B);
     }
     __device__ void info(int64_t l1, int32_t *f) const {
         const int2 lm = ls_md[l1];
-        const int64_t o0 = ls_off[lm.y];
-        f[0] = (int32_t)o0; f[1] = (int32_t)(ls_off[lm.y + 1] - o0); f[2] = lm.x; f[3] = lm.y;
+        const int64_t o0 = lsoff(lm.y);
+        f[0] = (int32_t)o0; f[1] = (int32_t)(lsoff(lm.y + 1) - o0); f[2] = lm.x; f[3] = lm.y;
     }
     template <class LDS>
     __device__ void prepare(LDS &, int64_t, int) const {}
@@ -1494,7 +1791,7 @@ hipError_t set_single_event(int64_t *ev_off, int64_t n, hipStream_t st) {
 }
 
 hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipStream_t st) {
-    const int32_t n_mod = a.g.n_mod, n_sens = a.g.n_sens, n_map = a.g.n_map;
+    const int32_t n_mod = a.g.n_mod, n_sens = a.g.n_sens;
     const int64_t ngm = (int64_t)a.n_ev * n_mod;
     int64_t *cnt = o.counts;
 
@@ -1524,27 +1821,35 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     mark(ev, 3, st);
 
     // a2: mini-doublets, anchored on (event, module)
-    MDStage md{w.bin_off, w.bin_hit, a.g.mod, a.p, n_mod, n_sens, o.md_hits, w.md_a, w.md_o, w.md_rq};
+    MDStage md{w.bin_off, w.bin_hit, a.g.mod, a.g.box, o.counts, a.p, n_mod, n_sens, o.md_hits, w.md_a, w.md_o,
+               w.md_rq};
     mark(ev, 14, st);
     run_stage(md, nullptr, ngm, w, cnt + LST_COUNT_MD, w.cap_md, cnt, st, ev, 2, a.tune);
     hipLaunchKernelGGL(k_fill_offsets<GmKey>, dim3(grid_for(w.cap_md + 1)), dim3(kBlock), 0, st, GmKey{w.md_a},
                        cnt + LST_COUNT_MD, w.cap_md, nullptr, ngm, w.md_mod_off);
     mark(ev, 15, st);
-    mark(ev, 16, st);
-    hipLaunchKernelGGL(k_ls_prefix, dim3(grid_for((ngm + kPrefRows - 1) / kPrefRows * kPrefSeg)), dim3(kBlock), 0, st, a.g.map_off, a.g.map_tgt, n_mod,
-                       n_map, a.n_ev, w.md_mod_off, w.rsum, w.rpref);
 
-    // a3: line segments, anchored on (event, module): the module's MDs against
-    // the MDs of its mapped modules
-    LSStage ls{w.md_a, w.md_o, w.md_rq, w.md_mod_off, w.rsum, w.rpref, a.g.map_off, a.g.map_tgt, a.g.mod, a.p,
-               n_mod, n_map, o.ls_md};
-    run_stage(ls, nullptr, ngm, w, cnt + LST_COUNT_LS, w.cap_ls, cnt, st, ev, 3, a.tune);
-    hipLaunchKernelGGL(k_fill_offsets<LsInKey>, dim3(grid_for(w.cap_ls + 1)), dim3(kBlock), 0, st, LsInKey{o.ls_md},
-                       cnt + LST_COUNT_LS, w.cap_ls, cnt + LST_COUNT_MD, w.cap_md, w.ls_off);
+    // a3: line segments, one inner MD per lane over the trimmed runs of its
+    // module-map row; CSR offsets by inner MD from the per-MD counts
+    mark(ev, 16, st);
+    LsArgs la{w.md_a, w.md_o, w.md_rq, w.md_mod_off, a.g, a.p, w.ls_cnt, w.ls_chunk, w.cap_ls, w.ls_wave,
+              w.ls_top, cnt, w.cap_md};
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.ls_top);
+    {
+        const int64_t tiles = (w.cap_md + 64 * kLsWaves - 1) / (64 * kLsWaves);
+        int nb = (int)(tiles < kLsBlocks ? tiles : kLsBlocks);
+        nb = round_up_xcd(nb < 1 ? 1 : nb);
+        mark(ev, 6, st);
+        hipLaunchKernelGGL(k_ls_eval, dim3(nb), dim3(kBlock), 0, st, la);
+        mark(ev, 7, st);
+        scan(CntF{w.ls_cnt}, cnt + LST_COUNT_MD, w.cap_md, w, w.ls_off, nullptr, st);
+        hipLaunchKernelGGL(k_ls_place, dim3(nb), dim3(kBlock), 0, st, la, (const int64_t *)w.ls_off, (int2 *)o.ls_md,
+                           w.cap_ls);
+    }
     mark(ev, 17, st);
 
     // a4: triplets, anchored on the inner LS
-    T3Stage t3{o.ls_md, w.ls_off, w.md_a, w.md_o, w.md_rq, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
+    T3Stage t3{o.ls_md, w.ls_off, w.cap_ls, w.md_a, w.md_o, w.md_rq, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
     mark(ev, 18, st);
     run_stage(t3, cnt + LST_COUNT_LS, w.cap_ls, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st, ev, 4, a.tune);
     hipLaunchKernelGGL(k_fill_offsets<T3InKey>, dim3(grid_for(w.cap_t3 + 1)), dim3(kBlock), 0, st, T3InKey{w.t3_mds},
