@@ -183,9 +183,9 @@ lst_status lst_score(lst_ctx *ctx, const void *X_dev, int32_t x_dtype, int64_t n
  * recent completed build, n <= 10 durations in ms: 0 whole build, 1 hit
  * binning, 2 MD, 3 LS, 4 T3 (2-4: each stage's candidate-evaluation kernel
  * alone), 5 T5 compaction kernels, 6 T5 features + DNN scoring, 7 MD, 8 LS,
- * 9 T3 (7-9: the whole stage, from the candidate-count scan through the
- * CSR offsets the next stage reads). The caller synchronises the stream
- * first; LST_E_STATE if timing was never enabled. */
+ * 9 T3 (7-9: the whole stage, through the CSR offsets the next stage
+ * reads). The caller synchronises the stream first; LST_E_STATE if timing
+ * was never enabled. */
 lst_status lst_set_timing(lst_ctx *ctx, int32_t enable);
 lst_status lst_stage_times(lst_ctx *ctx, float *ms, int32_t n);
 

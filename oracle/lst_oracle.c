@@ -76,7 +76,12 @@ orc_geom *orc_geom_load(const void *blob, size_t nbytes) {
     g->map_tgt = (uint32_t *)malloc(sizeof(uint32_t) * (nmap ? nmap : 1));
     memcpy(g->map_off, r, 4 * ((size_t)nm + 1));
     memcpy(g->map_tgt, r + 4 * ((size_t)nm + 1), 4 * (size_t)nmap);
-    if (g->map_off[nm] != nmap) { orc_geom_free(g); return NULL; }
+    /* a map row per module, in order, and targets that are modules */
+    int ok = g->map_off[0] == 0 && g->map_off[nm] == nmap && nm > 0 && nb <= nm;
+    for (uint32_t m = 0; ok && m < nm; ++m) ok = g->map_off[m] <= g->map_off[m + 1];
+    for (uint32_t i = 0; ok && i < nmap; ++i) ok = g->map_tgt[i] < nm;
+    for (uint32_t m = 0; ok && m < nm; ++m) ok = g->kind[m] == 0 || g->kind[m] == 1;
+    if (!ok) { orc_geom_free(g); return NULL; }
     return g;
 }
 
@@ -104,6 +109,8 @@ orc_model *orc_model_load(const void *blob, size_t nbytes) {
     const unsigned char *b = (const unsigned char *)blob;
     if (nbytes < 24 || memcmp(b, "LSTM", 4) != 0 || rd_u32(b + 4) != 1) return NULL;
     int ni = (int)rd_u32(b + 8), h1 = (int)rd_u32(b + 12), h2 = (int)rd_u32(b + 16);
+    /* the forward pass keeps each layer in a 64-entry array */
+    if (ni < 1 || ni > 64 || h1 < 1 || h1 > 64 || h2 < 1 || h2 > 64) return NULL;
     size_t nf = (size_t)2 * ni + (size_t)h1 * ni + h1 + (size_t)h2 * h1 + h2 + h2 + 1;
     if (nbytes != 24 + 4 * nf) return NULL;
     orc_model *m = (orc_model *)calloc(1, sizeof(orc_model));

@@ -12,6 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblst.so")
 SOURCES = ["lst_capi.hip", "lst_pipeline.hip", "lst_score.hip", "lst_gnn.hip"]
+HOST_SOURCES = ["lst_host.cpp"]      # plain C++ (blob parsers), built with the host compiler
+CXX = os.environ.get("CXX", "g++")
 ARCH = os.environ.get("LST_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # FP32 division and square root use the hardware's 1-ulp sequences instead of
@@ -40,8 +42,18 @@ def build(verbose: bool = False) -> str:
             print(r.stderr, file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+    def compile_host(src):
+        obj = os.path.join(objdir, src.replace(".cpp", ".o"))
+        cmd = [CXX, "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"{CXX} failed for {src}:\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + len(HOST_SOURCES)) as ex:
+        objs = list(ex.map(compile_one, SOURCES)) + list(ex.map(compile_host, HOST_SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *FLAGS, "-shared", *objs, "-o", tmp]
     if verbose:

@@ -1,7 +1,7 @@
 // Device-side data layout and arithmetic of the LST object builder (gfx950).
 //
-// Cuts (paper Sec. 1: "pre-defined quality selections ... consistency with a
-// continuous, helical trajectory") are evaluated in FP32; the paper gives no
+// Cuts (paper Sec. 1: each object is kept only if its hits are compatible
+// with one helix from the beam line) are evaluated in FP32; the paper gives no
 // formulas, so they follow this project's reading, derived from the helix of a
 // track from the beam line: half-curvature c = 1 / (2R), radius along the arc
 // r(s) = sin(c s) / c, z linear in s. Every cut is "pass iff v <= t" written
@@ -11,64 +11,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lst_host.h"
+
 namespace lst {
 
-constexpr int kNFeat = 42;
-constexpr int kH1 = 32;
-constexpr int kH2 = 32;
 constexpr int kMinTile = 256;       // smallest compaction tile (candidates)
-
-// ------------------------------------------------------------------ layout
-
-// Per-module constants, derived on the host from the FP64 geometry.
-struct ModConst {
-    int32_t kind;      // 0 barrel, 1 endcap
-    int32_t layer;     // 1..6 barrel, 7..11 disks
-    float b1_t;        // barrel: MD bend threshold (envelope + resolution)
-    float rho0;        // barrel: (r_up - r_lo) / r_lo
-    float rho1;        // barrel: (S(r_up) - S(r_lo)) / S(r_lo) at c_max
-    float gap;         // sensor separation
-    float pad0, pad1;
-};
-
-struct CutParams {
-    float kb, cmax, zlum, nsig, srphi, sz, sr, e2slack, ls3slack, chi2rz, chi2rphi;
-    double kb_d, cmax_d, zlum_d, nsig_d, srphi_d, sz_d, sr_d;
-    double isrphi_d, isr_d, isz_d;        // 1 / sigma, so the fits multiply instead of divide
-};
 
 struct ModelDev {
     const float *mu, *sd, *W1, *b1, *W2, *b2, *w3;
     float b3;
 };
-
-// Where a module's anchor hits lie (nominal sensor extent widened by a small
-// tolerance): transverse radius, z and azimuth ranges (phi in [0, 2 pi)).
-// Hits off their sensor are rejected as invalid input, so these boxes bound
-// every MD anchor of the module.
-struct ModBox {
-    float r_lo, r_hi, z_lo, z_hi, phi_lo, phi_hi, pad0, pad1;
-};
-
-// A row of the detector: modules of one layer (barrel z tile or endcap
-// ring) side by side in phi, all of one phi width.
-struct RowConst {
-    float r_lo, r_hi, z_lo, z_hi;   // anchor extent of the row's modules (ModBox)
-    float dphi, inv_dphi;           // phi width of a module and its inverse
-    float qb_max;                   // largest per-MD resolution term q of an anchor in the row
-    int32_t kind;                   // 0 barrel, 1 endcap
-};
-
-// A run of a module's map row: n consecutive target modules t_first ..
-// t_first + n - 1 of one detector row, adjacent in phi from phi_start.
-// row: index into the row table; bit 30: no phi trimming (the run reaches
-// phi separations where a circle through the beam line could pass the
-// curvature cut on its far side).
-struct RunRec {
-    int32_t t_first, n, row;
-    float phi_start;
-};
-constexpr int32_t kRunNoTrim = 1 << 30;
 
 // Batch-wide geometry handles.
 struct GeomDev {
@@ -78,7 +30,6 @@ struct GeomDev {
     const ModBox *box;        // [n_mod]
     const int32_t *run_off;   // [n_mod + 1] runs of each module's map row
     const RunRec *runs;       // [n_runs]
-    const RowConst *rows;     // [n_rows]
     int32_t n_mod, n_sens, n_map;
 };
 

@@ -107,18 +107,12 @@ struct RunArgs {
 
 // Timing windows (pairs of events): 0 whole build, 1 binning, 2 MD, 3 LS,
 // 4 T3 (2-4: the stage's eval kernel alone), 5 T5 compaction kernels, 6 T5
-// features + DNN scoring, then the whole MD, LS and T3 stages (7, 8, 9):
-// candidate-count scan, eval, tile-count scan, copy and CSR fill, for LS
-// also the per-entry prefix of the module map.
+// features + DNN scoring, then the whole MD, LS and T3 stages (7, 8, 9): for
+// MD and T3 the candidate-count scan, eval, tile-count scan, copy and CSR
+// fill; for LS the eval, the scan of the per-MD counts and the placement.
 constexpr int kTimingWindows = 10;
 constexpr int kTimingEvents = 2 * kTimingWindows;
 
-// Edge classifier: layers in model-blob order; all but the last are run on
-// MFMA from fragments in A-operand order (see lst_gnn.hip).
-enum GnnLayer {
-    kGEnc1, kGEnc2, kGInit, kGEdgeA0, kGEdgeB0, kGNodeA0, kGNodeB0, kGEdgeA1, kGEdgeB1, kGNodeA1, kGNodeB1,
-    kGHead1, kGHead2, kGnnLayers
-};
 struct GnnDev {
     const uint4 *frag;                // BF16 fragments of every MFMA layer
     int64_t foff[kGnnLayers];         // first fragment of each layer

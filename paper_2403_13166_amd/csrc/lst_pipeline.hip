@@ -995,33 +995,31 @@ __global__ __launch_bounds__(kBlock) void k_fill_offsets(KF key, const int64_t *
 // lie on their sensors (checked when MDs are written), so trimming never
 // removes a pair that the cuts would accept.
 //
-// Candidates that pass LS1 are queued in LDS; LS2 runs on dense batches of
-// 64 queue entries, and its survivors are queued again for LS3. A survivor
-// gets its rank among the survivors of its A (queues keep each A's candidate
-// order). At the end the wavefront knows its per-A counts, claims a chunk of
-// a scratch array with one atomic add, and writes its segments there in
-// (A, B) order. A scan of the per-A counts gives the CSR offsets of LS by
+// Each lane applies LS1 and LS2 to its candidates as it walks them (the
+// record of the next one is already in flight); pairs passing both are
+// queued in LDS and LS3 runs on dense batches of 64 queue entries. A survivor
+// gets its rank among the survivors of its A (the queue keeps each A's
+// candidate order). At the end the wavefront knows its per-A counts, claims a
+// chunk of a scratch array with one atomic add, and writes its segments there
+// in (A, B) order. A scan of the per-A counts gives the CSR offsets of LS by
 // inner MD, and a placement kernel copies every wavefront's chunk to its
 // final position. A wavefront whose survivors do not fit its LDS list is
 // recomputed by the placement kernel, one A per lane, writing directly.
 
 constexpr int kLsWaves = kBlock / 64;
-constexpr int kLsRunsPerRound = 6;      // trimmed runs staged per lane at a time
-constexpr int kLsQCap = 128;            // LS1 / LS2 queue entries per wavefront
-constexpr int kLsOutCap = 256;          // survivors kept per wavefront in LDS
-constexpr int kLsBlocks = 1024;         // persistent blocks of the eval and placement kernels
+constexpr int kLsRunsPerRound = 6;      // trimmed runs staged per lane at a time (even)
+constexpr int kLsQCap = 128;            // LS3 queue entries per wavefront
+constexpr int kLsOutCap = 512;          // survivors kept per wavefront in LDS
+constexpr int kLsBlocks = 1280;         // persistent blocks of the eval and placement kernels
 // queue entry tag: bits 0-5 owner lane, 6 bends positive, 7 / 8 direction cut
 // on A / on B (barrel MDs)
 constexpr int kTagPos = 64, kTagDirA = 128, kTagDirB = 256;
 
 struct LsLds {
     int2 rng[kLsWaves][kLsRunsPerRound][64];   // trimmed MD ranges [j, je) of each lane
-    int q1b[kLsWaves][kLsQCap];
-    float q1c[kLsWaves][kLsQCap];
-    int q1t[kLsWaves][kLsQCap];
-    int q2b[kLsWaves][kLsQCap];
-    float q2c[kLsWaves][kLsQCap];
-    int q2t[kLsWaves][kLsQCap];
+    int qb[kLsWaves][kLsQCap];                 // LS3 queue: B
+    float qc[kLsWaves][kLsQCap];               //            clamped curvature
+    int qt[kLsWaves][kLsQCap];                 //            tag
     int ob[kLsWaves][kLsOutCap];               // survivors: B
     int ot[kLsWaves][kLsOutCap];               // owner lane | rank among the owner's survivors << 6
     int cnt[kLsWaves][64];                     // survivors per owner lane
@@ -1092,39 +1090,36 @@ __device__ __forceinline__ void ls_zwindow(const CutParams &p, float za, float r
     hi += m;
 }
 
-// Trimmed MD range [j, je) of run k for anchor s (empty when je <= j).
-// Updates the anchor's barrel z window on its first barrel-to-barrel run.
-__device__ __forceinline__ int2 ls_run_range(const LsArgs &a, LsAnchor &s, int32_t k) {
-    const RunRec rr = a.g.runs[k];
-    const int32_t row = rr.row & (kRunNoTrim - 1);
-    const RowConst R = a.g.rows[row];
+// Kept target modules [t0, t0 + i0 .. i1] of run rr for anchor s (i1 < i0:
+// none). Sets the anchor's barrel z window on its first barrel-to-barrel run.
+__device__ __forceinline__ int2 ls_run_trim(const CutParams &p, LsAnchor &s, const RunRec &rr) {
     int i0 = 0, i1 = rr.n - 1;
     bool keep = true;
     // s ordering: every anchor of the row is below r_A
-    if (R.r_hi * (1.0f + 2e-5f) < s.r) keep = false;
+    if (rr.r_hi * (1.0f + 2e-5f) < s.r) keep = false;
     // barrel to barrel: z window, for the first barrel radius above r_A that
     // the map reaches (a second radius switches the window off)
-    if (keep && !s.end && R.kind == 0) {
+    if (keep && !s.end && !(rr.flags & kRunEndcap)) {
         if (!s.zw_on && !s.zw_off) {
-            if (R.r_lo > s.r * 1.0001f) {
-                ls_zwindow(a.p, s.z, s.r, R.r_lo, R.r_hi, s.zw_lo, s.zw_hi);
-                s.zw_r = R.r_lo;
+            if (rr.r_lo > s.r * 1.0001f) {
+                ls_zwindow(p, s.z, s.r, rr.r_lo, rr.r_hi, s.zw_lo, s.zw_hi);
+                s.zw_r = rr.r_lo;
                 s.zw_on = true;
             } else {
                 s.zw_off = true;
             }
-        } else if (s.zw_on && s.zw_r != R.r_lo) {
+        } else if (s.zw_on && s.zw_r != rr.r_lo) {
             s.zw_on = false;
             s.zw_off = true;
         }
-        if (s.zw_on && (R.z_hi < s.zw_lo || R.z_lo > s.zw_hi)) keep = false;
+        if (s.zw_on && (rr.z_hi < s.zw_lo || rr.z_lo > s.zw_hi)) keep = false;
     }
     // curvature: phi window
-    if (keep && !(rr.row & kRunNoTrim)) {
-        const float dmin = R.r_lo - s.r * (1.0f + 1e-6f);
+    if (keep && !(rr.flags & kRunNoTrim)) {
+        const float dmin = rr.r_lo - s.r * (1.0f + 1e-6f);
         if (dmin > 0.05f) {
-            const float clim = 1.001f * (a.p.cmax + a.p.nsig * sqrtf(s.q + R.qb_max) / dmin);
-            const float xh = clim * R.r_hi;
+            const float clim = 1.001f * (p.cmax + p.nsig * sqrtf(s.q + rr.qb_max) / dmin);
+            const float xh = clim * rr.r_hi;
             if (xh < 0.85f) {
                 const float w = asinf(xh) - asinf(clim * s.r) + 1e-4f;
                 // window [phi - w, phi + w] against the run [phi_start, phi_start + n dphi],
@@ -1133,7 +1128,7 @@ __device__ __forceinline__ int2 ls_run_range(const LsArgs &a, LsAnchor &s, int32
 #pragma unroll
                 for (int sh = -1; sh <= 1; ++sh) {
                     const float c = s.phi + (float)sh * 6.2831853f - rr.phi_start;
-                    const float u0 = (c - w) * R.inv_dphi - 1e-4f, u1 = (c + w) * R.inv_dphi + 1e-4f;
+                    const float u0 = (c - w) * rr.inv_dphi - 1e-4f, u1 = (c + w) * rr.inv_dphi + 1e-4f;
                     if (u1 >= 0.0f && u0 < (float)rr.n) {
                         const int v0 = u0 < 0.0f ? 0 : (int)u0;
                         const int v1 = u1 >= (float)(rr.n - 1) ? rr.n - 1 : (int)u1;
@@ -1146,9 +1141,8 @@ __device__ __forceinline__ int2 ls_run_range(const LsArgs &a, LsAnchor &s, int32
             }
         }
     }
-    if (!keep || i1 < i0) return make_int2(0, 0);
-    const int64_t t0 = s.ebase + rr.t_first;
-    return make_int2((int)a.md_mod_off[t0 + i0], (int)a.md_mod_off[t0 + i1 + 1]);
+    if (!keep) i1 = i0 - 1;
+    return make_int2(i0, i1);
 }
 
 // Barrel-to-barrel z window test of candidate B (conservative LS2 pre-test).
@@ -1157,51 +1151,52 @@ __device__ __forceinline__ bool ls_zpass(const LsAnchor &s, float zb, float2 qb)
     return zb >= s.zw_lo && zb <= s.zw_hi;
 }
 
-// LS2 on queue entries [0, n) (n <= 64) of Q1, survivors appended to Q2
-// (LS3 runs on Q2 whenever it holds 64 entries). The remaining entries move
-// to the front.
-__device__ void ls_flush2(const LsArgs &a, LsLds &L, int wv, int lane, int64_t wbase, int n, int &q1n, int &q2n,
-                          int &outn);
-
 __device__ __forceinline__ unsigned long long lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
-// LS3 on Q2 entries [0, n); survivors go to the output list with their rank
-// among their owner's survivors.
-__device__ void ls_flush3(const LsArgs &a, LsLds &L, int wv, int lane, int64_t wbase, int n, int &q2n, int &outn) {
+// LS1 and LS2 of (A, B); on a pass, the clamped curvature and the queue tag.
+__device__ __forceinline__ bool ls_pair(const CutParams &p, const LsAnchor &s, P3 PA, float2 qa, float4 PB,
+                                        float2 qb, int lane, float &cp, int &tag) {
+    if (!ls_zpass(s, PB.z, qb)) return false;
+    float c, sg;
+    if (!pair_curv_pass(p, PA, qa, P3{PB.x, PB.y, PB.z}, qb, c, sg)) return false;
+    cp = fminf(c, p.cmax);
+    if (!pair_z0_pass(p, PA, qa, P3{PB.x, PB.y, PB.z}, qb, cp)) return false;
+    tag = lane | (sg > 0.0f ? kTagPos : 0) | (s.end ? 0 : kTagDirA) | (signbit(qb.y) ? 0 : kTagDirB);
+    return true;
+}
+
+// LS3 on queue entries [0, n) (n <= 64); survivors go to the output list
+// with their rank among their owner's survivors, the remaining entries move
+// to the front.
+__device__ void ls_flush(const LsArgs &a, LsLds &L, int wv, int lane, int64_t wbase, int n, int &qn, int &outn) {
     wave_sync_lds();
     bool ok = false;
     int b = 0, owner = 0;
     if (lane < n) {
-        b = L.q2b[wv][lane];
-        const float cp = L.q2c[wv][lane];
-        const int tg = L.q2t[wv][lane];
+        b = L.qb[wv][lane];
+        const float cp = L.qc[wv][lane];
+        const int tg = L.qt[wv][lane];
         owner = tg & 63;
         const float sg = (tg & kTagPos) ? 1.0f : -1.0f;
+        const int64_t A = wbase + owner;
+        const int64_t ia = (tg & kTagDirA) ? A : b, ib = (tg & kTagDirB) ? b : ia;
+        const float4 PA = a.md_a[ia], PB = a.md_a[ib];
+        const float2 oa = a.md_o[ia], ob = a.md_o[ib];
         ok = true;
-        if (tg & kTagDirA) {
-            const int64_t A = wbase + owner;
-            const float4 P = a.md_a[A];
-            const float2 o = a.md_o[A];
-            ok = md_dir_pass(a.p, P3{P.x, P.y, P.z}, o.x, o.y, cp, sg);
-        }
-        if (ok && (tg & kTagDirB)) {
-            const float4 P = a.md_a[b];
-            const float2 o = a.md_o[b];
-            ok = md_dir_pass(a.p, P3{P.x, P.y, P.z}, o.x, o.y, cp, sg);
-        }
+        if (tg & kTagDirA) ok = md_dir_pass(a.p, P3{PA.x, PA.y, PA.z}, oa.x, oa.y, cp, sg);
+        if (ok && (tg & kTagDirB)) ok = md_dir_pass(a.p, P3{PB.x, PB.y, PB.z}, ob.x, ob.y, cp, sg);
     }
-    // move the unprocessed entries to the front
-    const int rest = q2n - n;
+    const int rest = qn - n;
     if (rest > 0) {
         wave_sync_lds();
         const int src = n + (lane < rest ? lane : 0);
-        const int tb = L.q2b[wv][src];
-        const float tc = L.q2c[wv][src];
-        const int tt = L.q2t[wv][src];
+        const int tb = L.qb[wv][src];
+        const float tc = L.qc[wv][src];
+        const int tt = L.qt[wv][src];
         wave_sync_lds();
-        if (lane < rest) { L.q2b[wv][lane] = tb; L.q2c[wv][lane] = tc; L.q2t[wv][lane] = tt; }
+        if (lane < rest) { L.qb[wv][lane] = tb; L.qc[wv][lane] = tc; L.qt[wv][lane] = tt; }
     }
-    q2n = rest;
+    qn = rest;
     // lanes of the same owner: equal in all six owner bits
     unsigned long long same = __ballot(ok);
 #pragma unroll
@@ -1226,59 +1221,63 @@ __device__ void ls_flush3(const LsArgs &a, LsLds &L, int wv, int lane, int64_t w
     wave_sync_lds();
 }
 
-__device__ void ls_flush2(const LsArgs &a, LsLds &L, int wv, int lane, int64_t wbase, int n, int &q1n, int &q2n,
-                          int &outn) {
-    wave_sync_lds();
-    bool ok = false;
-    int b = 0, tg = 0;
-    float cp = 0.0f;
-    if (lane < n) {
-        b = L.q1b[wv][lane];
-        cp = fminf(L.q1c[wv][lane], a.p.cmax);
-        tg = L.q1t[wv][lane];
-        const int64_t A = wbase + (tg & 63);
-        const float4 PA = a.md_a[A], PB = a.md_a[b];
-        const float2 qa = a.md_rq[A], qb = a.md_rq[b];
-        ok = pair_z0_pass(a.p, P3{PA.x, PA.y, PA.z}, qa, P3{PB.x, PB.y, PB.z}, qb, cp);
-        tg |= (signbit(qa.y) ? 0 : kTagDirA) | (signbit(qb.y) ? 0 : kTagDirB);
-    }
-    const int rest = q1n - n;
-    if (rest > 0) {
-        wave_sync_lds();
-        const int src = n + (lane < rest ? lane : 0);
-        const int tb = L.q1b[wv][src];
-        const float tc = L.q1c[wv][src];
-        const int tt = L.q1t[wv][src];
-        wave_sync_lds();
-        if (lane < rest) { L.q1b[wv][lane] = tb; L.q1c[wv][lane] = tc; L.q1t[wv][lane] = tt; }
-    }
-    q1n = rest;
-    const unsigned long long m = __ballot(ok);
-    const int pos = q2n + __popcll(m & lanes_below(lane));
-    wave_sync_lds();
-    if (ok) { L.q2b[wv][pos] = b; L.q2c[wv][pos] = cp; L.q2t[wv][pos] = tg; }
-    q2n += __popcll(m);
-    if (q2n >= 64) ls_flush3(a, L, wv, lane, wbase, 64, q2n, outn);
-    wave_sync_lds();
-}
-
-// Stage a round of trimmed runs [rbeg, rbeg + kLsRunsPerRound) of each lane's
-// anchor into LDS; returns the number of non-empty ranges of this lane and
-// adds their candidates to *cands.
+// Stage the trimmed MD ranges of runs [rbeg, rbeg + kLsRunsPerRound) of each
+// lane's anchor in LDS, two runs at a time (their records, then their four
+// module offsets, in flight together); returns the number of non-empty
+// ranges of this lane and adds their candidates to *cands.
 __device__ __forceinline__ int ls_stage_round(const LsArgs &a, LsLds &L, int wv, int lane, LsAnchor &s, bool act,
                                               int rbeg, int rmax, int &cands) {
     int nr = 0;
-    for (int r = rbeg; r < rbeg + kLsRunsPerRound && r < rmax; ++r) {
-        int2 g = make_int2(0, 0);
-        if (act && s.r0 + r < s.r1) g = ls_run_range(a, s, s.r0 + r);
-        if (g.y > g.x) {
-            L.rng[wv][nr][lane] = g;
-            cands += g.y - g.x;
+    const int last = s.r1 - 1 >= s.r0 ? s.r1 - 1 : s.r0;   // clamped run index (valid: the table is never empty)
+    for (int r = rbeg; r < rbeg + kLsRunsPerRound && r < rmax; r += 2) {
+        const bool h0 = act && s.r0 + r < s.r1, h1 = act && s.r0 + r + 1 < s.r1;
+        const int k0 = s.r0 + r < last ? s.r0 + r : last;
+        const int k1 = s.r0 + r + 1 < last ? s.r0 + r + 1 : last;
+        const RunRec ra = a.g.runs[k0], rb = a.g.runs[k1];
+        int2 ta = make_int2(0, -1), tb = make_int2(0, -1);
+        if (h0) ta = ls_run_trim(a.p, s, ra);
+        if (h1) tb = ls_run_trim(a.p, s, rb);
+        const int64_t ea = s.ebase + ra.t_first, eb = s.ebase + rb.t_first;
+        const int64_t ia0 = ta.y >= ta.x ? ea + ta.x : s.ebase, ia1 = ta.y >= ta.x ? ea + ta.y + 1 : s.ebase;
+        const int64_t ib0 = tb.y >= tb.x ? eb + tb.x : s.ebase, ib1 = tb.y >= tb.x ? eb + tb.y + 1 : s.ebase;
+        const int ja = (int)a.md_mod_off[ia0], jae = (int)a.md_mod_off[ia1];
+        const int jb = (int)a.md_mod_off[ib0], jbe = (int)a.md_mod_off[ib1];
+        if (jae > ja) {
+            L.rng[wv][nr][lane] = make_int2(ja, jae);
+            cands += jae - ja;
+            ++nr;
+        }
+        if (jbe > jb) {
+            L.rng[wv][nr][lane] = make_int2(jb, jbe);
+            cands += jbe - jb;
             ++nr;
         }
     }
     return nr;
 }
+
+// A lane's walk over its staged ranges: next() returns the next candidate
+// index and whether there is one.
+struct LsCursor {
+    int ri, nr, j, je;
+    bool on;
+    __device__ __forceinline__ void start(const LsLds &L, int wv, int lane, int n) {
+        ri = 0;
+        nr = n;
+        on = n > 0;
+        j = je = 0;
+        if (on) { const int2 g = L.rng[wv][0][lane]; j = g.x; je = g.y; }
+    }
+    __device__ __forceinline__ bool next(const LsLds &L, int wv, int lane, int &b) {
+        if (!on) return false;
+        b = j++;
+        if (j >= je) {
+            if (++ri < nr) { const int2 g = L.rng[wv][ri][lane]; j = g.x; je = g.y; }
+            else on = false;
+        }
+        return true;
+    }
+};
 
 __global__ __launch_bounds__(kBlock) void k_ls_eval(LsArgs a) {
     __shared__ LsLds L;
@@ -1292,10 +1291,10 @@ __global__ __launch_bounds__(kBlock) void k_ls_eval(LsArgs a) {
         if (w >= nwaves) continue;             // wavefront-uniform
         const int64_t wbase = w * 64, A = wbase + lane;
         const bool act = A < n_md;
-        const int64_t a_safe = act ? A : n_md - 1;
+        const int a_safe = (int)(act ? A : n_md - 1);
         LsAnchor s = ls_anchor(a, a_safe);
         L.cnt[wv][lane] = 0;
-        int q1n = 0, q2n = 0, outn = 0, cands = 0;
+        int qn = 0, outn = 0, cands = 0;
         // runs of the wavefront's longest map row
         int nrun = act ? s.r1 - s.r0 : 0;
 #pragma unroll
@@ -1308,47 +1307,49 @@ __global__ __launch_bounds__(kBlock) void k_ls_eval(LsArgs a) {
         for (int rbeg = 0; rbeg < nrun; rbeg += kLsRunsPerRound) {
             const int nr = ls_stage_round(a, L, wv, lane, s, act, rbeg, nrun, cands);
             wave_sync_lds();
-            int ri = 0, j = 0, je = 0;
-            bool on = nr > 0;
-            if (on) { const int2 g = L.rng[wv][0][lane]; j = g.x; je = g.y; }
-            // the next candidate's records are loaded one step ahead
-            int jn = on ? j : (int)a_safe;
-            float4 nb = a.md_a[jn];
-            float2 nq = a.md_rq[jn];
-            while (__ballot(on) != 0ull) {
-                const bool cur = on;
-                const int b = j;
-                const float4 PB = nb;
-                const float2 qb = nq;
-                if (on) {
-                    ++j;
-                    if (j >= je) {
-                        ++ri;
-                        if (ri < nr) { const int2 g = L.rng[wv][ri][lane]; j = g.x; je = g.y; }
-                        else on = false;
-                    }
-                }
-                jn = on ? j : (int)a_safe;
-                nb = a.md_a[jn];
-                nq = a.md_rq[jn];
-                bool pass = false;
-                float c = 0.0f, sg = 0.0f;
-                if (cur && ls_zpass(s, PB.z, qb))
-                    pass = pair_curv_pass(a.p, PA, qa, P3{PB.x, PB.y, PB.z}, qb, c, sg);
+            LsCursor cu;
+            cu.start(L, wv, lane, nr);
+            // Two register sets take alternate candidates; a set is reloaded
+            // right after its candidate is evaluated, so every load has the
+            // other set's evaluation to complete in (no register of a load in
+            // flight is copied).
+            int bA = a_safe, bB = a_safe;
+            bool vA = cu.next(L, wv, lane, bA);
+            float4 PBa = a.md_a[bA];
+            float2 QBa = a.md_rq[bA];
+            bool vB = cu.next(L, wv, lane, bB);
+            float4 PBb = a.md_a[bB];
+            float2 QBb = a.md_rq[bB];
+            auto step = [&](bool v, int b, const float4 &PB, const float2 &QB) {
+                float cp = 0.0f;
+                int tag = 0;
+                const bool pass = v && ls_pair(a.p, s, PA, qa, PB, QB, lane, cp, tag);
                 const unsigned long long m = __ballot(pass);
                 if (pass) {
-                    const int pos = q1n + __popcll(m & lanes_below(lane));
-                    L.q1b[wv][pos] = b;
-                    L.q1c[wv][pos] = c;
-                    L.q1t[wv][pos] = lane | (sg > 0.0f ? kTagPos : 0);
+                    const int pos = qn + __popcll(m & lanes_below(lane));
+                    L.qb[wv][pos] = b;
+                    L.qc[wv][pos] = cp;
+                    L.qt[wv][pos] = tag;
                 }
-                q1n += __popcll(m);
-                if (q1n >= 64) ls_flush2(a, L, wv, lane, wbase, 64, q1n, q2n, outn);
+                qn += __popcll(m);
+                if (qn >= 64) ls_flush(a, L, wv, lane, wbase, 64, qn, outn);
+            };
+            while (__ballot(vA) != 0ull) {
+                step(vA, bA, PBa, QBa);
+                bA = a_safe;
+                vA = cu.next(L, wv, lane, bA);
+                PBa = a.md_a[bA];
+                QBa = a.md_rq[bA];
+                if (__ballot(vB) == 0ull) break;
+                step(vB, bB, PBb, QBb);
+                bB = a_safe;
+                vB = cu.next(L, wv, lane, bB);
+                PBb = a.md_a[bB];
+                QBb = a.md_rq[bB];
             }
         }
-        // drain the queues
-        if (q1n > 0) ls_flush2(a, L, wv, lane, wbase, q1n, q1n, q2n, outn);
-        while (q2n > 0) ls_flush3(a, L, wv, lane, wbase, q2n < 64 ? q2n : 64, q2n, outn);
+        // drain the queue
+        while (qn > 0) ls_flush(a, L, wv, lane, wbase, qn < 64 ? qn : 64, qn, outn);
         wave_sync_lds();
         // per-A counts, the wavefront's prefix over them, and its chunk
         const int c = act ? L.cnt[wv][lane] : 0;
@@ -1390,25 +1391,29 @@ __global__ __launch_bounds__(kBlock) void k_ls_eval(LsArgs a) {
 
 // One A per lane, every candidate in order with all cuts, writing LS to
 // ls_md[k..] (the recompute path of a wavefront whose survivors overflowed
-// its list; identical cut code, so identical results).
+// its list; the same trimming and cut code, so the same results).
 __device__ void ls_recompute(const LsArgs &a, int64_t A, int64_t k, int2 *ls_md, int64_t cap_ls) {
     LsAnchor s = ls_anchor(a, A);
     const P3 PA{s.x, s.y, s.z};
     const float2 qa = make_float2(s.r, s.end ? -s.q : s.q);
-    const float2 oa = a.md_o[A];
     for (int32_t r = s.r0; r < s.r1; ++r) {
-        const int2 g = ls_run_range(a, s, r);
-        for (int b = g.x; b < g.y; ++b) {
+        const RunRec rr = a.g.runs[r];
+        const int2 t = ls_run_trim(a.p, s, rr);
+        if (t.y < t.x) continue;
+        const int64_t e0 = s.ebase + rr.t_first;
+        const int j0 = (int)a.md_mod_off[e0 + t.x], j1 = (int)a.md_mod_off[e0 + t.y + 1];
+        for (int b = j0; b < j1; ++b) {
             const float4 PB = a.md_a[b];
             const float2 qb = a.md_rq[b];
-            if (!ls_zpass(s, PB.z, qb)) continue;
-            float c, sg;
-            if (!pair_curv_pass(a.p, PA, qa, P3{PB.x, PB.y, PB.z}, qb, c, sg)) continue;
-            const float cp = fminf(c, a.p.cmax);
-            if (!pair_z0_pass(a.p, PA, qa, P3{PB.x, PB.y, PB.z}, qb, cp)) continue;
-            const float sgn = sg > 0.0f ? 1.0f : -1.0f;
-            if (!s.end && !md_dir_pass(a.p, PA, oa.x, oa.y, cp, sgn)) continue;
-            if (!signbit(qb.y)) {
+            float cp;
+            int tag;
+            if (!ls_pair(a.p, s, PA, qa, PB, qb, 0, cp, tag)) continue;
+            const float sgn = (tag & kTagPos) ? 1.0f : -1.0f;
+            if (tag & kTagDirA) {
+                const float2 oa = a.md_o[A];
+                if (!md_dir_pass(a.p, PA, oa.x, oa.y, cp, sgn)) continue;
+            }
+            if (tag & kTagDirB) {
                 const float2 ob = a.md_o[b];
                 if (!md_dir_pass(a.p, P3{PB.x, PB.y, PB.z}, ob.x, ob.y, cp, sgn)) continue;
             }
@@ -1775,10 +1780,6 @@ __global__ __launch_bounds__(64) void k_event_offsets(const int64_t *md_mod_off,
 struct GmKey {
     const float4 *md_a;
     __device__ int operator()(int64_t i) const { return __float_as_int(md_a[i].w); }
-};
-struct LsInKey {
-    const int2 *ls;
-    __device__ int operator()(int64_t i) const { return ls[i].x; }
 };
 struct T3InKey {
     const int4 *t;

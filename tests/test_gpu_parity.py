@@ -310,7 +310,8 @@ def test_autotune_keeps_results(geo_f, mdl):
     ref = b.build(dx, dy, dz, ds, event_offsets=doff).to_host()
     run = lambda: b.launch(dx, dy, dz, ds, event_offsets=doff)
     best, table = autotune(b, run, torch.cuda.synchronize, reps=1, log=_say)
-    assert len(table) == 7
+    from paper_2403_13166_amd.autotune import KNOBS
+    assert len(table) == len(KNOBS)
     B.lst_set_tuning(b.ctx, best)
     got = b.build(dx, dy, dz, ds, event_offsets=doff).to_host()
     for k in ("md_hits", "ls_md", "t3_ls", "t5_t3", "t5_score"):

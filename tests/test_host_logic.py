@@ -36,9 +36,9 @@ def test_autotune_search_with_fake_context(monkeypatch):
 
     def fake_times(ctx):
         t = state["tuning"]
-        # LS fastest at 8, binning fastest at 64, eval grid fastest at 2048; others flat
+        # T5 pre-cuts fastest at 4, binning fastest at 64, eval grid fastest at 2048; others flat
         return {"build": 1.0 + abs(t["eval_blocks"] - 2048) / 8192, "bin": 0.5 - 0.001 * t["bin_split"],
-                "md": 0.1, "ls": 1.0 / t["tile_per"][1], "t3": 0.05, "t5": 0.7, "score": 0.2}
+                "md": 0.1, "ls": 1.0, "t3": 0.05, "t5": 1.0 / t["tile_per"][3], "score": 0.2}
 
     monkeypatch.setattr(B, "lst_set_timing", lambda ctx, on: state.update(timing=on))
     monkeypatch.setattr(B, "lst_get_tuning", lambda ctx: {k: (list(v) if isinstance(v, list) else v)
@@ -53,8 +53,9 @@ def test_autotune_search_with_fake_context(monkeypatch):
             return [10, 20, 30, 40, 0, 0, 0, 0]
 
     best, table = AT.autotune(FakeBuilder(), lambda: None, lambda: None, reps=1)
-    assert best["tile_per"][1] == 8 and best["bin_split"] == 64 and best["eval_blocks"] == 2048
+    assert best["tile_per"][3] == 4 and best["bin_split"] == 64 and best["eval_blocks"] == 2048
     assert best["tile_per"][0] == 4                     # flat timings: no move without a clear gain
+    assert best["tile_per"][1] == 4                     # the line-segment stage has no tiles: not searched
     assert len(table) == len(AT.KNOBS) and state["tuning"] == best
 
     class ChangingBuilder(FakeBuilder):
