@@ -187,6 +187,16 @@ lst_status lst_score(lst_ctx *ctx, const void *X_dev, int32_t x_dtype, int64_t n
  * reads). The caller synchronises the stream first; LST_E_STATE if timing
  * was never enabled. */
 lst_status lst_set_timing(lst_ctx *ctx, int32_t enable);
+
+/* Failure injection, for testing how callers handle a failed build (no paper
+ * passage: the paper describes no error handling). With stage k in 1..6
+ * (1 hit binning, 2 MD, 3 LS, 4 T3, 5 T5, 6 T5-DNN scoring), every build call
+ * on ctx enqueues only the stages before k, synchronises its stream and
+ * returns LST_E_HIP with the stage in lst_last_error; outputs and counts are
+ * then undefined, and the context stays usable. 0 turns it off. The
+ * environment variable LST_FAIL_AT_STAGE=k sets it for every context created
+ * afterwards. LST_E_INVAL for k outside [0, 6]. */
+lst_status lst_set_fail_stage(lst_ctx *ctx, int32_t stage);
 lst_status lst_stage_times(lst_ctx *ctx, float *ms, int32_t n);
 
 /* Edge classifier on a graph of LST objects (the GNN proposed in Sec. 4:

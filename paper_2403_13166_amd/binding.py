@@ -34,7 +34,8 @@ N_FEATURES = 42
 
 EXPORTED = ("lst_create", "lst_destroy", "lst_load_geometry", "lst_load_model", "lst_workspace_size",
             "lst_build_objects", "lst_build_objects_noalloc", "lst_build_objects_batched", "lst_score", "lst_status_string",
-            "lst_last_error", "lst_set_timing", "lst_stage_times", "lst_get_tuning", "lst_set_tuning",
+            "lst_last_error", "lst_set_timing", "lst_set_fail_stage", "lst_stage_times", "lst_get_tuning",
+            "lst_set_tuning",
             "lst_load_gnn", "lst_gnn_workspace_size", "lst_gnn_score")
 
 
@@ -118,6 +119,8 @@ def lib():
         L.lst_score.restype = i32
         L.lst_set_timing.argtypes = [vp, i32]
         L.lst_set_timing.restype = i32
+        L.lst_set_fail_stage.argtypes = [vp, i32]
+        L.lst_set_fail_stage.restype = i32
         L.lst_stage_times.argtypes = [vp, vp, i32]
         L.lst_stage_times.restype = i32
         L.lst_load_gnn.argtypes = [vp, C.c_char_p, C.c_size_t]
@@ -208,6 +211,14 @@ STAGE_WINDOWS = ("build", "bin", "md", "ls", "t3", "t5", "score", "md_all", "ls_
 
 def lst_set_timing(ctx, enable: bool) -> None:
     _check(ctx, lib().lst_set_timing(ctx, int(bool(enable))), "lst_set_timing")
+
+
+# stages of the build that failure injection can stop before (0: off)
+FAIL_STAGES = ("off", "bin", "md", "ls", "t3", "t5", "score")
+
+
+def lst_set_fail_stage(ctx, stage: int) -> None:
+    _check(ctx, lib().lst_set_fail_stage(ctx, int(stage)), "lst_set_fail_stage")
 
 
 def lst_stage_times(ctx) -> dict:

@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -70,6 +71,8 @@ struct lst_ctx {
     GnnDev gnn{};
     // this device's address of the static scratch of lst_build_objects_noalloc
     void *noalloc_ws = nullptr;
+    // failure injection: builds stop before this pipeline stage and fail (0: off)
+    int32_t fail_stage = 0;
 };
 
 static lst_status fail(lst_ctx *c, lst_status s, const char *fmt, ...) {
@@ -115,6 +118,10 @@ lst_status lst_create(int device, lst_ctx **out) {
     if (hipSetDevice(device) != hipSuccess) return LST_E_HIP;
     lst_ctx *c = new lst_ctx();
     c->device = device;
+    if (const char *fs = getenv("LST_FAIL_AT_STAGE")) {
+        const int k = atoi(fs);
+        c->fail_stage = k >= 1 && k <= kFailStages ? k : 0;
+    }
     if (scratch_address(device, &c->noalloc_ws) != hipSuccess) {
         delete c;
         return LST_E_HIP;
@@ -329,11 +336,18 @@ static lst_status build_common(lst_ctx *c, const lst_hits *h, const int64_t *ev_
     a.ev_obj_off = ev_obj_off;
     a.timing = c->timing ? c->tev : nullptr;
     a.tune = c->tune;
+    a.stop_before = c->fail_stage;
     Outputs o{};
     o.md_hits = (int2 *)out->md_hits; o.ls_md = (int2 *)out->ls_md; o.t3_ls = (int2 *)out->t3_ls;
     o.t5_t3 = (int2 *)out->t5_t3; o.t5_score = out->t5_score; o.t5_chi2_rphi = out->t5_chi2_rphi;
     o.t5_chi2_rz = out->t5_chi2_rz; o.t5_feat = out->t5_feat; o.counts = out->counts_dev;
     HIP_TRY(c, run_pipeline(a, w, o, st));
+    if (c->fail_stage) {
+        // the stages before it ran; leave the stream idle before reporting
+        HIP_TRY(c, hipStreamSynchronize(st));
+        return fail(c, LST_E_HIP, "injected failure before pipeline stage %d (failure injection is on)",
+                    c->fail_stage);
+    }
     if (opt->flags & LST_ASYNC) return LST_OK;
     int64_t cnt[LST_COUNTS_LEN];
     HIP_TRY(c, hipMemcpyAsync(cnt, out->counts_dev, sizeof(cnt), hipMemcpyDeviceToHost, st));
@@ -377,6 +391,13 @@ lst_status lst_build_objects_noalloc(lst_ctx *c, const lst_hits *h, const lst_op
                     need, kNoAllocScratchBytes);
     if (!c->noalloc_ws) return fail(c, LST_E_STATE, "no static scratch address on this device");
     return build_common(c, h, nullptr, 1, opt, k, out, nullptr, c->noalloc_ws, kNoAllocScratchBytes, stream, true);
+}
+
+lst_status lst_set_fail_stage(lst_ctx *c, int32_t stage) {
+    if (!c) return LST_E_INVAL;
+    if (stage < 0 || stage > kFailStages) return fail(c, LST_E_INVAL, "fail stage %d outside [0, %d]", stage, kFailStages);
+    c->fail_stage = stage;
+    return LST_OK;
 }
 
 lst_status lst_set_timing(lst_ctx *c, int32_t enable) {

@@ -103,7 +103,12 @@ struct RunArgs {
     int64_t *ev_obj_off;              // device [4][n_ev + 1] or null
     hipEvent_t *timing;               // null, or kTimingEvents events recorded around the stages
     Tuning tune;
+    int32_t stop_before;              // 1..kFailStages: enqueue only the stages before this one
 };
+
+// Pipeline stages for failure injection: 1 hit binning, 2 MD, 3 LS, 4 T3,
+// 5 T5, 6 T5-DNN scoring.
+constexpr int32_t kFailStages = 6;
 
 // Timing windows (pairs of events): 0 whole build, 1 binning, 2 MD, 3 LS,
 // 4 T3 (2-4: the stage's eval kernel alone), 5 T5 compaction kernels, 6 T5

@@ -1799,6 +1799,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     hipEvent_t *ev = a.timing;
     mark(ev, 0, st);
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, cnt, (int64_t)LST_COUNTS_LEN, (int64_t)0);
+    if (a.stop_before == 1) return hipGetLastError();
     // a1: bin hits by (event, sensor)
     mark(ev, 2, st);
     {
@@ -1821,6 +1822,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     }
     mark(ev, 3, st);
 
+    if (a.stop_before == 2) return hipGetLastError();
     // a2: mini-doublets, anchored on (event, module)
     MDStage md{w.bin_off, w.bin_hit, a.g.mod, a.g.box, o.counts, a.p, n_mod, n_sens, o.md_hits, w.md_a, w.md_o,
                w.md_rq};
@@ -1830,6 +1832,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
                        cnt + LST_COUNT_MD, w.cap_md, nullptr, ngm, w.md_mod_off);
     mark(ev, 15, st);
 
+    if (a.stop_before == 3) return hipGetLastError();
     // a3: line segments, one inner MD per lane over the trimmed runs of its
     // module-map row; CSR offsets by inner MD from the per-MD counts
     mark(ev, 16, st);
@@ -1849,6 +1852,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     }
     mark(ev, 17, st);
 
+    if (a.stop_before == 4) return hipGetLastError();
     // a4: triplets, anchored on the inner LS
     T3Stage t3{o.ls_md, w.ls_off, w.cap_ls, w.md_a, w.md_o, w.md_rq, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
     mark(ev, 18, st);
@@ -1857,6 +1861,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
                        cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w.t3i_off);
     mark(ev, 19, st);
 
+    if (a.stop_before == 5) return hipGetLastError();
     // a5: quintuplets, anchored on the inner T3: FP32 beam-line cuts, then the
     // FP64 fits on the dense list of pre-candidates
     const bool score_cut = a.mode == 0 && a.score_min == a.score_min;
@@ -1874,6 +1879,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     }
     mark(ev, 11, st);
 
+    if (a.stop_before == 6) return hipGetLastError();
     // a6: features and T5-DNN scores (BF16 MFMA runs over the feature rows;
     // a score cut forces the FP32 path, which the T5 stage itself applied)
     bool mfma = a.mode == 0 && a.precision == 1 && !score_cut;

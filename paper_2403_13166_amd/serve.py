@@ -18,6 +18,10 @@ Sec. 3; this loop is the serving form of that):
     are on the GPU overlap with them on the device.
   * A request is finished when its objects are in host memory; latency is
     finish - arrival.
+  * A batch whose launch, completion or read-back raises is isolated: its
+    slot is freed at once and, if it held several requests, each is run
+    again alone ahead of the queue; a request that fails alone is reported
+    failed and the stream goes on.
 
 The scheduler (`run_loop`) is host logic that talks to an executor through
 launch / poll / finish, so it is tested on the CPU with a simulated executor
@@ -28,7 +32,7 @@ from __future__ import annotations
 import ctypes
 import time
 from collections import deque
-from dataclasses import dataclass
+from dataclasses import asdict, dataclass
 
 import numpy as np
 
@@ -53,6 +57,14 @@ class Done:
     @property
     def latency(self) -> float:
         return self.finished - self.arrival
+
+
+@dataclass
+class Failed:
+    idx: int
+    arrival: float
+    failed: float
+    error: str
 
 
 class Admission:
@@ -95,17 +107,30 @@ def run_loop(requests, executor, admission: Admission | None = None, clock=time.
     """Serve `requests` (sorted by arrival) on executor.n_slots slots. With
     `admission` every slot admits by those limits; without, each slot by its
     own (executor.slot_limits) and choose_slot picks the slot.
-    Returns (done list in finishing order, stats dict)."""
+    Returns (done list in finishing order, stats dict); stats["failed"] lists
+    the requests that failed alone (Failed records as dicts)."""
     reqs = sorted(requests, key=lambda r: (r.arrival, r.idx))
     nxt = 0
     queue = deque()
+    solo = deque()                        # requests of failed batches, each to run alone
     free = list(range(executor.n_slots))[::-1]
     inflight = {}                         # slot -> (handle, batch, admitted, batch id)
-    done, batches = [], []
+    done, batches, failed = [], [], []
     n_batch = 0
     max_inflight = 0
     t0 = clock()
-    while nxt < len(reqs) or queue or inflight:
+
+    def batch_failed(slot, batch, err):
+        reset = getattr(executor, "reset", None)
+        if reset is not None:
+            reset(slot)
+        free.append(slot)
+        if len(batch) > 1:
+            solo.extend(batch)
+        else:
+            failed.append(Failed(batch[0].idx, batch[0].arrival, clock() - t0, repr(err)))
+
+    while nxt < len(reqs) or queue or solo or inflight:
         now = clock() - t0
         while nxt < len(reqs) and reqs[nxt].arrival <= now:
             queue.append(reqs[nxt])
@@ -113,16 +138,29 @@ def run_loop(requests, executor, admission: Admission | None = None, clock=time.
         progressed = False
         for slot in list(inflight):
             h, batch, t_adm, bid = inflight[slot]
-            if executor.poll(h):
-                t_fin = clock() - t0
-                executor.finish(h)
+            try:
+                ready = executor.poll(h)
+                if ready:
+                    t_fin = clock() - t0
+                    executor.finish(h)
+            except Exception as err:          # noqa: BLE001 - isolate any failure of the batch
+                del inflight[slot]
+                batch_failed(slot, batch, err)
+                progressed = True
+                continue
+            if ready:
                 for r in batch:
                     done.append(Done(r.idx, r.arrival, t_adm, t_fin, bid, slot))
                 del inflight[slot]
                 free.append(slot)
                 progressed = True
-        while free and queue:
-            if admission is not None:
+        while free and (queue or solo):
+            if solo:
+                slot = free.pop() if admission is not None else choose_slot(free, 1, executor.slot_limits)
+                if admission is None:
+                    free.remove(slot)
+                batch = [solo.popleft()]
+            elif admission is not None:
                 slot = free.pop()
                 batch = admission.take(queue)
             else:
@@ -132,12 +170,16 @@ def run_loop(requests, executor, admission: Admission | None = None, clock=time.
                 free.remove(slot)
                 batch = Admission(*executor.slot_limits(slot)).take(queue)
             t_adm = clock() - t0
-            h = executor.launch(slot, batch)
+            progressed = True
+            try:
+                h = executor.launch(slot, batch)
+            except Exception as err:          # noqa: BLE001
+                batch_failed(slot, batch, err)
+                continue
             inflight[slot] = (h, batch, t_adm, n_batch)
             batches.append(len(batch))
             n_batch += 1
             max_inflight = max(max_inflight, len(inflight))
-            progressed = True
         if not progressed:
             wait = idle_poll
             if not inflight and not queue and nxt < len(reqs):
@@ -149,7 +191,8 @@ def run_loop(requests, executor, admission: Admission | None = None, clock=time.
              "events_per_s": len(done) / span if span > 0 else float("nan"),
              "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
              "mean_batch": float(np.mean(batches)) if batches else 0.0,
-             "max_batch": int(max(batches)) if batches else 0, "max_inflight": max_inflight}
+             "max_batch": int(max(batches)) if batches else 0, "max_inflight": max_inflight,
+             "failed": [asdict(f) for f in failed]}
     return done, stats
 
 
@@ -250,7 +293,9 @@ class _Slot:
         self.stream.synchronize()
         self.graph = g
 
-    def launch(self, batch):
+    def launch(self, batch, fail_stage: int = 0):
+        """Enqueue the batch; with fail_stage > 0 the build is run eagerly with
+        failure injection before that stage and raises."""
         torch = self.torch
         hits = sum(r.n_hits for r in batch)
         if hits > self.caps.hits or len(batch) > self.caps.events:
@@ -279,7 +324,14 @@ class _Slot:
                 ho[i + 1] = off
             ho[len(batch) + 1:] = off
             self.doff.copy_(self.h_off, non_blocking=True)
-            if self.graph is not None:
+            if fail_stage:
+                from . import binding as B
+                B.lst_set_fail_stage(self.b.ctx, fail_stage)
+                try:
+                    self._launch_build()
+                finally:
+                    B.lst_set_fail_stage(self.b.ctx, 0)
+            elif self.graph is not None:
                 self.graph.replay()
             else:
                 self._launch_build()
@@ -313,6 +365,10 @@ class _Slot:
         self.h_counts.copy_(buf["counts"])
         ne = self.caps.events + 1
         self.h_evobj.view(-1).copy_(buf["ev_obj"].view(-1)[:4 * ne])
+
+    def reset(self):
+        """After a failed batch: wait for the slot's stream to drain."""
+        self.stream.synchronize()
 
     def poll(self, h) -> bool:
         torch = self.torch
@@ -359,7 +415,9 @@ class _Slot:
 
 class GpuExecutor:
     """Slots on one GPU; `keep_results` stores every request's objects
-    (event-local indices) in `self.results[idx]`."""
+    (event-local indices) in `self.results[idx]`. `inject` maps request ids
+    to a pipeline stage (1..6): a batch holding such a request is built with
+    the library's failure injection before that stage, so it fails."""
 
     def __init__(self, geometry_blob: bytes, model_blob: bytes, n_slots: int, caps, mode: int = 0,
                  precision: int = 1, device: int = 0, use_graph: bool = True, keep_results: bool = False):
@@ -371,6 +429,7 @@ class GpuExecutor:
         self.n_slots = n_slots
         self.keep_results = keep_results
         self.results = {}
+        self.inject = {}
 
     def slot_bytes(self) -> int:
         return max(s.nbytes() for s in self.slots)
@@ -392,9 +451,13 @@ class GpuExecutor:
             self.finish(h)
 
     def launch(self, slot: int, batch):
-        h = self.slots[slot].launch(batch)
+        stage = max((self.inject.get(r.idx, 0) for r in batch), default=0)
+        h = self.slots[slot].launch(batch, stage)
         h["slot"] = slot
         return h
+
+    def reset(self, slot: int):
+        self.slots[slot].reset()
 
     def poll(self, h) -> bool:
         return self.slots[h["slot"]].poll(h)

@@ -67,3 +67,47 @@ def test_api_errors():
             assert isinstance(B.lst_status_string(st), str) and B.lst_status_string(st)
     finally:
         B.lst_destroy(ctx)
+
+
+def test_failure_injection_per_stage(monkeypatch):
+    """Each pipeline stage can be made to fail from the host: the build
+    returns LST_E_HIP naming the stage, and the context then builds the same
+    objects as before."""
+    from paper_2403_13166_amd import binding as B
+    from paper_2403_13166_amd.runtime import Builder, to_device
+    from paper_2403_13166_amd.synth import events as E
+    geo = G.make_geometry(False)
+    b = Builder(geo.to_blob(), M.make_model().to_blob(), 0)
+    try:
+        ev = E.make_event(geo, E.SMALL_BARREL, (0, 1))
+        d = to_device(ev, b.device)
+        cnt = lambda o: (len(o.md_hits), len(o.ls_md), len(o.t3_ls), len(o.t5_t3))
+        ref = b.build(*d).to_host()
+        assert cnt(ref)[1] > 0
+        for k in range(1, 7):
+            print("inject before stage", k, flush=True)
+            B.lst_set_fail_stage(b.ctx, k)
+            with pytest.raises(B.LstError) as e:
+                b.build(*d)
+            assert e.value.status == B.LST_E_HIP and f"stage {k}" in str(e.value)
+            B.lst_set_fail_stage(b.ctx, 0)
+            again = b.build(*d).to_host()
+            assert cnt(again) == cnt(ref)
+            assert np.array_equal(again.ls_md, ref.ls_md) and np.array_equal(again.t5_t3, ref.t5_t3)
+        with pytest.raises(B.LstError) as e:
+            B.lst_set_fail_stage(b.ctx, 7)
+        assert e.value.status == B.LST_E_INVAL
+    finally:
+        b.close()
+    # the environment switch applies to contexts created while it is set
+    monkeypatch.setenv("LST_FAIL_AT_STAGE", "4")
+    b2 = Builder(geo.to_blob(), M.make_model().to_blob(), 0)
+    monkeypatch.delenv("LST_FAIL_AT_STAGE")
+    try:
+        with pytest.raises(B.LstError) as e:
+            b2.build(*d)
+        assert "stage 4" in str(e.value)
+        B.lst_set_fail_stage(b2.ctx, 0)
+        assert cnt(b2.build(*d).to_host()) == cnt(ref)
+    finally:
+        b2.close()

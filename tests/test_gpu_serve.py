@@ -122,6 +122,39 @@ def test_served_capacity_overflow_recovers(setup):
     ex.close()
 
 
+@pytest.mark.parametrize("stage", [3, 6])
+def test_injected_failure_is_isolated(setup, stage):
+    """A request whose build fails (failure injection before the LS stage, or
+    before the scoring) fails alone: its batch mates are rebuilt one by one
+    and equal their builds alone, and the slots keep serving."""
+    from paper_2403_13166_amd.serve import Admission, GpuExecutor, Request, pinned_event, run_loop, slot_caps
+    geo, mdl, pool = setup
+    ref = _alone(geo, mdl, pool, 1)
+    cap = sum(e.n for e in pool)
+    _say("serve with injected failure before stage", stage)
+    ex = GpuExecutor(geo.to_blob(), mdl.to_blob(), 2, slot_caps(cap, 4), precision=1, use_graph=True,
+                     keep_results=True)
+    ex.inject = {2: stage}
+    pins = [pinned_event(e) for e in pool]
+    reqs = [Request(i, 0.0 if i < 4 else 0.003, pool[i].n, pins[i]) for i in range(len(pool))]
+    done, st = run_loop(reqs, ex, Admission(cap, 4))
+    _say("stats", {k: v for k, v in st.items() if k != "failed"}, "failed", st["failed"])
+    assert [f["idx"] for f in st["failed"]] == [2]
+    assert f"stage {stage}" in st["failed"][0]["error"]
+    assert sorted(d.idx for d in done) == [i for i in range(len(pool)) if i != 2]
+    for i in range(len(pool)):
+        if i != 2:
+            _check(ex.results[i], ref[i], f"request {i} next to a failed one")
+    # the slots still serve, the failed event included once injection is off
+    ex.inject = {}
+    reqs2 = [Request(100 + i, 0.0, pool[i].n, pins[i]) for i in range(4)]
+    done2, st2 = run_loop(reqs2, ex, Admission(cap, 4))
+    assert st2["failed"] == [] and st2["events"] == 4
+    for i in range(4):
+        _check(ex.results[100 + i], ref[i], f"after the failure, request {i}")
+    ex.close()
+
+
 def test_served_equals_alone_at_serving_occupancy():
     """The serving workload's occupancy (PU ~ U[50, 200]: 30 tracks and 500
     noise hits per unit) on the benchmark's slot shapes, a single-event slot

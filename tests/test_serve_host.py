@@ -176,3 +176,65 @@ def test_heterogeneous_slots_light_and_heavy_load():
     assert sum(len(ids) for slot, ids, _ in ex.launched if slot == 0) <= 2
     for slot, ids, _ in ex.launched:
         assert len(ids) <= limits[slot][1] and len(ids) * 100_000 <= limits[slot][0] or len(ids) == 1
+
+
+class FailingExecutor(SimExecutor):
+    """Batches holding a request of `bad_launch` raise at launch; those
+    holding one of `bad_poll` raise when polled after their service time
+    (the device failed mid-build). Counts the resets of freed slots."""
+
+    def __init__(self, clock, n_slots, bad_launch=(), bad_poll=(), **kw):
+        super().__init__(clock, n_slots, **kw)
+        self.bad_launch, self.bad_poll = set(bad_launch), set(bad_poll)
+        self.resets = []
+
+    def launch(self, slot, batch):
+        if self.bad_launch & {r.idx for r in batch}:
+            raise RuntimeError("injected launch failure")
+        return super().launch(slot, batch)
+
+    def poll(self, h):
+        ready = super().poll(h)
+        if ready and self.bad_poll & {r.idx for r in h["batch"]}:
+            raise RuntimeError("injected device failure")
+        return ready
+
+    def reset(self, slot):
+        self.busy.discard(slot)
+        self.resets.append(slot)
+
+
+@pytest.mark.parametrize("where", ["launch", "poll"])
+def test_failed_request_is_isolated_and_its_slot_freed(where):
+    clk = Clock()
+    rng = np.random.default_rng(3)
+    n = 120
+    arr = np.concatenate([np.zeros(40), 0.05 + poisson_arrivals(400.0, n - 40, rng)])
+    bad = {7, 61}
+    kw = {"bad_launch": bad} if where == "launch" else {"bad_poll": bad}
+    ex = FailingExecutor(clk, n_slots=2, fixed=2e-3, per_hit=1e-8, **kw)
+    done, st = run_loop(_reqs(arr, [20_000] * n), ex, Admission(200_000, 8), clock=clk, sleep=clk.sleep)
+    # every other request is served exactly once; the bad ones fail alone
+    assert sorted(d.idx for d in done) == sorted(set(range(n)) - bad)
+    assert sorted(f["idx"] for f in st["failed"]) == sorted(bad)
+    assert all("injected" in f["error"] for f in st["failed"])
+    # a bad request's batch mates were retried, each in a batch of its own
+    # (request 7 arrives in the initial burst, so its first batch is shared)
+    if where == "poll":
+        for b in bad:
+            first = next(ids for _, ids, _ in ex.launched if b in ids)
+            assert len(first) > 1 or b != 7
+            for m in set(first) - {b}:
+                assert [ids for _, ids, _ in ex.launched if m in ids][-1] == [m]
+            assert [ids for _, ids, _ in ex.launched if b in ids][-1] == [b]
+    # every slot was freed after each failure and is idle at the end
+    assert not ex.busy
+    assert len(ex.resets) >= len(bad)
+    assert st["events"] == n - len(bad)
+
+
+def test_stream_goes_on_after_every_request_fails():
+    clk = Clock()
+    ex = FailingExecutor(clk, n_slots=2, bad_launch=set(range(10)))
+    done, st = run_loop(_reqs(np.zeros(10), [1000] * 10), ex, Admission(100_000, 4), clock=clk, sleep=clk.sleep)
+    assert done == [] and sorted(f["idx"] for f in st["failed"]) == list(range(10))
