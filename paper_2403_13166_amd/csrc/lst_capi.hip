@@ -263,8 +263,7 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     x.md_mod_off = (int64_t *)take(8 * (ev * nmod + 1));
     x.ls_off = (int64_t *)take(8 * (md + 1));
     x.ls_cnt = (int32_t *)take(4 * md);
-    x.ls_chunk = (int2 *)take(8 * (k->ls > 0 ? k->ls : 1));
-    x.ls_wave = (int64_t *)take(8 * (md / 64 + 2));
+    x.ls_chunk = (int4 *)take(16 * (k->ls > 0 ? k->ls : 1));
     x.ls_top = (unsigned long long *)take(8);
     x.t3_mds = (int4 *)take(16 * (k->t3 > 0 ? k->t3 : 1));
     x.t3i_off = (int64_t *)take(8 * (md + 1));

@@ -50,10 +50,10 @@ constexpr double kPi = 3.141592653589793;
 // Largest phi separation at which the line-segment stage trims a run: a pair
 // whose curvature passes the curvature cut lies either within the window
 // asin(c r_B) - asin(c r_A) of the near side of its circle, or beyond
-// pi - 2 asin(0.85) = 1.1096 rad on the far side (the device trims only while
-// c r_B < 0.85); runs that reach 1.10 rad from their source module are
+// pi - 2 asin(0.8) = 1.287 rad on the far side (the device trims only while
+// c r_B < 0.8); runs that reach 1.25 rad from their source module are
 // therefore never trimmed in phi.
-constexpr double kFarSidePhi = 1.10;
+constexpr double kFarSidePhi = 1.25;
 
 // Constants of one detector row, copied into every run of the row.
 struct RowConst {

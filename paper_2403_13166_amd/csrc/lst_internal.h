@@ -70,9 +70,8 @@ struct Work {
     // LS
     int64_t *ls_off;                  // [cap_md + 1] CSR by inner MD (exclusive scan of ls_cnt)
     int32_t *ls_cnt;                  // [cap_md] LS per inner MD
-    int2 *ls_chunk;                   // [cap_ls] (A, B) of each wavefront's segments before placement
-    int64_t *ls_wave;                 // [cap_md / 64 + 1] chunk start of each wavefront (-1: recompute)
-    unsigned long long *ls_top;       // [1] chunk allocator
+    int4 *ls_chunk;                   // [cap_ls] (A, B, rank of B among A's segments) before placement
+    unsigned long long *ls_top;       // [1] records written
     // T3
     int4 *t3_mds;                     // [cap_t3] MDs (A, B, C)
     int64_t *t3i_off;                 // [cap_md + 1] T3 by inner MD (they are sorted by it)

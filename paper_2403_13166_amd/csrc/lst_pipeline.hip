@@ -979,50 +979,60 @@ __global__ __launch_bounds__(kBlock) void k_fill_offsets(KF key, const int64_t *
 // event and module) and each lane walks its own candidates B, in ascending B,
 // so no candidate is ever decoded from a flat index. A's map row is stored as
 // runs (consecutive target modules of one detector row, adjacent in phi), and
-// every run is first trimmed for this A to the modules the cuts can accept:
+// for this A every run gets windows that contain every B the cuts can accept:
 //  * s ordering: LS2 needs s_B > s_A, i.e. r_B > r_A, so a run whose rows lie
 //    below r_A is skipped;
-//  * curvature: LS1 accepts c = |A x B| / (r_A r_B |B - A|) <= c_lim, and on a
-//    circle through the beam line with half-curvature c the points at radii
-//    r_A < r_B are asin(c r_B) - asin(c r_A) apart in phi; with |B - A| >=
-//    r_B,min - r_A and the largest resolution term of the row, this bounds
-//    |phi_B - phi_A| and keeps only the run's modules inside that window;
+//  * phi: on a circle through the beam line with signed half-curvature k the
+//    points at radii r_A < r_B are g(k, r_B) = asin(k r_B) - asin(k r_A) apart
+//    in phi, and g grows with k. LS1 bounds |k| by c_lim (with |B - A| >=
+//    r_B,min - r_A and the row's largest resolution term). For a barrel A,
+//    LS3 on A compares the MD's own chord direction alpha (angle from the
+//    radial direction at the chord midpoint M) with sgn asin(c' |M|),
+//    c' = min(c, c_max), so sgn c' lies in [sin(alpha - tol), sin(alpha +
+//    tol)] / |M|; when that interval reaches +-c_max the pair's k may run on
+//    to +-c_lim. The k interval maps to a phi window [g(k_lo), g(k_hi)] over
+//    the row's radii, which trims the run's modules and is tested on every B
+//    (two cross products with the window's edge directions);
 //  * z0, barrel to barrel: z_B = z_A + (z_A - z0) rho with
 //    rho = s_B / s_A - 1 between its values at c = 0 and c_max and
-//    |z0| <= z_lum + n_sigma sigma_z0, which bounds z_B; runs outside are
-//    skipped, and each candidate is tested against the same window.
+//    |z0| <= z_lum + n_sigma sigma_z0 bounds z_B; runs outside are skipped and
+//    every barrel B of the run is tested against the window.
 // Every bound is widened well beyond FP32 rounding, and anchors are known to
-// lie on their sensors (checked when MDs are written), so trimming never
-// removes a pair that the cuts would accept.
+// lie on their sensors (checked when MDs are written), so the windows never
+// remove a pair that the cuts would accept.
 //
-// Each lane applies LS1 and LS2 to its candidates as it walks them (the
-// record of the next one is already in flight); pairs passing both are
-// queued in LDS and LS3 runs on dense batches of 64 queue entries. A survivor
-// gets its rank among the survivors of its A (the queue keeps each A's
-// candidate order). At the end the wavefront knows its per-A counts, claims a
-// chunk of a scratch array with one atomic add, and writes its segments there
-// in (A, B) order. A scan of the per-A counts gives the CSR offsets of LS by
-// inner MD, and a placement kernel copies every wavefront's chunk to its
-// final position. A wavefront whose survivors do not fit its LDS list is
-// recomputed by the placement kernel, one A per lane, writing directly.
+// Candidates inside the windows are queued in LDS; LS1 and LS2 run on dense
+// batches of 64 queue entries (the anchor of each entry is shuffled from its
+// owner lane), and the pairs passing both are queued again for LS3, also run
+// on dense batches. The queues keep each A's candidate order, so an LS3
+// survivor gets its rank among the segments of its A. Survivors collect in an
+// LDS list that is written out, a few hundred at a time, as (A, B, rank)
+// records to a scratch array (one atomic add per write-out). A scan of the
+// per-A counts gives the CSR offsets of LS by inner MD, and a placement kernel
+// stores each record at offset[A] + rank.
 
 constexpr int kLsWaves = kBlock / 64;
-constexpr int kLsRunsPerRound = 6;      // trimmed runs staged per lane at a time (even)
-constexpr int kLsQCap = 128;            // LS3 queue entries per wavefront
-constexpr int kLsOutCap = 512;          // survivors kept per wavefront in LDS
-constexpr int kLsBlocks = 1280;         // persistent blocks of the eval and placement kernels
+constexpr int kLsRunsPerRound = 2;      // trimmed runs staged per lane at a time (even)
+constexpr int kLsQCap = 128;            // queue entries per wavefront (up to 63 waiting + 64 new)
+constexpr int kLsOutCap = 256;          // survivors held per wavefront before a write-out
+constexpr int kLsBlocks = 1280;         // persistent blocks of the eval kernel
+constexpr float kLsCrossMargin = 1e-3f; // cm: slack of the phi-window cross products
 // queue entry tag: bits 0-5 owner lane, 6 bends positive, 7 / 8 direction cut
 // on A / on B (barrel MDs)
 constexpr int kTagPos = 64, kTagDirA = 128, kTagDirB = 256;
 
 struct LsLds {
-    int2 rng[kLsWaves][kLsRunsPerRound][64];   // trimmed MD ranges [j, je) of each lane
-    int qb[kLsWaves][kLsQCap];                 // LS3 queue: B
-    float qc[kLsWaves][kLsQCap];               //            clamped curvature
-    int qt[kLsWaves][kLsQCap];                 //            tag
-    int ob[kLsWaves][kLsOutCap];               // survivors: B
-    int ot[kLsWaves][kLsOutCap];               // owner lane | rank among the owner's survivors << 6
-    int cnt[kLsWaves][64];                     // survivors per owner lane
+    int2 rng[kLsWaves][kLsRunsPerRound][64];     // trimmed MD ranges [j, je) of each lane
+    float4 win[kLsWaves][kLsRunsPerRound][64];   // their phi-window edge directions (all 0: no window)
+    float2 zw[kLsWaves][kLsRunsPerRound][64];    // their z windows
+    int pb[kLsWaves][kLsQCap];                   // window survivors: B
+    int po[kLsWaves][kLsQCap];                   //                   owner lane
+    int qb[kLsWaves][kLsQCap];                   // LS1 + LS2 survivors: B
+    float qc[kLsWaves][kLsQCap];                 //                      clamped curvature
+    int qt[kLsWaves][kLsQCap];                   //                      tag
+    int ob[kLsWaves][kLsOutCap];                 // LS3 survivors: B
+    int ot[kLsWaves][kLsOutCap];                 //                owner lane | rank << 6
+    int cnt[kLsWaves][64];                       // survivors per owner lane
 };
 
 struct LsArgs {
@@ -1033,10 +1043,9 @@ struct LsArgs {
     GeomDev g;
     CutParams p;
     int32_t *ls_cnt;                 // [cap_md] LS per inner MD
-    int2 *chunk;                     // [cap_chunk] (A, B) of every wavefront's segments
+    int4 *chunk;                     // [cap_chunk] (A, B, rank of B among A's segments, 0)
     int64_t cap_chunk;
-    int64_t *wave_base;              // [cap_md / 64 + 1] chunk start of each wavefront, -1: recompute
-    unsigned long long *top;         // chunk allocator (zeroed before the eval kernel)
+    unsigned long long *top;         // records written (zeroed before the eval kernel)
     int64_t *counts;
     int64_t cap_md;
 };
@@ -1044,12 +1053,12 @@ struct LsArgs {
 // The anchor MD of one lane.
 struct LsAnchor {
     float x, y, z, r, q, phi;   // q: resolution term |rq.y|; phi in [0, 2 pi)
+    float ux, uy;               // radial unit vector
+    float klo, khi;             // LS3 interval of sgn * min(c, c_max) (barrel, when hask)
     bool end;                   // endcap MD
+    bool hask, none;            // k interval in use; no B can pass (empty interval)
     int64_t ebase;              // event * n_mod
     int32_t r0, r1;             // runs of the module's map row
-    // z window of barrel-to-barrel candidates (valid when zw_on)
-    float zw_lo, zw_hi, zw_r;
-    bool zw_on, zw_off;
 };
 
 __device__ __forceinline__ LsAnchor ls_anchor(const LsArgs &a, int64_t A) {
@@ -1064,11 +1073,45 @@ __device__ __forceinline__ LsAnchor ls_anchor(const LsArgs &a, int64_t A) {
     s.end = signbit(rq.y);
     float ph = atan2f(p.y, p.x);
     s.phi = ph < 0.0f ? ph + 6.2831853f : ph;
+    s.ux = p.x / s.r;
+    s.uy = p.y / s.r;
     s.ebase = (int64_t)e * a.g.n_mod;
     s.r0 = a.g.run_off[m];
     s.r1 = a.g.run_off[m + 1];
-    s.zw_on = s.zw_off = false;
-    s.zw_lo = s.zw_hi = s.zw_r = 0.0f;
+    s.hask = s.none = false;
+    s.klo = s.khi = 0.0f;
+    if (!s.end) {
+        // LS3 on A: the chord d from the anchor to the other hit, at angle
+        // alpha from the radial direction of the chord midpoint M; the
+        // interval ends are sin(alpha -+ tol) / |M| with alpha -+ tol clipped
+        // to [-pi/2, pi/2] (taken from sin and cos of alpha, no angles)
+        const float2 o = a.md_o[A];
+        const float dx = o.x - p.x, dy = o.y - p.y;
+        const float mx = 0.5f * (p.x + o.x), my = 0.5f * (p.y + o.y);
+        const float mm = sqrtf(mx * mx + my * my), dl = sqrtf(dx * dx + dy * dy);
+        const float inv = 1.0f / (mm * dl);
+        const float sa = (mx * dy - my * dx) * inv, ca = (mx * dx + my * dy) * inv;
+        const float tol = (a.p.nsig * 1.41421356f * a.p.srphi / dl + a.p.ls3slack) * 1.001f + 2e-5f;
+        if (tol < 0.5f) {
+            s.hask = true;
+            float st, ct;
+            __sincosf(tol, &st, &ct);
+            const float sp = sa * ct + ca * st, cp = ca * ct - sa * st;   // alpha + tol
+            const float sm = sa * ct - ca * st, cm = ca * ct + sa * st;   // alpha - tol
+            float shi = sp, slo = sm;
+            if (cp < 0.0f) {
+                if (sp > 0.0f) shi = 1.0f;
+                else s.none = true;
+            }
+            if (cm < 0.0f) {
+                if (sm < 0.0f) slo = -1.0f;
+                else s.none = true;
+            }
+            s.klo = slo / mm;
+            s.khi = shi / mm;
+            if (s.khi < -a.p.cmax || s.klo > a.p.cmax) s.none = true;
+        }
+    }
     return s;
 }
 
@@ -1090,45 +1133,54 @@ __device__ __forceinline__ void ls_zwindow(const CutParams &p, float za, float r
     hi += m;
 }
 
-// Kept target modules [t0, t0 + i0 .. i1] of run rr for anchor s (i1 < i0:
-// none). Sets the anchor's barrel z window on its first barrel-to-barrel run.
-__device__ __forceinline__ int2 ls_run_trim(const CutParams &p, LsAnchor &s, const RunRec &rr) {
+// asin(x) for |x| <= 0.8 from the arc-length polynomial (relative error below
+// 1e-7, far inside the windows' slack)
+__device__ __forceinline__ float ls_asin(float x) { return x * asin_over_x_f(x * x); }
+
+// Kept target modules i0 .. i1 of run rr for anchor s (i1 < i0: none), with
+// the phi window every candidate must pass (edge directions e_lo, e_hi; all
+// zero: no window) and its z window.
+__device__ __forceinline__ int2 ls_run_trim(const CutParams &p, const LsAnchor &s, const RunRec &rr, float4 &win,
+                                            float2 &zw) {
     int i0 = 0, i1 = rr.n - 1;
-    bool keep = true;
+    win = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    zw = make_float2(-INFINITY, INFINITY);
     // s ordering: every anchor of the row is below r_A
-    if (rr.r_hi * (1.0f + 2e-5f) < s.r) keep = false;
-    // barrel to barrel: z window, for the first barrel radius above r_A that
-    // the map reaches (a second radius switches the window off)
-    if (keep && !s.end && !(rr.flags & kRunEndcap)) {
-        if (!s.zw_on && !s.zw_off) {
-            if (rr.r_lo > s.r * 1.0001f) {
-                ls_zwindow(p, s.z, s.r, rr.r_lo, rr.r_hi, s.zw_lo, s.zw_hi);
-                s.zw_r = rr.r_lo;
-                s.zw_on = true;
-            } else {
-                s.zw_off = true;
-            }
-        } else if (s.zw_on && s.zw_r != rr.r_lo) {
-            s.zw_on = false;
-            s.zw_off = true;
-        }
-        if (s.zw_on && (rr.z_hi < s.zw_lo || rr.z_lo > s.zw_hi)) keep = false;
+    bool keep = !s.none && !(rr.r_hi * (1.0f + 2e-5f) < s.r);
+    // barrel to barrel: z window
+    if (keep && !s.end && !(rr.flags & kRunEndcap) && rr.r_lo > s.r * 1.0001f) {
+        ls_zwindow(p, s.z, s.r, rr.r_lo, rr.r_hi, zw.x, zw.y);
+        if (rr.z_hi < zw.x || rr.z_lo > zw.y) keep = false;
     }
-    // curvature: phi window
+    // curvature (and, for a barrel A, its direction): phi window
     if (keep && !(rr.flags & kRunNoTrim)) {
         const float dmin = rr.r_lo - s.r * (1.0f + 1e-6f);
         if (dmin > 0.05f) {
             const float clim = 1.001f * (p.cmax + p.nsig * sqrtf(s.q + rr.qb_max) / dmin);
             const float xh = clim * rr.r_hi;
-            if (xh < 0.85f) {
-                const float w = asinf(xh) - asinf(clim * s.r) + 1e-4f;
-                // window [phi - w, phi + w] against the run [phi_start, phi_start + n dphi],
-                // at shifts of -2 pi, 0, 2 pi; the hull of the overlaps is kept
+            if (xh < 0.8f) {
+                // every |k r| below is at most xh < 0.8, where asin(x) =
+                // x asin_over_x(x^2) holds to 1e-7
+                float dlo, dhi;
+                if (s.hask) {
+                    const float kl = s.klo <= -p.cmax ? -clim : fmaxf(s.klo, -clim);
+                    const float kh = s.khi >= p.cmax ? clim : fminf(s.khi, clim);
+                    dlo = ls_asin(kl * (kl >= 0.0f ? rr.r_lo : rr.r_hi)) - ls_asin(kl * s.r);
+                    dhi = ls_asin(kh * (kh >= 0.0f ? rr.r_hi : rr.r_lo)) - ls_asin(kh * s.r);
+                } else {
+                    dhi = ls_asin(xh) - ls_asin(clim * s.r);
+                    dlo = -dhi;
+                }
+                dlo -= 1e-4f;
+                dhi += 1e-4f;
+                // window [phi + dlo, phi + dhi] against the run [phi_start,
+                // phi_start + n dphi], at shifts of -2 pi, 0, 2 pi; the hull of
+                // the overlaps is kept
                 int lo = rr.n, hi = -1;
 #pragma unroll
                 for (int sh = -1; sh <= 1; ++sh) {
                     const float c = s.phi + (float)sh * 6.2831853f - rr.phi_start;
-                    const float u0 = (c - w) * rr.inv_dphi - 1e-4f, u1 = (c + w) * rr.inv_dphi + 1e-4f;
+                    const float u0 = (c + dlo) * rr.inv_dphi - 1e-4f, u1 = (c + dhi) * rr.inv_dphi + 1e-4f;
                     if (u1 >= 0.0f && u0 < (float)rr.n) {
                         const int v0 = u0 < 0.0f ? 0 : (int)u0;
                         const int v1 = u1 >= (float)(rr.n - 1) ? rr.n - 1 : (int)u1;
@@ -1138,6 +1190,11 @@ __device__ __forceinline__ int2 ls_run_trim(const CutParams &p, LsAnchor &s, con
                 }
                 i0 = lo;
                 i1 = hi;
+                float sl, cl, sh, ch;
+                __sincosf(dlo, &sl, &cl);
+                __sincosf(dhi, &sh, &ch);
+                win = make_float4(cl * s.ux - sl * s.uy, sl * s.ux + cl * s.uy, ch * s.ux - sh * s.uy,
+                                  sh * s.ux + ch * s.uy);
             }
         }
     }
@@ -1145,30 +1202,37 @@ __device__ __forceinline__ int2 ls_run_trim(const CutParams &p, LsAnchor &s, con
     return make_int2(i0, i1);
 }
 
-// Barrel-to-barrel z window test of candidate B (conservative LS2 pre-test).
-__device__ __forceinline__ bool ls_zpass(const LsAnchor &s, float zb, float2 qb) {
-    if (!s.zw_on || signbit(qb.y) || s.end) return true;
-    return zb >= s.zw_lo && zb <= s.zw_hi;
+// Window test of candidate B: between the edge directions (the window spans
+// less than pi) and inside the z window.
+__device__ __forceinline__ bool ls_window_pass(const float4 &w, const float2 &zw, const float4 &PB) {
+    return w.x * PB.y - w.y * PB.x >= -kLsCrossMargin && PB.x * w.w - PB.y * w.z >= -kLsCrossMargin &&
+           PB.z >= zw.x && PB.z <= zw.y;
 }
 
 __device__ __forceinline__ unsigned long long lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
-// LS1 and LS2 of (A, B); on a pass, the clamped curvature and the queue tag.
-__device__ __forceinline__ bool ls_pair(const CutParams &p, const LsAnchor &s, P3 PA, float2 qa, float4 PB,
-                                        float2 qb, int lane, float &cp, int &tag) {
-    if (!ls_zpass(s, PB.z, qb)) return false;
-    float c, sg;
-    if (!pair_curv_pass(p, PA, qa, P3{PB.x, PB.y, PB.z}, qb, c, sg)) return false;
-    cp = fminf(c, p.cmax);
-    if (!pair_z0_pass(p, PA, qa, P3{PB.x, PB.y, PB.z}, qb, cp)) return false;
-    tag = lane | (sg > 0.0f ? kTagPos : 0) | (s.end ? 0 : kTagDirA) | (signbit(qb.y) ? 0 : kTagDirB);
-    return true;
+// Write the wavefront's LDS list of survivors [0, outn) to the scratch array
+// as (A, B, rank) records.
+__device__ void ls_spill(const LsArgs &a, LsLds &L, int wv, int lane, int64_t wbase, int &outn) {
+    wave_sync_lds();
+    unsigned long long b0 = 0;
+    if (lane == 0) b0 = atomicAdd(a.top, (unsigned long long)outn);
+    const long long base = (long long)__shfl((long long)b0, 0, 64);
+    for (int i = lane; i < outn; i += 64) {
+        if (base + i < a.cap_chunk) {
+            const int t = L.ot[wv][i];
+            a.chunk[base + i] = make_int4((int)(wbase + (t & 63)), L.ob[wv][i], t >> 6, 0);
+        }
+    }
+    outn = 0;
+    wave_sync_lds();
 }
 
 // LS3 on queue entries [0, n) (n <= 64); survivors go to the output list
 // with their rank among their owner's survivors, the remaining entries move
 // to the front.
 __device__ void ls_flush(const LsArgs &a, LsLds &L, int wv, int lane, int64_t wbase, int n, int &qn, int &outn) {
+    if (outn > kLsOutCap - 64) ls_spill(a, L, wv, lane, wbase, outn);
     wave_sync_lds();
     bool ok = false;
     int b = 0, owner = 0;
@@ -1213,7 +1277,7 @@ __device__ void ls_flush(const LsArgs &a, LsLds &L, int wv, int lane, int64_t wb
     if (ok && rank == 0) L.cnt[wv][owner] = base + __popcll(same);
     const unsigned long long mo = __ballot(ok);
     const int pos = outn + __popcll(mo & lanes_below(lane));
-    if (ok && pos < kLsOutCap) {
+    if (ok) {
         L.ob[wv][pos] = b;
         L.ot[wv][pos] = owner | ((base + rank) << 6);
     }
@@ -1221,12 +1285,62 @@ __device__ void ls_flush(const LsArgs &a, LsLds &L, int wv, int lane, int64_t wb
     wave_sync_lds();
 }
 
+// LS1 and LS2 on window-survivor entries [0, n) (n <= 64), the anchor of
+// each taken from its owner lane; passing pairs join the LS3 queue, the
+// remaining entries move to the front. Called with every lane active.
+__device__ void ls_dense(const LsArgs &a, LsLds &L, int wv, int lane, int64_t wbase, const LsAnchor &s, int n,
+                         int &pn, int &qn, int &outn) {
+    wave_sync_lds();
+    int b = 0, o = 0;
+    if (lane < n) {
+        b = L.pb[wv][lane];
+        o = L.po[wv][lane];
+    }
+    const float ax = __shfl(s.x, o, 64), ay = __shfl(s.y, o, 64), az = __shfl(s.z, o, 64);
+    const float ar = __shfl(s.r, o, 64), aq = __shfl(s.end ? -s.q : s.q, o, 64);
+    bool pass = false;
+    float cp = 0.0f;
+    int tag = 0;
+    if (lane < n) {
+        const float4 PB = a.md_a[b];
+        const float2 qb = a.md_rq[b];
+        const P3 PA{ax, ay, az}, PBp{PB.x, PB.y, PB.z};
+        const float2 qa = make_float2(ar, aq);
+        float c, sg;
+        if (pair_curv_pass(a.p, PA, qa, PBp, qb, c, sg)) {
+            cp = fminf(c, a.p.cmax);
+            if (pair_z0_pass(a.p, PA, qa, PBp, qb, cp)) {
+                pass = true;
+                tag = o | (sg > 0.0f ? kTagPos : 0) | (signbit(aq) ? 0 : kTagDirA) | (signbit(qb.y) ? 0 : kTagDirB);
+            }
+        }
+    }
+    const int rest = pn - n;
+    if (rest > 0) {
+        wave_sync_lds();
+        const int src = n + (lane < rest ? lane : 0);
+        const int tb = L.pb[wv][src], to = L.po[wv][src];
+        wave_sync_lds();
+        if (lane < rest) { L.pb[wv][lane] = tb; L.po[wv][lane] = to; }
+    }
+    pn = rest;
+    const unsigned long long m = __ballot(pass);
+    if (pass) {
+        const int pos = qn + __popcll(m & lanes_below(lane));
+        L.qb[wv][pos] = b;
+        L.qc[wv][pos] = cp;
+        L.qt[wv][pos] = tag;
+    }
+    qn += __popcll(m);
+    if (qn >= 64) ls_flush(a, L, wv, lane, wbase, 64, qn, outn);
+}
+
 // Stage the trimmed MD ranges of runs [rbeg, rbeg + kLsRunsPerRound) of each
-// lane's anchor in LDS, two runs at a time (their records, then their four
-// module offsets, in flight together); returns the number of non-empty
-// ranges of this lane and adds their candidates to *cands.
-__device__ __forceinline__ int ls_stage_round(const LsArgs &a, LsLds &L, int wv, int lane, LsAnchor &s, bool act,
-                                              int rbeg, int rmax, int &cands) {
+// lane's anchor in LDS with their windows, two runs at a time (their records,
+// then their four module offsets, in flight together); returns the number of
+// non-empty ranges of this lane and adds their candidates to *cands.
+__device__ __forceinline__ int ls_stage_round(const LsArgs &a, LsLds &L, int wv, int lane, const LsAnchor &s,
+                                              bool act, int rbeg, int rmax, int &cands) {
     int nr = 0;
     const int last = s.r1 - 1 >= s.r0 ? s.r1 - 1 : s.r0;   // clamped run index (valid: the table is never empty)
     for (int r = rbeg; r < rbeg + kLsRunsPerRound && r < rmax; r += 2) {
@@ -1235,8 +1349,10 @@ __device__ __forceinline__ int ls_stage_round(const LsArgs &a, LsLds &L, int wv,
         const int k1 = s.r0 + r + 1 < last ? s.r0 + r + 1 : last;
         const RunRec ra = a.g.runs[k0], rb = a.g.runs[k1];
         int2 ta = make_int2(0, -1), tb = make_int2(0, -1);
-        if (h0) ta = ls_run_trim(a.p, s, ra);
-        if (h1) tb = ls_run_trim(a.p, s, rb);
+        float4 wa, wb;
+        float2 za, zb;
+        if (h0) ta = ls_run_trim(a.p, s, ra, wa, za);
+        if (h1) tb = ls_run_trim(a.p, s, rb, wb, zb);
         const int64_t ea = s.ebase + ra.t_first, eb = s.ebase + rb.t_first;
         const int64_t ia0 = ta.y >= ta.x ? ea + ta.x : s.ebase, ia1 = ta.y >= ta.x ? ea + ta.y + 1 : s.ebase;
         const int64_t ib0 = tb.y >= tb.x ? eb + tb.x : s.ebase, ib1 = tb.y >= tb.x ? eb + tb.y + 1 : s.ebase;
@@ -1244,11 +1360,15 @@ __device__ __forceinline__ int ls_stage_round(const LsArgs &a, LsLds &L, int wv,
         const int jb = (int)a.md_mod_off[ib0], jbe = (int)a.md_mod_off[ib1];
         if (jae > ja) {
             L.rng[wv][nr][lane] = make_int2(ja, jae);
+            L.win[wv][nr][lane] = wa;
+            L.zw[wv][nr][lane] = za;
             cands += jae - ja;
             ++nr;
         }
         if (jbe > jb) {
             L.rng[wv][nr][lane] = make_int2(jb, jbe);
+            L.win[wv][nr][lane] = wb;
+            L.zw[wv][nr][lane] = zb;
             cands += jbe - jb;
             ++nr;
         }
@@ -1257,29 +1377,42 @@ __device__ __forceinline__ int ls_stage_round(const LsArgs &a, LsLds &L, int wv,
 }
 
 // A lane's walk over its staged ranges: next() returns the next candidate
-// index and whether there is one.
+// index with its range's windows, and whether there is one.
 struct LsCursor {
     int ri, nr, j, je;
     bool on;
+    float4 w;
+    float2 zw;
+    __device__ __forceinline__ void load(const LsLds &L, int wv, int lane) {
+        const int2 g = L.rng[wv][ri][lane];
+        j = g.x;
+        je = g.y;
+        w = L.win[wv][ri][lane];
+        zw = L.zw[wv][ri][lane];
+    }
     __device__ __forceinline__ void start(const LsLds &L, int wv, int lane, int n) {
         ri = 0;
         nr = n;
         on = n > 0;
         j = je = 0;
-        if (on) { const int2 g = L.rng[wv][0][lane]; j = g.x; je = g.y; }
+        w = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        zw = make_float2(0.0f, 0.0f);
+        if (on) load(L, wv, lane);
     }
-    __device__ __forceinline__ bool next(const LsLds &L, int wv, int lane, int &b) {
+    __device__ __forceinline__ bool next(const LsLds &L, int wv, int lane, int &b, float4 &wo, float2 &zo) {
         if (!on) return false;
         b = j++;
+        wo = w;
+        zo = zw;
         if (j >= je) {
-            if (++ri < nr) { const int2 g = L.rng[wv][ri][lane]; j = g.x; je = g.y; }
+            if (++ri < nr) load(L, wv, lane);
             else on = false;
         }
         return true;
     }
 };
 
-__global__ __launch_bounds__(kBlock) void k_ls_eval(LsArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_ls_eval(LsArgs a) {
     __shared__ LsLds L;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t n_md = dev_count(a.counts + LST_COUNT_MD, a.cap_md);
@@ -1292,9 +1425,9 @@ __global__ __launch_bounds__(kBlock) void k_ls_eval(LsArgs a) {
         const int64_t wbase = w * 64, A = wbase + lane;
         const bool act = A < n_md;
         const int a_safe = (int)(act ? A : n_md - 1);
-        LsAnchor s = ls_anchor(a, a_safe);
+        const LsAnchor s = ls_anchor(a, a_safe);
         L.cnt[wv][lane] = 0;
-        int qn = 0, outn = 0, cands = 0;
+        int pn = 0, qn = 0, outn = 0, cands = 0;
         // runs of the wavefront's longest map row
         int nrun = act ? s.r1 - s.r0 : 0;
 #pragma unroll
@@ -1302,148 +1435,76 @@ __global__ __launch_bounds__(kBlock) void k_ls_eval(LsArgs a) {
             const int o = __shfl_xor(nrun, d, 64);
             nrun = o > nrun ? o : nrun;
         }
-        const P3 PA{s.x, s.y, s.z};
-        const float2 qa = make_float2(s.r, s.end ? -s.q : s.q);
         for (int rbeg = 0; rbeg < nrun; rbeg += kLsRunsPerRound) {
             const int nr = ls_stage_round(a, L, wv, lane, s, act, rbeg, nrun, cands);
             wave_sync_lds();
             LsCursor cu;
             cu.start(L, wv, lane, nr);
             // Two register sets take alternate candidates; a set is reloaded
-            // right after its candidate is evaluated, so every load has the
-            // other set's evaluation to complete in (no register of a load in
-            // flight is copied).
+            // right after its candidate is tested, so every load has the
+            // other set's test to complete in.
             int bA = a_safe, bB = a_safe;
-            bool vA = cu.next(L, wv, lane, bA);
+            float4 wA, wB;
+            float2 zA, zB;
+            bool vA = cu.next(L, wv, lane, bA, wA, zA);
             float4 PBa = a.md_a[bA];
-            float2 QBa = a.md_rq[bA];
-            bool vB = cu.next(L, wv, lane, bB);
+            bool vB = cu.next(L, wv, lane, bB, wB, zB);
             float4 PBb = a.md_a[bB];
-            float2 QBb = a.md_rq[bB];
-            auto step = [&](bool v, int b, const float4 &PB, const float2 &QB) {
-                float cp = 0.0f;
-                int tag = 0;
-                const bool pass = v && ls_pair(a.p, s, PA, qa, PB, QB, lane, cp, tag);
+            auto step = [&](bool v, int b, const float4 &PB, const float4 &wn, const float2 &zn) {
+                const bool pass = v && ls_window_pass(wn, zn, PB);
                 const unsigned long long m = __ballot(pass);
                 if (pass) {
-                    const int pos = qn + __popcll(m & lanes_below(lane));
-                    L.qb[wv][pos] = b;
-                    L.qc[wv][pos] = cp;
-                    L.qt[wv][pos] = tag;
+                    const int pos = pn + __popcll(m & lanes_below(lane));
+                    L.pb[wv][pos] = b;
+                    L.po[wv][pos] = lane;
                 }
-                qn += __popcll(m);
-                if (qn >= 64) ls_flush(a, L, wv, lane, wbase, 64, qn, outn);
+                pn += __popcll(m);
+                if (pn >= 64) ls_dense(a, L, wv, lane, wbase, s, 64, pn, qn, outn);
             };
             while (__ballot(vA) != 0ull) {
-                step(vA, bA, PBa, QBa);
+                step(vA, bA, PBa, wA, zA);
                 bA = a_safe;
-                vA = cu.next(L, wv, lane, bA);
+                vA = cu.next(L, wv, lane, bA, wA, zA);
                 PBa = a.md_a[bA];
-                QBa = a.md_rq[bA];
                 if (__ballot(vB) == 0ull) break;
-                step(vB, bB, PBb, QBb);
+                step(vB, bB, PBb, wB, zB);
                 bB = a_safe;
-                vB = cu.next(L, wv, lane, bB);
+                vB = cu.next(L, wv, lane, bB, wB, zB);
                 PBb = a.md_a[bB];
-                QBb = a.md_rq[bB];
             }
         }
-        // drain the queue
+        // drain the queues
+        while (pn > 0) ls_dense(a, L, wv, lane, wbase, s, pn < 64 ? pn : 64, pn, qn, outn);
         while (qn > 0) ls_flush(a, L, wv, lane, wbase, qn < 64 ? qn : 64, qn, outn);
+        if (outn > 0) ls_spill(a, L, wv, lane, wbase, outn);
         wave_sync_lds();
-        // per-A counts, the wavefront's prefix over them, and its chunk
-        const int c = act ? L.cnt[wv][lane] : 0;
-        if (act) a.ls_cnt[A] = c;
-        int incl = c;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int o = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += o;
-        }
-        const int tot = __shfl(incl, 63, 64);
-        wave_sync_lds();
-        L.cnt[wv][lane] = incl - c;            // exclusive prefix, by owner
-        wave_sync_lds();
-        bool ovf = outn > kLsOutCap;
-        long long base = 0;
-        if (!ovf && tot > 0) {
-            unsigned long long b0 = 0;
-            if (lane == 0) b0 = atomicAdd(a.top, (unsigned long long)tot);
-            base = (long long)__shfl((long long)b0, 0, 64);
-            if (base + tot > a.cap_chunk) ovf = true;
-        }
-        if (!ovf)
-            for (int i = lane; i < outn; i += 64) {
-                const int t = L.ot[wv][i];
-                const int owner = t & 63;
-                a.chunk[base + L.cnt[wv][owner] + (t >> 6)] = make_int2((int)(wbase + owner), L.ob[wv][i]);
-            }
+        if (act) a.ls_cnt[A] = L.cnt[wv][lane];
         int cs = cands;
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) cs += __shfl_xor(cs, d, 64);
-        if (lane == 0) {
-            a.wave_base[w] = ovf ? -1 : base;
-            atomicAdd((unsigned long long *)&a.counts[LST_COUNT_LSCAND], (unsigned long long)cs);
-        }
+        if (lane == 0) atomicAdd((unsigned long long *)&a.counts[LST_COUNT_LSCAND], (unsigned long long)cs);
         wave_sync_lds();
     }
 }
 
-// One A per lane, every candidate in order with all cuts, writing LS to
-// ls_md[k..] (the recompute path of a wavefront whose survivors overflowed
-// its list; the same trimming and cut code, so the same results).
-__device__ void ls_recompute(const LsArgs &a, int64_t A, int64_t k, int2 *ls_md, int64_t cap_ls) {
-    LsAnchor s = ls_anchor(a, A);
-    const P3 PA{s.x, s.y, s.z};
-    const float2 qa = make_float2(s.r, s.end ? -s.q : s.q);
-    for (int32_t r = s.r0; r < s.r1; ++r) {
-        const RunRec rr = a.g.runs[r];
-        const int2 t = ls_run_trim(a.p, s, rr);
-        if (t.y < t.x) continue;
-        const int64_t e0 = s.ebase + rr.t_first;
-        const int j0 = (int)a.md_mod_off[e0 + t.x], j1 = (int)a.md_mod_off[e0 + t.y + 1];
-        for (int b = j0; b < j1; ++b) {
-            const float4 PB = a.md_a[b];
-            const float2 qb = a.md_rq[b];
-            float cp;
-            int tag;
-            if (!ls_pair(a.p, s, PA, qa, PB, qb, 0, cp, tag)) continue;
-            const float sgn = (tag & kTagPos) ? 1.0f : -1.0f;
-            if (tag & kTagDirA) {
-                const float2 oa = a.md_o[A];
-                if (!md_dir_pass(a.p, PA, oa.x, oa.y, cp, sgn)) continue;
-            }
-            if (tag & kTagDirB) {
-                const float2 ob = a.md_o[b];
-                if (!md_dir_pass(a.p, P3{PB.x, PB.y, PB.z}, ob.x, ob.y, cp, sgn)) continue;
-            }
-            if (k < cap_ls) ls_md[k] = make_int2((int)A, b);
-            ++k;
-        }
-    }
-}
-
-// Place every wavefront's segments at their CSR offsets (ls_off = exclusive
-// scan of the per-A counts), or recompute the wavefronts that overflowed.
+// Place every record at offset[A] + rank (ls_off = exclusive scan of the
+// per-A counts). When more segments were found than the scratch holds (the
+// build then reports a capacity overflow), the list is filled with valid
+// indices instead, for the stages that still read it.
 __global__ __launch_bounds__(kBlock) void k_ls_place(LsArgs a, const int64_t *ls_off, int2 *ls_md, int64_t cap_ls) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t n_md = dev_count(a.counts + LST_COUNT_MD, a.cap_md);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.counts[LST_COUNT_LS] = ls_off[n_md];
-    const int64_t nwaves = (n_md + 63) / 64;
-    const int64_t ntiles = (nwaves + kLsWaves - 1) / kLsWaves;
-    const TileWalk walk(ntiles);
-    for (int64_t tile = walk.first; tile < walk.end; tile += walk.step) {
-        const int64_t w = tile * kLsWaves + wv;
-        if (w >= nwaves) continue;
-        const int64_t A0 = w * 64, A1 = A0 + 64 < n_md ? A0 + 64 : n_md;
-        const int64_t o0 = ls_off[A0], tot = ls_off[A1] - o0;
-        const int64_t wb = a.wave_base[w];
-        if (wb >= 0) {
-            for (int64_t i = lane; i < tot; i += 64)
-                if (o0 + i < cap_ls) ls_md[o0 + i] = a.chunk[wb + i];
-        } else if (A0 + lane < n_md) {
-            ls_recompute(a, A0 + lane, ls_off[A0 + lane], ls_md, cap_ls);
-        }
+    const int64_t tot = ls_off[n_md];
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.counts[LST_COUNT_LS] = tot;
+    const int64_t top = (int64_t)*a.top;
+    if (top > a.cap_chunk) {
+        const int64_t n = tot < cap_ls ? tot : cap_ls;
+        for (int64_t i = grid_tid(); i < n; i += grid_stride()) ls_md[i] = make_int2(0, 0);
+        return;
+    }
+    for (int64_t i = grid_tid(); i < top; i += grid_stride()) {
+        const int4 r = a.chunk[i];
+        const int64_t pos = ls_off[r.x] + r.z;
+        if (pos < cap_ls) ls_md[pos] = make_int2(r.x, r.y);
     }
 }
 
@@ -1836,8 +1897,8 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     // a3: line segments, one inner MD per lane over the trimmed runs of its
     // module-map row; CSR offsets by inner MD from the per-MD counts
     mark(ev, 16, st);
-    LsArgs la{w.md_a, w.md_o, w.md_rq, w.md_mod_off, a.g, a.p, w.ls_cnt, w.ls_chunk, w.cap_ls, w.ls_wave,
-              w.ls_top, cnt, w.cap_md};
+    LsArgs la{w.md_a, w.md_o, w.md_rq, w.md_mod_off, a.g, a.p, w.ls_cnt, w.ls_chunk, w.cap_ls, w.ls_top, cnt,
+              w.cap_md};
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.ls_top);
     {
         const int64_t tiles = (w.cap_md + 64 * kLsWaves - 1) / (64 * kLsWaves);
@@ -1847,8 +1908,8 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
         hipLaunchKernelGGL(k_ls_eval, dim3(nb), dim3(kBlock), 0, st, la);
         mark(ev, 7, st);
         scan(CntF{w.ls_cnt}, cnt + LST_COUNT_MD, w.cap_md, w, w.ls_off, nullptr, st);
-        hipLaunchKernelGGL(k_ls_place, dim3(nb), dim3(kBlock), 0, st, la, (const int64_t *)w.ls_off, (int2 *)o.ls_md,
-                           w.cap_ls);
+        hipLaunchKernelGGL(k_ls_place, dim3(grid_for(w.cap_ls)), dim3(kBlock), 0, st, la, (const int64_t *)w.ls_off,
+                           (int2 *)o.ls_md, w.cap_ls);
     }
     mark(ev, 17, st);
 
