@@ -17,7 +17,8 @@ reading, step by step, per event:
     (-pi, pi]), s_X = asin(c r_X) / c (r_X at c = 0), cot = (z_E - z_A) /
     (s_E - s_A), z0 = z_A - s_A cot. An object with s_E <= s_A or c r >= 1 has
     no parameters and matches no seed.
- 2. Match chi2 of seed p and object o: the sum over kappa, phi0 (difference
+ 2. Match chi2 of seed p and object o (options taken as FP32 numbers, as the
+    library receives them): the sum over kappa, phi0 (difference
     wrapped to (-pi, pi]), cot and z0 of (p_i - o_i)^2 / (sigma_p,i^2 +
     sigma_o,i^2), with the seed's own sigmas and the object sigmas of the
     options (sigma_kappa,o = kappa_rel |kappa_o| + kappa_abs). A pair matches
@@ -33,8 +34,8 @@ reading, step by step, per event:
     share more than half of the smaller one's MDs. A TC is removed when it has
     a duplicate of higher priority. Priority: kind (pT5, then T5, then pT3),
     then quality (T5: higher DNN score, or lower r-phi fit chi2 when there is
-    no score; pT3: lower match chi2), then the smaller object index. pLS TCs
-    are never removed.
+    no score; pT3: lower match chi2 rounded to FP32), then the smaller object
+    index. pLS TCs are never removed.
 
 TC kinds: 0 pT5, 1 T5, 2 pT3, 3 pLS. Each TC is (kind, seed or -1, object
 index or -1): the T5 index for pT5 / T5, the T3 index for pT3.
@@ -89,8 +90,14 @@ def object_params(x, y, z, md_hits, obj_mds):
     return P, valid
 
 
+def _f32(v):
+    """Options are single-precision numbers (as the library receives them)."""
+    return float(np.float32(v))
+
+
 def chi2_matrix(seeds, P, valid, opt: TcOptions):
     """Step 2: [n_seeds, n_obj] chi2 (inf where the object has no parameters)."""
+    opt = TcOptions(*(_f32(getattr(opt, k)) for k in TcOptions.__dataclass_fields__))
     s = np.asarray(seeds, np.float64)
     C = np.full((s.shape[0], P.shape[0]), np.inf)
     if not s.shape[0] or not P.shape[0]:
@@ -144,7 +151,7 @@ def select_event(x, y, z, md_hits, t3_mds, t5_mds, t5_t3, t5_quality, seeds, opt
     P5, v5 = object_params(x, y, z, md_hits, t5_mds)
     P3, v3 = object_params(x, y, z, md_hits, t3_mds)
     C5 = chi2_matrix(seeds, P5, v5, opt)
-    pt5 = mutual_best(C5, opt.chi2_max, np.ones(ns, bool), np.ones(n5, bool))
+    pt5 = mutual_best(C5, _f32(opt.chi2_max), np.ones(ns, bool), np.ones(n5, bool))
     seed_used = np.zeros(ns, bool)
     t5_used = np.zeros(n5, bool)
     t3_used = np.zeros(n3, bool)
@@ -154,15 +161,16 @@ def select_event(x, y, z, md_hits, t3_mds, t5_mds, t5_t3, t5_quality, seeds, opt
         t3_used[t5_t3[t, 0]] = True
         t3_used[t5_t3[t, 1]] = True
     C3 = chi2_matrix(seeds, P3, v3, opt)
-    pt3 = mutual_best(C3, opt.chi2_max, ~seed_used, ~t3_used)
+    pt3 = mutual_best(C3, _f32(opt.chi2_max), ~seed_used, ~t3_used)
     for p, t in pt3:
         seed_used[p] = True
     tcs = [(K_PT5, p, t) for p, t in sorted(pt5, key=lambda v: v[1])]
     tcs += [(K_T5, -1, t) for t in range(n5) if not t5_used[t]]
     tcs += [(K_PT3, p, t) for p, t in sorted(pt3, key=lambda v: v[1])]
     tcs += [(K_PLS, p, -1) for p in range(ns) if not seed_used[p]]
-    chi2 = {(K_PT5, p, t): float(C5[p, t]) for p, t in pt5}
-    chi2.update({(K_PT3, p, t): float(C3[p, t]) for p, t in pt3})
+    # match chi2 of the pairs, rounded to FP32 as in the ranking
+    chi2 = {(K_PT5, p, t): float(_key(C5[p, t])) for p, t in pt5}
+    chi2.update({(K_PT3, p, t): float(_key(C3[p, t])) for p, t in pt3})
     # step 7
     ot = [i for i, tc in enumerate(tcs) if tc[0] != K_PLS]
     mds = [t5_mds[tcs[i][2]] if tcs[i][0] in (K_PT5, K_T5) else t3_mds[tcs[i][2]] for i in ot]

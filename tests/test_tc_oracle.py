@@ -61,7 +61,8 @@ def test_chi2_shifts_and_seam():
     opt = TC.TcOptions()
     P = np.array([[3e-3, 3.1, 0.5, 1.0], [-2e-3, -1.0, -2.0, -4.0]])
     v = np.ones(2, bool)
-    sig_o = lambda p: np.array([opt.kappa_rel * abs(p[0]) + opt.kappa_abs, opt.phi0, opt.cot, opt.z0])
+    f = lambda v: float(np.float32(v))        # the options are FP32 numbers
+    sig_o = lambda p: np.array([f(opt.kappa_rel) * abs(p[0]) + f(opt.kappa_abs), f(opt.phi0), f(opt.cot), f(opt.z0)])
     for j in range(2):
         s_seed = np.array([1e-4, 1e-3, 2e-3, 0.05])
         seed = np.concatenate([P[j], s_seed])[None, :]
