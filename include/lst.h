@@ -177,6 +177,72 @@ lst_status lst_build_objects_batched(lst_ctx *ctx, const lst_hits *hits,
 lst_status lst_score(lst_ctx *ctx, const void *X_dev, int32_t x_dtype, int64_t n,
                      float *scores_dev, int32_t precision, void *stream);
 
+/* Track-candidate selection (Sec. 1 and Table 1 steps 5-8) with duplicate
+ * removal (named in Sec. 2), on the objects of a completed build and a list of
+ * pixel seeds (pLS, Table 1 step 0; inputs here, from an upstream iteration).
+ * The paper gives the steps in words only; the library's rules:
+ *  - every T5 and T3 gets helix parameters (kappa = signed half-curvature with
+ *    the sign of A x E, phi0 = direction at the beam line, cot(theta), z0)
+ *    from its first (A) and last (E) MD anchor hits on a circle through the
+ *    beam line, in FP64;
+ *  - seed p and object o match when chi2 = sum over the four parameters of
+ *    (p_i - o_i)^2 / (sigma_p,i^2 + sigma_o,i^2) <= chi2_max (phi0 difference
+ *    wrapped to (-pi, pi]; object widths from the options, sigma_kappa,o =
+ *    sigma_kappa_rel |kappa_o| + sigma_kappa_abs);
+ *  - kind 0 pT5: seed and T5 that are each other's best match (smallest chi2
+ *    rounded to FP32, ties to the smaller index); kind 1 T5: the other T5s;
+ *    kind 2 pT3: the same mutual best match between the seeds left and the T3s
+ *    that are not one of the two T3s of a pT5's T5; kind 3 pLS: the seeds left;
+ *  - duplicate removal: two TCs with outer-tracker MDs (pT5 / T5: the T5's 5,
+ *    pT3: the T3's 3) are duplicates when they share more than half of the
+ *    smaller one's MDs; a TC is removed when it has a duplicate of higher
+ *    priority: kind (0 < 1 < 2), then quality (T5: higher score, or lower
+ *    r-phi chi2 when the score is NaN; pT3: lower match chi2 as FP32), then
+ *    the smaller object index. pLS TCs are never removed.
+ * Seeds: params device [n][8] FP32 = kappa (1/cm), phi0 (rad), cot(theta),
+ * z0 (cm), then their sigmas in the same order; event_off device int64
+ * [n_events + 1] seed ranges per event (event_off[0] = 0, last = n). */
+typedef struct {
+    const float *params;
+    const int64_t *event_off;
+    int64_t n;
+} lst_seeds;
+
+typedef struct {
+    float chi2_max;                       /* match threshold, > 0 */
+    float sigma_kappa_abs, sigma_kappa_rel, sigma_phi0, sigma_cot, sigma_z0;   /* object widths, >= 0 */
+} lst_tc_options;
+
+/* Selected TCs (device arrays of cap entries, caller-owned), in order: pT5 by
+ * T5 index, T5 by T5 index, pT3 by T3 index, pLS by seed index; object and
+ * seed indices as in the objects / seeds given. counts_dev (device, 8
+ * entries): kept TCs of kind 0..3, kept in total, TCs before duplicate
+ * removal. n is filled on return. */
+typedef struct {
+    int32_t *kind;
+    int32_t *seed;                        /* seed index, -1 for kind 1 */
+    int32_t *obj;                         /* T5 (kinds 0, 1) or T3 (kind 2) index, -1 for kind 3 */
+    int64_t *counts_dev;
+    int64_t cap;
+    int64_t n;
+} lst_tcs;
+
+/* Workspace bytes of lst_select_tcs for these object and seed counts
+ * (256-byte aligned base required). */
+lst_status lst_tc_workspace_size(const lst_ctx *ctx, const lst_objects *objects, int64_t n_seeds,
+                                 int32_t n_events, size_t *bytes);
+
+/* Select TCs. hits: the build's input hits (device); objects: its outputs with
+ * the host counts n_md .. n_t5 filled (a synchronous build); event_obj_offsets:
+ * the batched build's device [4][n_events + 1] offsets, or NULL when
+ * n_events = 1. Synchronises the stream. LST_E_CAPACITY when more TCs are kept
+ * than out->cap (out->n then holds the number needed); LST_E_INVAL on a bad
+ * argument. */
+lst_status lst_select_tcs(lst_ctx *ctx, const lst_hits *hits, const lst_objects *objects,
+                          const int64_t *event_obj_offsets_dev, int32_t n_events, const lst_seeds *seeds,
+                          const lst_tc_options *opt, lst_tcs *out, void *workspace, size_t ws_bytes,
+                          void *stream);
+
 /* Stage timing for measurement: while enabled, every build records HIP
  * events on its stream around the pipeline's stages (also when the build is
  * captured into a HIP graph). lst_stage_times then returns, for the most

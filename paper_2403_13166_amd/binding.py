@@ -36,7 +36,7 @@ EXPORTED = ("lst_create", "lst_destroy", "lst_load_geometry", "lst_load_model", 
             "lst_build_objects", "lst_build_objects_noalloc", "lst_build_objects_batched", "lst_score", "lst_status_string",
             "lst_last_error", "lst_set_timing", "lst_set_fail_stage", "lst_stage_times", "lst_get_tuning",
             "lst_set_tuning",
-            "lst_load_gnn", "lst_gnn_workspace_size", "lst_gnn_score")
+            "lst_load_gnn", "lst_gnn_workspace_size", "lst_gnn_score", "lst_tc_workspace_size", "lst_select_tcs")
 
 
 class LstHits(C.Structure):
@@ -75,6 +75,24 @@ class LstTuning(C.Structure):
             t.tile_per[i] = int(v)
         t.eval_blocks = int(d["eval_blocks"])
         return t
+
+
+class LstSeeds(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("event_off", C.c_void_p), ("n", C.c_int64)]
+
+
+class LstTcOptions(C.Structure):
+    _fields_ = [("chi2_max", C.c_float), ("sigma_kappa_abs", C.c_float), ("sigma_kappa_rel", C.c_float),
+                ("sigma_phi0", C.c_float), ("sigma_cot", C.c_float), ("sigma_z0", C.c_float)]
+
+
+class LstTcs(C.Structure):
+    _fields_ = [("kind", C.c_void_p), ("seed", C.c_void_p), ("obj", C.c_void_p), ("counts_dev", C.c_void_p),
+                ("cap", C.c_int64), ("n", C.c_int64)]
+
+
+TC_COUNTS_LEN = 8
+TC_KINDS = ("pT5", "T5", "pT3", "pLS")
 
 
 class LstError(RuntimeError):
@@ -129,6 +147,11 @@ def lib():
         L.lst_gnn_workspace_size.restype = i32
         L.lst_gnn_score.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, C.c_size_t, i32, vp]
         L.lst_gnn_score.restype = i32
+        L.lst_tc_workspace_size.argtypes = [vp, C.POINTER(LstObjects), i64, i32, C.POINTER(C.c_size_t)]
+        L.lst_tc_workspace_size.restype = i32
+        L.lst_select_tcs.argtypes = [vp, C.POINTER(LstHits), C.POINTER(LstObjects), vp, i32, C.POINTER(LstSeeds),
+                                     C.POINTER(LstTcOptions), C.POINTER(LstTcs), vp, C.c_size_t, vp]
+        L.lst_select_tcs.restype = i32
         L.lst_get_tuning.argtypes = [vp, C.POINTER(LstTuning)]
         L.lst_get_tuning.restype = i32
         L.lst_set_tuning.argtypes = [vp, C.POINTER(LstTuning)]
@@ -272,3 +295,20 @@ def lst_status_string(status: int) -> str:
 
 def lst_last_error(ctx) -> str:
     return lib().lst_last_error(ctx).decode()
+
+
+def lst_tc_workspace_size(ctx, objects: LstObjects, n_seeds: int, n_events: int) -> int:
+    n = C.c_size_t()
+    _check(ctx, lib().lst_tc_workspace_size(ctx, C.byref(objects), int(n_seeds), int(n_events), C.byref(n)),
+           "lst_tc_workspace_size")
+    return int(n.value)
+
+
+def lst_select_tcs(ctx, hits: LstHits, objects: LstObjects, event_obj_offsets_dev: int, n_events: int,
+                   seeds: LstSeeds, opt: LstTcOptions, out: LstTcs, ws: int, ws_bytes: int, stream: int,
+                   check: bool = True) -> int:
+    st = lib().lst_select_tcs(ctx, C.byref(hits), C.byref(objects), event_obj_offsets_dev, int(n_events),
+                              C.byref(seeds), C.byref(opt), C.byref(out), ws, ws_bytes, stream)
+    if check:
+        _check(ctx, st, "lst_select_tcs")
+    return st

@@ -16,6 +16,7 @@
 
 #include "../../include/lst.h"
 #include "lst_internal.h"
+#include "lst_tc.h"
 
 using namespace lst;
 
@@ -527,6 +528,75 @@ lst_status lst_score(lst_ctx *c, const void *X, int32_t x_dtype, int64_t n, floa
     if (n == 0) return LST_OK;
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, run_score(c->md, X, x_dtype, n, scores, precision, (hipStream_t)stream));
+    return LST_OK;
+}
+
+static bool tc_sizes(lst_ctx *c, const lst_objects *o, int64_t n_seeds, int32_t n_ev, TcSizes *z) {
+    if (!o || n_seeds < 0 || n_ev < 1) return false;
+    if (o->n_md < 0 || o->n_ls < 0 || o->n_t3 < 0 || o->n_t5 < 0) return false;
+    if (o->n_md > INT32_MAX || o->n_t3 > INT32_MAX || o->n_t5 > INT32_MAX || n_seeds > INT32_MAX) return false;
+    if ((int64_t)n_ev * kTcPhiBins * 2 > INT32_MAX) return false;
+    z->n_md = o->n_md; z->n3 = o->n_t3; z->n5 = o->n_t5; z->ns = n_seeds; z->n_ev = n_ev;
+    (void)c;
+    return true;
+}
+
+lst_status lst_tc_workspace_size(const lst_ctx *c, const lst_objects *o, int64_t n_seeds, int32_t n_events,
+                                 size_t *bytes) {
+    if (!c || !bytes) return LST_E_INVAL;
+    TcSizes z{};
+    if (!tc_sizes(nullptr, o, n_seeds, n_events, &z)) return LST_E_INVAL;
+    *bytes = tc_layout(z, nullptr, nullptr);
+    return LST_OK;
+}
+
+lst_status lst_select_tcs(lst_ctx *c, const lst_hits *h, const lst_objects *o, const int64_t *ev_obj, int32_t n_ev,
+                          const lst_seeds *s, const lst_tc_options *opt, lst_tcs *out, void *ws, size_t ws_bytes,
+                          void *stream) {
+    if (!c) return LST_E_INVAL;
+    if (!h || !o || !s || !opt || !out) return fail(c, LST_E_INVAL, "null argument");
+    TcSizes z{};
+    if (!tc_sizes(c, o, s->n, n_ev, &z)) return fail(c, LST_E_INVAL, "bad object / seed / event counts");
+    if (n_ev > 1 && !ev_obj) return fail(c, LST_E_INVAL, "several events need the event object offsets");
+    if (!s->event_off) return fail(c, LST_E_INVAL, "null seed event offsets");
+    if (s->n > 0 && !s->params) return fail(c, LST_E_INVAL, "null seed parameters");
+    const bool has_obj = o->n_t3 > 0 || o->n_t5 > 0;
+    if (has_obj && (!h->x || !h->y || !h->z || !o->md_hits || !o->ls_md || !o->t3_ls))
+        return fail(c, LST_E_INVAL, "null hit or object array");
+    if (o->n_t5 > 0 && (!o->t5_t3 || !o->t5_score || !o->t5_chi2_rphi)) return fail(c, LST_E_INVAL, "null T5 array");
+    const float f[6] = {opt->chi2_max, opt->sigma_kappa_abs, opt->sigma_kappa_rel, opt->sigma_phi0, opt->sigma_cot,
+                        opt->sigma_z0};
+    if (!(f[0] > 0.0f) || !isfinite(f[0])) return fail(c, LST_E_INVAL, "chi2_max must be positive");
+    for (int i = 1; i < 6; ++i)
+        if (!(f[i] >= 0.0f) || !isfinite(f[i])) return fail(c, LST_E_INVAL, "object widths must be finite, >= 0");
+    if (out->cap < 0 || (out->cap > 0 && (!out->kind || !out->seed || !out->obj)) || !out->counts_dev)
+        return fail(c, LST_E_INVAL, "bad TC output arrays");
+    if (((uintptr_t)ws & 255) != 0) return fail(c, LST_E_INVAL, "workspace must be 256-byte aligned");
+    const size_t need = tc_layout(z, nullptr, nullptr);
+    if (ws_bytes < need) return fail(c, LST_E_INVAL, "workspace %zu bytes, need %zu", ws_bytes, need);
+    HIP_TRY(c, hipSetDevice(c->device));
+    TcWork w{};
+    tc_layout(z, (char *)ws, &w);
+    w.out_kind = out->kind; w.out_seed = out->seed; w.out_obj = out->obj;
+    w.out_counts = out->counts_dev; w.cap_tc = out->cap;
+    TcArgs a{};
+    a.x = h->x; a.y = h->y; a.z = h->z;
+    a.md_hits = (const int2 *)o->md_hits; a.ls_md = (const int2 *)o->ls_md; a.t3_ls = (const int2 *)o->t3_ls;
+    a.t5_t3 = (const int2 *)o->t5_t3; a.t5_score = o->t5_score; a.t5_chi2_rphi = o->t5_chi2_rphi;
+    a.n_md = o->n_md; a.n_ls = o->n_ls; a.n3 = o->n_t3; a.n5 = o->n_t5;
+    a.ev_obj = ev_obj;                    // null for one event: offsets {0, n} are made on the device
+    a.n_ev = n_ev;
+    a.seeds = s->params; a.seed_off = s->event_off; a.ns = s->n;
+    a.opt = *opt;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, run_tc(a, w, st));
+    int64_t cnt[kTcCounts];
+    HIP_TRY(c, hipMemcpyAsync(cnt, out->counts_dev, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    out->n = cnt[kTcCountKept];
+    if (out->n > out->cap)
+        return fail(c, LST_E_CAPACITY, "%lld track candidates kept, capacity %lld", (long long)out->n,
+                    (long long)out->cap);
     return LST_OK;
 }
 

@@ -306,3 +306,50 @@ def to_device(ev, device) -> tuple:
     """Event arrays (numpy) -> device tensors (x, y, z, sensor)."""
     d = torch.device(device)
     return tuple(torch.from_numpy(np.ascontiguousarray(a)).to(d) for a in (ev.x, ev.y, ev.z, ev.sensor))
+
+
+# default options of track-candidate selection (object widths match the
+# resolution of the first-to-last anchor helix estimate)
+TC_OPTIONS = dict(chi2_max=20.0, sigma_kappa_abs=5e-6, sigma_kappa_rel=0.05, sigma_phi0=2e-3, sigma_cot=5e-3,
+                  sigma_z0=0.3)
+
+
+@dataclass
+class Tcs:
+    kind: torch.Tensor        # [n] int32: 0 pT5, 1 T5, 2 pT3, 3 pLS
+    seed: torch.Tensor        # [n] int32 seed index or -1
+    obj: torch.Tensor         # [n] int32 T5 / T3 index or -1
+    counts: list              # kept per kind (4), kept, before duplicate removal
+
+
+def select_tcs(builder: Builder, x, y, z, objects: Objects, seeds: torch.Tensor, seed_offsets: torch.Tensor,
+               options: dict | None = None) -> Tcs:
+    """Track candidates of a completed build (lst_select_tcs): seeds [n, 8]
+    float32 and seed_offsets [n_events + 1] int64 on the device."""
+    opt = dict(TC_OPTIONS, **(options or {}))
+    dev = builder.device
+    n_ev = int(seed_offsets.shape[0]) - 1
+    if seeds.dtype != torch.float32 or seeds.dim() != 2 or seeds.shape[1] != 8 or not seeds.is_contiguous():
+        raise ValueError("seeds must be a contiguous float32 [n, 8] tensor")
+    n_md, n_ls, n_t3, n_t5 = objects.counts()
+    ob = B.LstObjects(_ptr(objects.md_hits), _ptr(objects.ls_md), _ptr(objects.t3_ls), _ptr(objects.t5_t3),
+                      _ptr(objects.t5_score), _ptr(objects.t5_chi2_rphi), _ptr(objects.t5_chi2_rz), None, None,
+                      n_md, n_ls, n_t3, n_t5)
+    ws_bytes = B.lst_tc_workspace_size(builder.ctx, ob, seeds.shape[0], n_ev)
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    cap = n_t5 + n_t3 + seeds.shape[0] + 1
+    kind = torch.empty(cap, dtype=torch.int32, device=dev)
+    seed = torch.empty(cap, dtype=torch.int32, device=dev)
+    obj = torch.empty(cap, dtype=torch.int32, device=dev)
+    counts = torch.zeros(B.TC_COUNTS_LEN, dtype=torch.int64, device=dev)
+    out = B.LstTcs(kind.data_ptr(), seed.data_ptr(), obj.data_ptr(), counts.data_ptr(), cap, 0)
+    hits = B.LstHits(_ptr(x), _ptr(y), _ptr(z), None, int(x.shape[0]))
+    sd = B.LstSeeds(seeds.data_ptr(), seed_offsets.data_ptr(), int(seeds.shape[0]))
+    ev = objects.event_offsets
+    if n_ev > 1 and ev is None:
+        raise ValueError("several events need the batched build's event offsets")
+    B.lst_select_tcs(builder.ctx, hits, ob, _ptr(ev.contiguous()) if ev is not None else None, n_ev, sd,
+                     B.LstTcOptions(*(opt[k] for k in TC_OPTIONS)), out, (ws.data_ptr() + 255) & ~255, ws_bytes,
+                     torch.cuda.current_stream(dev).cuda_stream)
+    n = int(out.n)
+    return Tcs(kind[:n], seed[:n], obj[:n], counts.cpu().tolist()[:6])
