@@ -137,17 +137,32 @@ def _time_ms(fn, stream, reps=10):
     return float(np.median(ts))
 
 
-def measure_extras(b, dx, dy, dz, ds, doff, stream, prec):
-    """Standalone T5-DNN scoring of 1M feature rows (BF16 MFMA and FP32), the
-    edge classifier on a 200k-node / 1M-edge LST-like graph, and the T5 stage
-    of the same batch in pre-DNN mode (circle-fit chi2 cut, no DNN)."""
+def measure_extras(b, dx, dy, dz, ds, doff, stream, prec, geo, evs):
+    """Track-candidate selection on the batch's objects with synthetic pixel
+    seeds, standalone T5-DNN scoring of 1M feature rows (BF16 MFMA and FP32),
+    the edge classifier on a 200k-node / 1M-edge LST-like graph, and the T5
+    stage of the same batch in pre-DNN mode (circle-fit chi2 cut, no DNN)."""
     import torch
     from paper_2403_13166_amd import binding as B
-    from paper_2403_13166_amd.runtime import EdgeClassifier
-    from paper_2403_13166_amd.synth import gnn as SG, model as M
+    from paper_2403_13166_amd.runtime import EdgeClassifier, select_tcs
+    from paper_2403_13166_amd.synth import events as E, gnn as SG, model as M, seeds as S
     dev = dx.device
     out = {}
     with torch.cuda.stream(stream):
+        # TC selection (Table 1 steps 5-8 + duplicate removal) on this batch
+        b.launch(dx, dy, dz, ds, event_offsets=doff, mode=B.LST_MODE_DNN, precision=prec)
+        stream.synchronize()
+        objs = b.view()
+        sds = [S.make_seeds(geo, e, E.event_rng(5, i), eff=0.9, fake_frac=0.05) for i, e in enumerate(evs)]
+        sp, soff = S.concat_seeds(sds)
+        tsp, tsoff = torch.from_numpy(sp).to(dev), torch.from_numpy(soff).to(dev)
+        res = {}
+        ms = _time_ms(lambda: res.__setitem__("t", select_tcs(b, dx, dy, dz, objs, tsp, tsoff)), stream)
+        c = res["t"].counts
+        out["tc_selection"] = {"ms": ms, "seeds": int(len(sp)), "t5": int(objs.counts()[3]),
+                               "t3": int(objs.counts()[2]), "kept": {k: int(v) for k, v in zip(B.TC_KINDS, c[:4])},
+                               "before_duplicate_removal": int(c[5]),
+                               "events_per_s": len(evs) / (ms * 1e-3)}
         X = torch.from_numpy(M.make_scoring_inputs(1_000_000)).to(dev)
         for name, p_ in (("bf16_mfma", B.LST_PREC_BF16), ("f32_valu", B.LST_PREC_F32)):
             ms = _time_ms(lambda: b.score(X, precision=p_), stream)
@@ -389,7 +404,7 @@ def main():
     if not a.skip_extras:
         e2e = measure_end_to_end(b, step, (dx, dy, dz, ds), (x, y, z, s), final, stream, 10)
         e2e["events_per_s"] = a.events / (e2e["ms_per_batch"] * 1e-3)
-        extras = measure_extras(b, dx, dy, dz, ds, doff, stream, prec)
+        extras = measure_extras(b, dx, dy, dz, ds, doff, stream, prec, geo, evs)
         extras["batched_with_pcie"] = e2e
 
     # ---------------- served path: Poisson streams of PU-varying events with

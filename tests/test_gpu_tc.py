@@ -205,3 +205,49 @@ def test_tc_batched_equals_per_event(env):
         marg, viol = _classify(diff, ev, r, sds[e].params, opt, res) if diff else (0, 0)
         _say(f"batched event {e}: TCs {len(got)} / {len(ref)} marginal {marg} violation {viol}")
         assert viol == 0
+
+
+def test_tc_benchmark_batch_sampled(env):
+    """The 64-event benchmark batch (build in DNN mode, FP32 scores) with
+    seeds for every event and one selection call: the three events with the
+    fewest hits are compared with the oracle in full, and every event's TC
+    counts satisfy the structural bounds (pT5 + pT3 + pLS = seeds, pT5 + T5
+    before removal = T5s)."""
+    from paper_2403_13166_amd.runtime import TC_OPTIONS, select_tcs
+    from oracle import tc as TC
+    geo, mdl, b, og, om = env
+    rng = E.event_rng(2, 0)
+    evs = [E.make_event(geo, E.batch_event_config(rng), (2, 0, e)) for e in range(64)]
+    sds = [S.make_seeds(geo, e, E.event_rng(5, i), eff=0.9, fake_frac=0.05) for i, e in enumerate(evs)]
+    x, y, z, s, off = E.concat_events(evs)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(b.device)
+    dx, dy, dz, ds, doff = T(x), T(y), T(z), T(s), T(off)
+    objs = b.build(dx, dy, dz, ds, event_offsets=doff)
+    sp, soff = S.concat_seeds(sds)
+    tcs = select_tcs(b, dx, dy, dz, objs, T(sp), T(soff))
+    _say("benchmark batch TCs: kept per kind", tcs.counts[:4], "before removal", tcs.counts[5],
+         "seeds", len(sp), "T5", objs.counts()[3])
+    h = objs.to_host()
+    k5, k3 = _keys_gpu(h)
+    kind, seed, obj = tcs.kind.cpu().numpy(), tcs.seed.cpu().numpy(), tcs.obj.cpu().numpy()
+    # a seed is in at most one kept TC; pLS are never removed
+    used = seed[seed >= 0]
+    assert len(np.unique(used)) == len(used) <= len(sp)
+    eo = h.event_offsets
+    opt = TC.TcOptions(*(TC_OPTIONS[k] for k in TC_OPTIONS))
+    for e in np.argsort([ev.n for ev in evs])[:3]:
+        ev = evs[e]
+        in5 = (obj >= eo[3, e]) & (obj < eo[3, e + 1])
+        in3 = (obj >= eo[2, e]) & (obj < eo[2, e + 1])
+        ins = (seed >= soff[e]) & (seed < soff[e + 1])
+        sel = np.where(kind <= 1, in5, np.where(kind == 2, in3, ins))
+        got = _tc_set(kind[sel], np.where(seed[sel] >= 0, seed[sel] - soff[e], -1), obj[sel], k5, k3, hit0=off[e])
+        r = O_build(og, om, ev)
+        res = _oracle_event(ev, r, sds[e].params, opt)
+        o5, o3 = _keys_orc(r)
+        ref = _tc_set([t[0] for t in res.tcs], [t[1] for t in res.tcs], [t[2] for t in res.tcs], o5, o3)
+        diff = got ^ ref
+        marg, viol = _classify(diff, ev, r, sds[e].params, opt, res) if diff else (0, 0)
+        _say(f"benchmark batch event {e} ({ev.n} hits): TCs {len(got)} / {len(ref)} marginal {marg} "
+             f"violation {viol}")
+        assert viol == 0
