@@ -38,16 +38,14 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE, WRITE_SIZE, each scaled by the counts of a plain 512 MiB
 # elementwise kernel), kept with the hash of the kernel sources they were
 # taken on: a changed kernel reports null until it is measured again.
-MEASURED_TRAFFIC = {
-    ("ls stage", 8): {"bytes": 234035314.1, "source_sha1": "271eda82f324af414d58440acac96e9cfa6cc28a"},
-}
+MEASURED_TRAFFIC = {}
 KERNEL_SOURCES = ("paper_2403_13166_amd/csrc/lst_pipeline.hip", "paper_2403_13166_amd/csrc/lst_device.h",
                   "paper_2403_13166_amd/csrc/lst_internal.h")
 
 
-def measured_traffic(kernel: str, tile: int):
+def measured_traffic(kernel: str):
     import hashlib
-    rec = MEASURED_TRAFFIC.get((kernel, tile))
+    rec = MEASURED_TRAFFIC.get(kernel)
     if rec is None:
         return None
     h = hashlib.sha1()
@@ -115,11 +113,13 @@ def stage_bytes(c, n_hits, n_ev, n_mod, n_sens):
     }
 
 
-def implementation_bytes(n_ev, n_map):
+def implementation_bytes(c):
     """Bytes the build moves beyond the compulsory ones: the LS stage's
-    per-(event, map entry) prefix table of target-MD counts (written once by
-    the prefix kernel and read back by the eval kernel's staging)."""
-    return {"ls_entry_prefix_table": 2 * 4 * n_map * n_ev}
+    (A, B, rank) records (16 B, written by the eval kernel and read by the
+    placement kernel) and its per-MD segment counts (4 B written, read by the
+    scan)."""
+    md, ls = c[0], c[1]
+    return {"ls_records": 2 * 16 * ls, "ls_counts": 2 * 4 * md}
 
 
 def _time_ms(fn, stream, reps=10):
@@ -444,13 +444,11 @@ def main():
     dom = max(kern, key=kern.get)
     sb = stage_bytes(final, len(x), a.events, geo.n_modules, geo.n_sensors)
     achieved = sb[dom] / (avg[dom] * 1e-3) / 1e9
-    stage_idx = {"md": 0, "ls": 1, "t3": 2, "t5": 4}
-    tile = tuned["tile_per"][stage_idx[dom]] if dom in stage_idx else None
     roofline = {"bound": "hbm", "kernel": f"{dom} stage eval kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"{dom} stage", tile),
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"{dom} stage"),
                 "algorithmic_bytes_per_launch": sb[dom], "avg_launch_ms": avg[dom]}
     stage_gbs = {k: sb[k] / (avg[k] * 1e-3) / 1e9 for k in kern}
-    # whole stages: count scan, eval, tile scan, copy, CSR fill (LS: and its map prefix)
+    # whole stages: count scan, eval, tile scan, copy, CSR fill (LS: eval, count scan, placement)
     whole = {"bin": avg["bin"], "md": avg["md_all"], "ls": avg["ls_all"], "t3": avg["t3_all"], "t5": avg["t5"],
              "score": avg["score"]}
     stage_whole = {k: {"ms": v, "gb_per_s": sb[k] / (v * 1e-3) / 1e9,
@@ -476,7 +474,7 @@ def main():
         "batch_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "speedup_batched_vs_plain": value / plain_rate,
         "stage_ms": avg, "stage_gbs": stage_gbs, "stage_whole": stage_whole,
-        "algorithmic_bytes": sb, "implementation_bytes": implementation_bytes(a.events, int(geo.map_tgt.shape[0])),
+        "algorithmic_bytes": sb, "implementation_bytes": implementation_bytes(final),
         "objects_per_event": {"md": per_ev[0], "ls": per_ev[1], "t3": per_ev[2], "t5": per_ev[3]},
         "max_candidates_per_stage": int(final[5]), "t5_pre_candidates": int(final[6]),
         "served": served, "extras": extras,

@@ -8,6 +8,9 @@
 namespace lst {
 
 constexpr int kTcPhiBins = 256;           // phi0 bins per event of the object index
+constexpr int kTcEtaBins = 32;            // asinh(cot) bins per event (uniform over +-kTcEtaMax)
+constexpr double kTcEtaMax = 2.6;
+constexpr int kTcBinsPerEvent = kTcPhiBins * kTcEtaBins;
 constexpr int kTcPT5 = 0, kTcT5 = 1, kTcPT3 = 2, kTcPLS = 3, kTcT3 = 4;   // kTcT3: MD list of a T3
 constexpr int kTcCounts = 8;              // out counts: kept per kind (0-3), kept, before removal
 constexpr int kTcCountKept = 4, kTcCountBefore = 5;
@@ -35,15 +38,15 @@ struct TcWork {
     int32_t *okey;                        // [n5 + n3] (kind, event, phi0 bin) or -1
     uint64_t *obj_best;                   // [n5 + n3] best (chi2, seed) offered
     int32_t *obj_pair;                    // [n5 + n3] paired seed or -1
-    int32_t *bin_cnt, *bin_off, *bin_cur; // [2 n_ev kTcPhiBins (+1)]
+    int32_t *bin_cnt, *bin_off, *bin_cur; // [2 n_ev kTcBinsPerEvent (+1)] (kind, event, eta bin, phi0 bin)
     int32_t *bin_obj;                     // [n5 + n3] objects by bin
     uint64_t *seed_best;                  // [ns] best (chi2, object) of the current pass
     int32_t *seed_pair, *seed_kind;       // [ns] paired object (T5 or T3 index) or -1, its kind
     float *seed_chi2;                     // [ns] chi2 of the pair (FP32)
     int32_t *t3_used;                     // [n3] T3 of a pT5's T5
     int32_t *c_kind, *c_seed, *c_obj;     // [n5 + n3 + ns] TCs before duplicate removal
-    double *c_q;                          //   quality (lower = better)
-    int32_t *c_md;                        //   [5] MDs (-1 padded)
+    int64_t *c_key;                       //   [2] priority key: quality bits, kind << 32 | object
+    int32_t *c_md;                        //   [8] MDs (-1 padded)
     int32_t *c_drop;                      //   removed as a duplicate
     int32_t *md_cnt, *md_cur;             // [n_md] TCs per MD
     int64_t *md_off;                      // [n_md] their list starts

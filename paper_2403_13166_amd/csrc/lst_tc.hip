@@ -65,6 +65,18 @@ __device__ __forceinline__ int event_of(const int64_t *off, int n, int64_t i) {
     return lo;
 }
 
+__device__ __forceinline__ int phi_bin(double phi) {
+    const int b = (int)floor((phi + kPi) * (kTcPhiBins / kTwoPi));
+    return b < 0 ? 0 : (b >= kTcPhiBins ? kTcPhiBins - 1 : b);
+}
+
+// bin of asinh(cot) = pseudorapidity; values beyond +-kTcEtaMax go to the edge bins
+__device__ __forceinline__ int eta_bin(double eta) {
+    const double f = (eta + kTcEtaMax) * (kTcEtaBins / (2.0 * kTcEtaMax));
+    if (!(f >= 0.0)) return 0;
+    return f >= kTcEtaBins ? kTcEtaBins - 1 : (int)f;
+}
+
 __device__ __forceinline__ uint64_t pack(float chi2, int32_t idx) {
     return ((uint64_t)__float_as_uint(chi2) << 32) | (uint32_t)idx;
 }
@@ -120,9 +132,8 @@ __global__ void k_tc_params(TcArgs a, TcWork w) {
                 const bool t5 = i < a.n5;
                 const int64_t *off = t5 ? a.ev_obj + 3 * (a.n_ev + 1) : a.ev_obj + 2 * (a.n_ev + 1);
                 const int e = event_of(off, a.n_ev, t5 ? i : i - a.n5);
-                int b = (int)((phi0 + kPi) * (kTcPhiBins / kTwoPi));
-                b = b < 0 ? 0 : (b >= kTcPhiBins ? kTcPhiBins - 1 : b);
-                key = (t5 ? 0 : a.n_ev * kTcPhiBins) + e * kTcPhiBins + b;
+                key = (t5 ? 0 : a.n_ev * kTcBinsPerEvent) + e * kTcBinsPerEvent +
+                      eta_bin(asinh(cot)) * kTcPhiBins + phi_bin(phi0);
                 atomicAdd(&w.bin_cnt[key], 1);
             }
         }
@@ -130,34 +141,6 @@ __global__ void k_tc_params(TcArgs a, TcWork w) {
         w.okey[i] = key;
         w.obj_best[i] = kNone;
         w.obj_pair[i] = -1;
-    }
-}
-
-// Exclusive scan of n counts in one block (n = 2 n_ev bins, small).
-__global__ void k_tc_scan_bins(const int32_t *cnt, int64_t n, int32_t *off, int32_t *cur) {
-    __shared__ int32_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t b0 = t * per, b1 = b0 + per < n ? b0 + per : n;
-    int32_t s = 0;
-    for (int64_t i = b0; i < b1; ++i) s += cnt[i];
-    part[t] = s;
-    __syncthreads();
-    if (t == 0) {
-        int32_t run = 0;
-        for (int i = 0; i < 1024; ++i) {
-            const int32_t v = part[i];
-            part[i] = run;
-            run += v;
-        }
-        off[n] = run;
-    }
-    __syncthreads();
-    int32_t run = part[t];
-    for (int64_t i = b0; i < b1; ++i) {
-        off[i] = run;
-        cur[i] = 0;
-        run += cnt[i];
     }
 }
 
@@ -190,8 +173,9 @@ __global__ void k_tc_match(TcArgs a, TcWork w) {
             const double oz = (double)a.opt.sigma_z0 * a.opt.sigma_z0;
             const double cmax = a.opt.chi2_max;
             const int e = event_of(a.seed_off, a.n_ev, s);
-            // the window in phi0: chi2 >= dphi^2 / (sigma_p^2 + sigma_o^2)
+            // windows in phi0 and cot: chi2 >= d^2 / (sigma_p^2 + sigma_o^2) for each parameter
             const double hw = sqrt(cmax * (wphi + ophi)) * (1.0 + 1e-9) + 1e-12;
+            const double hc = sqrt(cmax * (wc + oc)) * (1.0 + 1e-9) + 1e-12;
             int b0 = 0, nb = kTcPhiBins;
             if (hw < kPi) {
                 b0 = (int)floor((sphi - hw + kPi) * (kTcPhiBins / kTwoPi));
@@ -199,17 +183,22 @@ __global__ void k_tc_match(TcArgs a, TcWork w) {
                 nb = b1 - b0 + 1;
                 if (nb > kTcPhiBins) nb = kTcPhiBins;
             }
-            const int kbase = (T3 ? a.n_ev * kTcPhiBins : 0) + e * kTcPhiBins;
+            const int c0 = eta_bin(asinh(sc - hc)), c1 = eta_bin(asinh(sc + hc));
+            const int ebase = (T3 ? a.n_ev * kTcBinsPerEvent : 0) + e * kTcBinsPerEvent;
+            for (int cb = c0; cb <= c1; ++cb)
             for (int j = 0; j < nb; ++j) {
                 int b = (b0 + j) % kTcPhiBins;
                 if (b < 0) b += kTcPhiBins;
-                const int key = kbase + b;
+                const int key = ebase + cb * kTcPhiBins + b;
                 for (int32_t q = w.bin_off[key]; q < w.bin_off[key + 1]; ++q) {
                     const int32_t o = w.bin_obj[q];
                     if (T3 && w.t3_used[o - a.n5]) continue;
                     const double4 P = w.par[o];
                     const double ok = (double)a.opt.sigma_kappa_rel * fabs(P.x) + a.opt.sigma_kappa_abs;
-                    const double dk = sk - P.x, dp = wrap_pi(sphi - P.y), dc = sc - P.z, dz = sz - P.w;
+                    double dp = sphi - P.y;   // both in (-pi, pi]: one turn at most
+                    if (dp > kPi) dp -= kTwoPi;
+                    else if (dp <= -kPi) dp += kTwoPi;
+                    const double dk = sk - P.x, dc = sc - P.z, dz = sz - P.w;
                     const double chi2 = dk * dk / (wk + ok * ok) + dp * dp / (wphi + ophi) + dc * dc / (wc + oc) +
                                         dz * dz / (wz + oz);
                     if (!(chi2 <= cmax)) continue;
@@ -305,10 +294,11 @@ struct TcCand {
             const float sc = a.t5_score[obj];
             q = isfinite(sc) ? -(double)sc : (double)a.t5_chi2_rphi[obj];
         }
-        w.c_q[pos] = q;
-        int32_t m[5];
+        *(int4 *)&w.c_key[2 * pos] = make_int4(__double2loint(q), __double2hiint(q), obj, kind);
+        int32_t m[5] = {-1, -1, -1, -1, -1};
         const int nm = kind == kTcPLS ? 0 : obj_mds(a, kind == kTcPT3 ? kTcT3 : kTcT5, obj, m);
-        for (int k = 0; k < 5; ++k) w.c_md[5 * pos + k] = k < nm ? m[k] : -1;
+        *(int4 *)&w.c_md[8 * pos] = make_int4(m[0], nm > 1 ? m[1] : -1, nm > 2 ? m[2] : -1, nm > 3 ? m[3] : -1);
+        *(int4 *)&w.c_md[8 * pos + 4] = make_int4(nm > 4 ? m[4] : -1, -1, -1, -1);
         w.c_drop[pos] = 0;
         for (int k = 0; k < nm; ++k) atomicAdd(&w.md_cnt[m[k]], 1);
     }
@@ -326,7 +316,19 @@ struct TcKept {
             w.out_seed[pos] = w.c_seed[u];
             w.out_obj[pos] = w.c_obj[u];
         }
-        atomicAdd((unsigned long long *)&w.out_counts[w.c_kind[u]], 1ull);
+    }
+};
+
+// Offsets of the object bins (and the end entry).
+struct BinOff {
+    TcWork w;
+    int64_t n;
+    __device__ __forceinline__ int64_t size() const { return n; }
+    __device__ __forceinline__ int value(int64_t i) const { return w.bin_cnt[i]; }
+    __device__ __forceinline__ void put(int64_t i, int64_t pos) const {
+        w.bin_off[i] = (int32_t)pos;
+        w.bin_cur[i] = 0;
+        if (i == n - 1) w.bin_off[n] = (int32_t)(pos + w.bin_cnt[i]);
     }
 };
 
@@ -436,7 +438,7 @@ __global__ void k_tc_incidence(TcWork w) {
     const int64_t n = w.n_cand[0];
     for (int64_t u = gtid(); u < n; u += gstride()) {
         for (int k = 0; k < 5; ++k) {
-            const int32_t m = w.c_md[5 * u + k];
+            const int32_t m = w.c_md[8 * u + k];
             if (m < 0) break;
             const int32_t p = atomicAdd(&w.md_cur[m], 1);
             w.md_tc[w.md_off[m] + p] = (int32_t)u;
@@ -444,42 +446,94 @@ __global__ void k_tc_incidence(TcWork w) {
     }
 }
 
-__device__ __forceinline__ bool tc_before(const TcWork &w, int64_t j, int64_t i) {
-    // priority of TC j over TC i: kind, then quality, then object index
-    if (w.c_kind[j] != w.c_kind[i]) return w.c_kind[j] < w.c_kind[i];
-    if (w.c_q[j] != w.c_q[i]) return w.c_q[j] < w.c_q[i];
-    return w.c_obj[j] < w.c_obj[i];
+// priority key of a TC: (quality, kind << 32 | object index) in 16 bytes
+__device__ __forceinline__ void tc_key(const TcWork &w, int64_t i, double &q, int64_t &ko) {
+    const int4 v = *(const int4 *)&w.c_key[2 * i];
+    q = __hiloint2double(v.y, v.x);
+    ko = ((int64_t)v.w << 32) | (uint32_t)v.z;
 }
 
-__global__ void k_tc_dups(TcWork w) {
+// priority of key j over key i: kind, then quality, then object index
+__device__ __forceinline__ bool key_before(double qj, int64_t koj, double qi, int64_t koi) {
+    const int64_t kj = koj >> 32, ki = koi >> 32;
+    if (kj != ki) return kj < ki;
+    if (qj != qi) return qj < qi;
+    return koj < koi;
+}
+
+// 16 lanes per TC walk the incidence lists of its MDs together; a candidate
+// j is compared only when it has priority over i.
+constexpr int kDupLanes = 16;
+__global__ __launch_bounds__(kTcBlock) void k_tc_dups(TcWork w) {
     const int64_t n = w.n_cand[0];
-    for (int64_t i = gtid(); i < n; i += gstride()) {
-        int32_t mi[5];
-        int ni = 0;
-        for (int k = 0; k < 5; ++k) {
-            mi[k] = w.c_md[5 * i + k];
-            ni += mi[k] >= 0;
-        }
+    const int lane = threadIdx.x & 63, gl = threadIdx.x & (kDupLanes - 1);
+    const int64_t g0 = ((int64_t)blockIdx.x * kTcBlock + threadIdx.x) / kDupLanes;
+    const int64_t gs = (int64_t)gridDim.x * kTcBlock / kDupLanes;
+    for (int64_t i = g0; i < n; i += gs) {
+        const int4 ma = *(const int4 *)&w.c_md[8 * i], mb = *(const int4 *)&w.c_md[8 * i + 4];
+        const int32_t mi[5] = {ma.x, ma.y, ma.z, ma.w, mb.x};
+        const int ni = (ma.x >= 0) + (ma.y >= 0) + (ma.z >= 0) + (ma.w >= 0) + (mb.x >= 0);
+        // the incidence lists of MDs 0..4 as one sequence of tot entries
+        // (MD slots are filled from the front: a -1 ends the list)
+        const int64_t o0 = ma.x >= 0 ? w.md_off[ma.x] : 0, o1 = ma.y >= 0 ? w.md_off[ma.y] : 0;
+        const int64_t o2 = ma.z >= 0 ? w.md_off[ma.z] : 0, o3 = ma.w >= 0 ? w.md_off[ma.w] : 0;
+        const int64_t o4 = mb.x >= 0 ? w.md_off[mb.x] : 0;
+        const int e1 = ma.x >= 0 ? w.md_cnt[ma.x] : 0;
+        const int e2 = e1 + (ma.y >= 0 ? w.md_cnt[ma.y] : 0);
+        const int e3 = e2 + (ma.z >= 0 ? w.md_cnt[ma.z] : 0);
+        const int e4 = e3 + (ma.w >= 0 ? w.md_cnt[ma.w] : 0);
+        int tot = e4 + (mb.x >= 0 ? w.md_cnt[mb.x] : 0);
+        double qi;
+        int64_t koi;
+        tc_key(w, i, qi, koi);
+        // a TC only loses to a kind at least as long: a pT5 / T5 (5 MDs) to
+        // one sharing 3 of them, so to one in the lists of its first 3 MDs; a
+        // pT3 (3 MDs) to one sharing 2, so to one in the lists of its first 2
+        tot = (koi >> 32) <= kTcT5 ? e3 : e2;
         bool drop = false;
-        for (int k = 0; k < ni && !drop; ++k) {
-            const int32_t m = mi[k];
-            const int64_t q1 = w.md_off[m] + w.md_cnt[m];
-            for (int64_t q = w.md_off[m]; q < q1 && !drop; ++q) {
-                const int32_t j = w.md_tc[q];
-                if (j == i) continue;
-                int nj = 0, shared = 0;
-                for (int l = 0; l < 5; ++l) {
-                    const int32_t mj = w.c_md[5 * (int64_t)j + l];
-                    if (mj < 0) break;
-                    ++nj;
-                    for (int r = 0; r < ni; ++r) shared += mj == mi[r];
-                }
-                const int nmin = ni < nj ? ni : nj;
-                if (2 * shared > nmin && tc_before(w, j, i)) drop = true;
+        for (int t = gl; t < tot && !drop; t += kDupLanes) {
+            const int64_t src = t < e1 ? o0 + t : t < e2 ? o1 + (t - e1) : t < e3 ? o2 + (t - e2)
+                              : t < e4 ? o3 + (t - e3) : o4 + (t - e4);
+            const int32_t j = w.md_tc[src];
+            if (j == i) continue;
+            double qj;
+            int64_t koj;
+            tc_key(w, j, qj, koj);
+            if (!key_before(qj, koj, qi, koi)) continue;
+            const int4 ja = *(const int4 *)&w.c_md[8 * (int64_t)j], jb = *(const int4 *)&w.c_md[8 * (int64_t)j + 4];
+            const int32_t mj[5] = {ja.x, ja.y, ja.z, ja.w, jb.x};
+            int nj = 0, shared = 0;
+            for (int l = 0; l < 5; ++l) {
+                if (mj[l] < 0) continue;
+                ++nj;
+                for (int q = 0; q < ni; ++q) shared += mj[l] == mi[q];
             }
+            const int nmin = ni < nj ? ni : nj;
+            if (2 * shared > nmin) drop = true;
         }
-        w.c_drop[i] = drop ? 1 : 0;
+        const unsigned long long bal = __ballot(drop);
+        const unsigned long long gmask = ((1ull << kDupLanes) - 1) << (lane & ~(kDupLanes - 1));
+        if (gl == 0) w.c_drop[i] = (bal & gmask) ? 1 : 0;
     }
+}
+
+// Kept TCs per kind: block sums, one atomic add per block and kind.
+__global__ __launch_bounds__(kTcBlock) void k_tc_kind_counts(TcWork w) {
+    __shared__ unsigned long long cnt[4];
+    if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t n = w.n_cand[0];
+    unsigned long long c[4] = {0, 0, 0, 0};
+    for (int64_t u = gtid(); u < n; u += gstride())
+        if (!w.c_drop[u]) ++c[w.c_kind[u] & 3];
+    for (int k = 0; k < 4; ++k) {
+        unsigned long long v = c[k];
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+        if ((threadIdx.x & 63) == 0 && v) atomicAdd(&cnt[k], v);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && cnt[threadIdx.x])
+        atomicAdd((unsigned long long *)&w.out_counts[threadIdx.x], cnt[threadIdx.x]);
 }
 
 __global__ void k_tc_zero(TcWork w, int64_t n_md) {
@@ -527,8 +581,9 @@ size_t tc_layout(const TcSizes &z, char *base, TcWork *w) {
         off += (bytes + 255) & ~(size_t)255;
         return p;
     };
-    const int64_t no = z.n5 + z.n3, nc = z.n5 + z.n3 + z.ns, nbins = 2 * (int64_t)z.n_ev * kTcPhiBins;
-    const int64_t nscan = 2 * z.n5 + z.n3 + z.ns > z.n_md ? 2 * z.n5 + z.n3 + z.ns : z.n_md;
+    const int64_t no = z.n5 + z.n3, nc = z.n5 + z.n3 + z.ns, nbins = 2 * (int64_t)z.n_ev * kTcBinsPerEvent;
+    int64_t nscan = 2 * z.n5 + z.n3 + z.ns > z.n_md ? 2 * z.n5 + z.n3 + z.ns : z.n_md;
+    nscan = nscan > nbins ? nscan : nbins;
     TcWork x{};
     x.par = (double4 *)take(sizeof(double4) * (no + 1));
     x.okey = (int32_t *)take(4 * (no + 1));
@@ -546,8 +601,8 @@ size_t tc_layout(const TcSizes &z, char *base, TcWork *w) {
     x.c_kind = (int32_t *)take(4 * (nc + 1));
     x.c_seed = (int32_t *)take(4 * (nc + 1));
     x.c_obj = (int32_t *)take(4 * (nc + 1));
-    x.c_q = (double *)take(8 * (nc + 1));
-    x.c_md = (int32_t *)take(20 * (nc + 1));
+    x.c_key = (int64_t *)take(16 * (nc + 1));
+    x.c_md = (int32_t *)take(32 * (nc + 1));
     x.c_drop = (int32_t *)take(4 * (nc + 1));
     x.md_cnt = (int32_t *)take(4 * (z.n_md + 1));
     x.md_off = (int64_t *)take(8 * (z.n_md + 1));
@@ -567,13 +622,12 @@ hipError_t run_tc(const TcArgs &a0, const TcWork &w0, hipStream_t st) {
         hipLaunchKernelGGL(k_tc_single_off, dim3(1), dim3(64), 0, st, w.ev_single, a.n_md, a.n_ls, a.n3, a.n5);
         a.ev_obj = w.ev_single;
     }
-    const int64_t no = a.n5 + a.n3, nbins = 2 * (int64_t)a.n_ev * kTcPhiBins;
+    const int64_t no = a.n5 + a.n3, nbins = 2 * (int64_t)a.n_ev * kTcBinsPerEvent;
     hipLaunchKernelGGL(k_tc_zero_bins, dim3(grid_of(nbins)), dim3(kTcBlock), 0, st, w, nbins);
     hipLaunchKernelGGL(k_tc_zero, dim3(grid_of(a.n_md)), dim3(kTcBlock), 0, st, w, a.n_md);
     hipLaunchKernelGGL(k_tc_seed_init, dim3(grid_of(a.ns > a.n3 ? a.ns : a.n3)), dim3(kTcBlock), 0, st, a, w);
     hipLaunchKernelGGL(k_tc_params, dim3(grid_of(no)), dim3(kTcBlock), 0, st, a, w);
-    hipLaunchKernelGGL(k_tc_scan_bins, dim3(1), dim3(1024), 0, st, (const int32_t *)w.bin_cnt, nbins, w.bin_off,
-                       w.bin_cur);
+    compact(BinOff{w, nbins}, nbins, w.blk, nullptr, st);
     hipLaunchKernelGGL(k_tc_bin_scatter, dim3(grid_of(no)), dim3(kTcBlock), 0, st, a, w);
     // steps 5 and 7: pT5, then pT3 among what is left
     hipLaunchKernelGGL(k_tc_match<false>, dim3(grid_of(a.ns, 64)), dim3(64), 0, st, a, w);
@@ -587,8 +641,9 @@ hipError_t run_tc(const TcArgs &a0, const TcWork &w0, hipStream_t st) {
     compact(MdOff{a, w}, a.n_md, w.blk, nullptr, st);
     const int64_t nc = a.n5 + a.n3 + a.ns;
     hipLaunchKernelGGL(k_tc_incidence, dim3(grid_of(nc)), dim3(kTcBlock), 0, st, w);
-    hipLaunchKernelGGL(k_tc_dups, dim3(grid_of(nc)), dim3(kTcBlock), 0, st, w);
+    hipLaunchKernelGGL(k_tc_dups, dim3(grid_of(nc * kDupLanes)), dim3(kTcBlock), 0, st, w);
     compact(TcKept{w}, nc, w.blk, nullptr, st);
+    hipLaunchKernelGGL(k_tc_kind_counts, dim3(grid_of(nc < 262144 ? nc : 262144)), dim3(kTcBlock), 0, st, w);
     hipLaunchKernelGGL(k_tc_totals, dim3(1), dim3(64), 0, st, w);
     return hipGetLastError();
 }
