@@ -161,6 +161,25 @@ def measure_extras(b, dx, dy, dz, ds, doff, stream, prec, geo, evs):
         res = {}
         ms = _time_ms(lambda: res.__setitem__("t", select_tcs(b, dx, dy, dz, objs, tsp, tsoff)), stream)
         c = res["t"].counts
+        # the MD/LS graph of Sec. 4 on the same objects: graph building alone,
+        # then graph + edge classifier + components (TCs of >= 3 MDs)
+        from paper_2403_13166_amd.runtime import graph_tcs
+        gclf = EdgeClassifier(SG.make_gnn_model().to_blob(), dev.index or 0)
+        n_md, n_ls = objs.counts()[:2]
+        gf = torch.empty((n_md, 7), dtype=torch.float32, device=dev)
+        gs = torch.empty(n_ls, dtype=torch.int32, device=dev)
+        gd = torch.empty(n_ls, dtype=torch.int32, device=dev)
+        gob = B.LstObjects(objs.md_hits.data_ptr(), objs.ls_md.data_ptr(), None, None, None, None, None, None,
+                           None, n_md, n_ls, 0, 0)
+        ghits = B.LstHits(dx.data_ptr(), dy.data_ptr(), dz.data_ptr(), ds.data_ptr(), int(dx.shape[0]))
+        ms_g = _time_ms(lambda: B.lst_md_graph(b.ctx, ghits, gob, gf.data_ptr(), gs.data_ptr(), gd.data_ptr(),
+                                               stream.cuda_stream), stream)
+        gres = {}
+        ms_p = _time_ms(lambda: gres.__setitem__("r", graph_tcs(b, gclf, dx, dy, dz, ds, objs)), stream)
+        out["md_ls_graph"] = {"graph_build_ms": ms_g, "graph_classify_components_ms": ms_p, "nodes": int(n_md),
+                              "edges": int(n_ls), "tcs_min3": int(gres["r"].n_tc),
+                              "note": "untrained classifier weights: the TC count shows the pipeline, not a physics figure"}
+        gclf.close()
         out["tc_selection"] = {"ms": ms, "seeds": int(len(sp)), "t5": int(objs.counts()[3]),
                                "t3": int(objs.counts()[2]), "kept": {k: int(v) for k, v in zip(B.TC_KINDS, c[:4])},
                                "before_duplicate_removal": int(c[5]),

@@ -294,6 +294,31 @@ lst_status lst_gnn_score(lst_ctx *ctx, const float *x_dev, int64_t n_nodes, cons
                          const int32_t *dst_dev, int64_t n_edges, float *scores_dev, void *workspace,
                          size_t ws_bytes, int32_t flags, void *stream);
 
+/* The graph Sec. 4 proposes building with LST: MDs as nodes, LSs as edges.
+ * From a completed build (host counts filled): features_dev [n_md][7] FP32
+ * per MD, all local to it: r_A / 100, phi_A / pi, z_A / 100 (anchor hit A,
+ * cm), 10 alpha (angle from the radial direction at the chord midpoint to the
+ * chord towards the other hit, transverse plane), asinh(dz / dr) of the chord
+ * clipped to [-5, 5], is_endcap, layer / 11; src_dev / dst_dev int32 [n_ls]:
+ * LS (inner a, outer b) as the edge b -> a, so dst is sorted ascending as
+ * lst_gnn_score requires. The paper fixes no features; these are the
+ * library's. Asynchronous on `stream`; LST_E_STATE without a geometry. */
+lst_status lst_md_graph(lst_ctx *ctx, const lst_hits *hits, const lst_objects *objects, float *features_dev,
+                        int32_t *src_dev, int32_t *dst_dev, void *stream);
+
+/* Track candidates read off the classified graph (Sec. 4: a GNN on the
+ * LST-built graph "to produce TCs"; the paper gives no rule, the library's
+ * is): the connected components of the edges with score >= threshold,
+ * labels_dev [n_nodes] = the smallest node index of each node's component;
+ * *n_tc_dev (device int64) = the number of components with at least min_mds
+ * nodes. Synchronises; LST_E_INVAL when an edge's node id is out of range
+ * (such edges are skipped, the rest is still labelled). */
+lst_status lst_graph_components_workspace_size(const lst_ctx *ctx, int64_t n_nodes, size_t *bytes);
+lst_status lst_graph_components(lst_ctx *ctx, int64_t n_nodes, const int32_t *src_dev, const int32_t *dst_dev,
+                                const float *scores_dev, int64_t n_edges, float threshold, int32_t min_mds,
+                                int32_t *labels_dev, int64_t *n_tc_dev, void *workspace, size_t ws_bytes,
+                                void *stream);
+
 /* Launch shapes of the build kernels. They never change results: every stage
  * writes its objects in candidate order whatever the tiling, so a tuning only
  * changes speed (the autotuner in the Python package times them).

@@ -36,7 +36,8 @@ EXPORTED = ("lst_create", "lst_destroy", "lst_load_geometry", "lst_load_model", 
             "lst_build_objects", "lst_build_objects_noalloc", "lst_build_objects_batched", "lst_score", "lst_status_string",
             "lst_last_error", "lst_set_timing", "lst_set_fail_stage", "lst_stage_times", "lst_get_tuning",
             "lst_set_tuning",
-            "lst_load_gnn", "lst_gnn_workspace_size", "lst_gnn_score", "lst_tc_workspace_size", "lst_select_tcs")
+            "lst_load_gnn", "lst_gnn_workspace_size", "lst_gnn_score", "lst_tc_workspace_size", "lst_select_tcs",
+            "lst_md_graph", "lst_graph_components_workspace_size", "lst_graph_components")
 
 
 class LstHits(C.Structure):
@@ -152,6 +153,12 @@ def lib():
         L.lst_select_tcs.argtypes = [vp, C.POINTER(LstHits), C.POINTER(LstObjects), vp, i32, C.POINTER(LstSeeds),
                                      C.POINTER(LstTcOptions), C.POINTER(LstTcs), vp, C.c_size_t, vp]
         L.lst_select_tcs.restype = i32
+        L.lst_md_graph.argtypes = [vp, C.POINTER(LstHits), C.POINTER(LstObjects), vp, vp, vp, vp]
+        L.lst_md_graph.restype = i32
+        L.lst_graph_components_workspace_size.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
+        L.lst_graph_components_workspace_size.restype = i32
+        L.lst_graph_components.argtypes = [vp, i64, vp, vp, vp, i64, C.c_float, i32, vp, vp, vp, C.c_size_t, vp]
+        L.lst_graph_components.restype = i32
         L.lst_get_tuning.argtypes = [vp, C.POINTER(LstTuning)]
         L.lst_get_tuning.restype = i32
         L.lst_set_tuning.argtypes = [vp, C.POINTER(LstTuning)]
@@ -311,4 +318,27 @@ def lst_select_tcs(ctx, hits: LstHits, objects: LstObjects, event_obj_offsets_de
                               C.byref(seeds), C.byref(opt), C.byref(out), ws, ws_bytes, stream)
     if check:
         _check(ctx, st, "lst_select_tcs")
+    return st
+
+
+def lst_md_graph(ctx, hits: LstHits, objects: LstObjects, features_dev: int, src_dev: int, dst_dev: int,
+                 stream: int) -> None:
+    _check(ctx, lib().lst_md_graph(ctx, C.byref(hits), C.byref(objects), features_dev, src_dev, dst_dev, stream),
+           "lst_md_graph")
+
+
+def lst_graph_components_workspace_size(ctx, n_nodes: int) -> int:
+    n = C.c_size_t()
+    _check(ctx, lib().lst_graph_components_workspace_size(ctx, int(n_nodes), C.byref(n)),
+           "lst_graph_components_workspace_size")
+    return int(n.value)
+
+
+def lst_graph_components(ctx, n_nodes: int, src_dev: int, dst_dev: int, scores_dev: int, n_edges: int,
+                         threshold: float, min_mds: int, labels_dev: int, n_tc_dev: int, ws: int, ws_bytes: int,
+                         stream: int, check: bool = True) -> int:
+    st = lib().lst_graph_components(ctx, int(n_nodes), src_dev, dst_dev, scores_dev, int(n_edges), float(threshold),
+                                    int(min_mds), labels_dev, n_tc_dev, ws, ws_bytes, stream)
+    if check:
+        _check(ctx, st, "lst_graph_components")
     return st

@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblst.so")
-SOURCES = ["lst_capi.hip", "lst_pipeline.hip", "lst_score.hip", "lst_gnn.hip", "lst_tc.hip"]
+SOURCES = ["lst_capi.hip", "lst_pipeline.hip", "lst_score.hip", "lst_gnn.hip", "lst_tc.hip", "lst_graph.hip"]
 HOST_SOURCES = ["lst_host.cpp"]      # plain C++ (blob parsers), built with the host compiler
 CXX = os.environ.get("CXX", "g++")
 ARCH = os.environ.get("LST_OFFLOAD_ARCH", "gfx950")

@@ -17,6 +17,7 @@
 #include "../../include/lst.h"
 #include "lst_internal.h"
 #include "lst_tc.h"
+#include "lst_graph.h"
 
 using namespace lst;
 
@@ -597,6 +598,58 @@ lst_status lst_select_tcs(lst_ctx *c, const lst_hits *h, const lst_objects *o, c
     if (out->n > out->cap)
         return fail(c, LST_E_CAPACITY, "%lld track candidates kept, capacity %lld", (long long)out->n,
                     (long long)out->cap);
+    return LST_OK;
+}
+
+lst_status lst_md_graph(lst_ctx *c, const lst_hits *h, const lst_objects *o, float *features, int32_t *src,
+                        int32_t *dst, void *stream) {
+    if (!c) return LST_E_INVAL;
+    if (!c->geom_loaded) return fail(c, LST_E_STATE, "load a geometry first");
+    if (!h || !o) return fail(c, LST_E_INVAL, "null argument");
+    if (o->n_md < 0 || o->n_ls < 0 || o->n_md > INT32_MAX || o->n_ls > INT32_MAX)
+        return fail(c, LST_E_INVAL, "bad object counts");
+    if (o->n_md > 0 && (!h->x || !h->y || !h->z || !h->sensor || !o->md_hits || !features))
+        return fail(c, LST_E_INVAL, "null hit, MD or feature array");
+    if (o->n_ls > 0 && (!o->ls_md || !src || !dst)) return fail(c, LST_E_INVAL, "null LS or edge array");
+    if (o->n_md == 0 && o->n_ls == 0) return LST_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    GraphArgs a{};
+    a.x = h->x; a.y = h->y; a.z = h->z; a.sensor = h->sensor;
+    a.md_hits = (const int2 *)o->md_hits; a.ls_md = (const int2 *)o->ls_md; a.mod = c->d_mod;
+    a.n_md = o->n_md; a.n_ls = o->n_ls;
+    a.feat = features; a.src = src; a.dst = dst;
+    HIP_TRY(c, run_md_graph(a, (hipStream_t)stream));
+    return LST_OK;
+}
+
+lst_status lst_graph_components_workspace_size(const lst_ctx *c, int64_t n_nodes, size_t *bytes) {
+    if (!c || !bytes || n_nodes < 0 || n_nodes > INT32_MAX) return LST_E_INVAL;
+    *bytes = components_workspace(n_nodes);
+    return LST_OK;
+}
+
+lst_status lst_graph_components(lst_ctx *c, int64_t n_nodes, const int32_t *src, const int32_t *dst,
+                                const float *scores, int64_t n_edges, float threshold, int32_t min_mds,
+                                int32_t *labels, int64_t *n_tc, void *ws, size_t ws_bytes, void *stream) {
+    if (!c) return LST_E_INVAL;
+    if (n_nodes < 0 || n_nodes > INT32_MAX || n_edges < 0) return fail(c, LST_E_INVAL, "bad graph size");
+    if (!n_tc || (n_nodes > 0 && !labels) || (n_edges > 0 && (!src || !dst || !scores)))
+        return fail(c, LST_E_INVAL, "null graph array");
+    if (!isfinite(threshold)) return fail(c, LST_E_INVAL, "threshold must be finite");
+    if (min_mds < 1) return fail(c, LST_E_INVAL, "min_mds must be at least 1");
+    if (((uintptr_t)ws & 255) != 0) return fail(c, LST_E_INVAL, "workspace must be 256-byte aligned");
+    const size_t need = components_workspace(n_nodes);
+    if (ws_bytes < need) return fail(c, LST_E_INVAL, "workspace %zu bytes, need %zu", ws_bytes, need);
+    HIP_TRY(c, hipSetDevice(c->device));
+    ComponentsArgs a = components_layout((char *)ws, n_nodes);
+    a.src = src; a.dst = dst; a.scores = scores; a.n_nodes = n_nodes; a.n_edges = n_edges;
+    a.threshold = threshold; a.min_mds = min_mds; a.labels = labels; a.n_tc = n_tc;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, run_components(a, st));
+    int64_t err = 0;
+    HIP_TRY(c, hipMemcpyAsync(&err, a.err, sizeof(err), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (err) return fail(c, LST_E_INVAL, "an edge's node id is out of range (those edges were skipped)");
     return LST_OK;
 }
 

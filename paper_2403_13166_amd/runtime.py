@@ -353,3 +353,38 @@ def select_tcs(builder: Builder, x, y, z, objects: Objects, seeds: torch.Tensor,
                      torch.cuda.current_stream(dev).cuda_stream)
     n = int(out.n)
     return Tcs(kind[:n], seed[:n], obj[:n], counts.cpu().tolist()[:6])
+
+
+@dataclass
+class GraphTcs:
+    features: torch.Tensor    # [n_md, 7] float32 node features
+    src: torch.Tensor         # [n_ls] int32 edge sources (outer MD)
+    dst: torch.Tensor         # [n_ls] int32 edge targets (inner MD, ascending)
+    scores: torch.Tensor      # [n_ls] float32 edge scores
+    labels: torch.Tensor      # [n_md] int32 component label (smallest MD index)
+    n_tc: int                 # components with at least min_mds MDs
+
+
+def graph_tcs(builder: Builder, classifier: "EdgeClassifier", x, y, z, sensor, objects: Objects,
+              threshold: float = 0.5, min_mds: int = 3) -> GraphTcs:
+    """Sec. 4's pipeline on a completed build: the MD/LS graph (lst_md_graph),
+    edge scores (lst_gnn_score) and track candidates as components of the
+    kept edges (lst_graph_components)."""
+    dev = builder.device
+    n_md, n_ls = objects.counts()[:2]
+    feat = torch.empty((n_md, 7), dtype=torch.float32, device=dev)
+    src = torch.empty(n_ls, dtype=torch.int32, device=dev)
+    dst = torch.empty(n_ls, dtype=torch.int32, device=dev)
+    ob = B.LstObjects(_ptr(objects.md_hits), _ptr(objects.ls_md), None, None, None, None, None, None, None,
+                      n_md, n_ls, 0, 0)
+    hits = B.LstHits(_ptr(x), _ptr(y), _ptr(z), _ptr(sensor), int(x.shape[0]))
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    B.lst_md_graph(builder.ctx, hits, ob, feat.data_ptr(), src.data_ptr(), dst.data_ptr(), stream)
+    scores = classifier.score(feat, src, dst)
+    labels = torch.empty(n_md, dtype=torch.int32, device=dev)
+    n_tc = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws_bytes = B.lst_graph_components_workspace_size(builder.ctx, n_md)
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    B.lst_graph_components(builder.ctx, n_md, src.data_ptr(), dst.data_ptr(), scores.data_ptr(), n_ls, threshold,
+                           min_mds, labels.data_ptr(), n_tc.data_ptr(), (ws.data_ptr() + 255) & ~255, ws_bytes, stream)
+    return GraphTcs(feat, src, dst, scores, labels, int(n_tc.item()))
