@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=None,
-                    help='fixed launch shapes as JSON {"bin_split", "tile_per": [5], "eval_blocks"} (no autotuning)')
+                    help='fixed launch shapes as JSON {"bin_split", "tile_per": [5], "eval_blocks", "t3_masks"} (no autotuning)')
     ap.add_argument("--plain-events", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
@@ -119,9 +119,12 @@ def implementation_bytes(c):
     """Bytes the build moves beyond the compulsory ones: the LS stage's
     (A, B, rank) records (16 B, written by the eval kernel and read by the
     placement kernel) and its per-MD segment counts (4 B written, read by the
-    scan)."""
+    scan); the T3 stage's candidate range of every inner LS (8 B written by
+    the count kernel, read by the write kernel) and first T3 position of
+    every inner LS (8 B written, read by the CSR kernel)."""
     md, ls = c[0], c[1]
-    return {"ls_records": 2 * 16 * ls, "ls_counts": 2 * 4 * md}
+    return {"ls_records": 2 * 16 * ls, "ls_counts": 2 * 4 * md, "t3_ranges": 2 * 8 * ls,
+            "t3_positions": 2 * 8 * ls}
 
 
 def _time_ms(fn, stream, reps=10):

@@ -326,18 +326,23 @@ lst_status lst_graph_components(lst_ctx *ctx, int64_t n_nodes, const int32_t *sr
  *                block in LDS (1..64; raised at launch to the number of ranges
  *                of at most 1024 sensor ids that cover the geometry);
  *   tile_per[s]  candidates per thread of a 256-thread compaction tile, for
- *                stage s = 0 MD {2,4,8}, 2 T3 {1,2,4}, 3 T5 FP32 pre-cuts
- *                {1,2,4}, 4 T5 FP64 fits {1,2}; entry 1 is accepted with
- *                {2,4,8} and has no effect (the line-segment stage runs one
- *                inner MD per lane, without compaction tiles);
- *   eval_blocks  blocks of the compaction kernels (256..8192).
- * Defaults: {4, {4, 8, 2, 2, 1}, 8192}. lst_set_tuning(ctx, NULL) restores
+ *                stage s = 0 MD {2,4,8}, 3 T5 FP32 pre-cuts {1,2,4}, 4 T5
+ *                FP64 fits {1,2}; entries 1 ({2,4,8}) and 2 ({1,2,4}) are
+ *                accepted and have no effect (the line-segment and T3 stages
+ *                have no compaction tiles);
+ *   eval_blocks  blocks of the compaction kernels (256..8192);
+ *   t3_masks     pass masks of 64 candidates the T3 stage keeps per
+ *                wavefront of 64 inner LSs (1..8); the T3 of a wavefront
+ *                with more candidates are written by a second kernel that
+ *                evaluates the candidates beyond them again.
+ * Defaults: {4, {4, 8, 2, 2, 1}, 8192, 8}. lst_set_tuning(ctx, NULL) restores
  * them; an unsupported value gives LST_E_INVAL and leaves the tuning as it
  * was. The tuning in force when a build is enqueued (or captured) is used. */
 typedef struct {
     int32_t bin_split;
     int32_t tile_per[5];
     int32_t eval_blocks;
+    int32_t t3_masks;
 } lst_tuning;
 
 lst_status lst_get_tuning(const lst_ctx *ctx, lst_tuning *out);

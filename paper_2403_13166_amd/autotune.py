@@ -4,10 +4,12 @@ Knobs (all exposed through lst_set_tuning; none changes a result):
   * bin_split: sensor-id ranges per event in hit binning, each sorted by one
     block in LDS (the module-bin size);
   * tile_per[s]: candidates per thread of each compaction stage's 256-thread
-    tile (the LDS tile holds the tile's anchor window); the line-segment stage
-    has no compaction tiles (one inner MD per lane), so tile_per[1] is not
+    tile (the LDS tile holds the tile's anchor window); the line-segment and
+    T3 stages have no compaction tiles, so tile_per[1] and tile_per[2] are not
     searched;
-  * eval_blocks: persistent blocks of the compaction kernels.
+  * eval_blocks: persistent blocks of the compaction kernels;
+  * t3_masks: pass masks the T3 stage keeps per wavefront (wavefronts with
+    more candidates go to a second kernel that evaluates the rest again).
 
 Search: coordinate descent. Each knob is timed on the stage window it governs
 (HIP events recorded on the build stream around that stage), the others held
@@ -23,19 +25,21 @@ from . import binding as B
 
 BIN_SPLITS = (1, 48, 64)      # sensor ranges per event (raised to what the geometry needs)
 EVAL_BLOCKS = (1024, 2048, 4096, 8192)
+T3_MASKS = (2, 4, 8)
 # (knob, stage index or None, choices, timing window)
 KNOBS = (
     ("bin_split", None, BIN_SPLITS, "bin"),
     ("tile_per", 0, B.TILE_CHOICES[0], "md"),
-    ("tile_per", 2, B.TILE_CHOICES[2], "t3"),
     ("tile_per", 3, B.TILE_CHOICES[3], "t5"),
     ("tile_per", 4, B.TILE_CHOICES[4], "t5"),
     ("eval_blocks", None, EVAL_BLOCKS, "build"),
+    ("t3_masks", None, T3_MASKS, "t3"),
 )
 
 
 def _with(t: dict, knob: str, idx, v) -> dict:
-    n = {"bin_split": t["bin_split"], "tile_per": list(t["tile_per"]), "eval_blocks": t["eval_blocks"]}
+    n = {"bin_split": t["bin_split"], "tile_per": list(t["tile_per"]), "eval_blocks": t["eval_blocks"],
+         "t3_masks": t.get("t3_masks", B.T3_MASKS_DEFAULT)}
     if idx is None:
         n[knob] = v
     else:

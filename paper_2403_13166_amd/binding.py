@@ -63,10 +63,12 @@ class LstOptions(C.Structure):
 
 
 class LstTuning(C.Structure):
-    _fields_ = [("bin_split", C.c_int32), ("tile_per", C.c_int32 * 5), ("eval_blocks", C.c_int32)]
+    _fields_ = [("bin_split", C.c_int32), ("tile_per", C.c_int32 * 5), ("eval_blocks", C.c_int32),
+                ("t3_masks", C.c_int32)]
 
     def as_dict(self) -> dict:
-        return {"bin_split": self.bin_split, "tile_per": list(self.tile_per), "eval_blocks": self.eval_blocks}
+        return {"bin_split": self.bin_split, "tile_per": list(self.tile_per), "eval_blocks": self.eval_blocks,
+                "t3_masks": self.t3_masks}
 
     @staticmethod
     def from_dict(d: dict) -> "LstTuning":
@@ -75,6 +77,7 @@ class LstTuning(C.Structure):
         for i, v in enumerate(d["tile_per"]):
             t.tile_per[i] = int(v)
         t.eval_blocks = int(d["eval_blocks"])
+        t.t3_masks = int(d.get("t3_masks", T3_MASKS_DEFAULT))
         return t
 
 
@@ -279,6 +282,7 @@ def lst_gnn_score(ctx, x_dev: int, n_nodes: int, src_dev: int, dst_dev: int, n_e
 
 # tile sizes each stage is compiled for (candidates per thread): MD, LS, T3, T5 pre, T5 fit
 TILE_CHOICES = ((2, 4, 8), (2, 4, 8), (1, 2, 4), (1, 2, 4), (1, 2))
+T3_MASKS_DEFAULT = 8
 
 
 def lst_get_tuning(ctx) -> dict:
@@ -288,7 +292,8 @@ def lst_get_tuning(ctx) -> dict:
 
 
 def lst_set_tuning(ctx, tuning: dict | None) -> None:
-    """Set launch shapes ({"bin_split", "tile_per": [5], "eval_blocks"}); None restores the defaults."""
+    """Set launch shapes ({"bin_split", "tile_per": [5], "eval_blocks", "t3_masks"}, t3_masks optional);
+    None restores the defaults."""
     if tuning is None:
         _check(ctx, lib().lst_set_tuning(ctx, None), "lst_set_tuning")
     else:

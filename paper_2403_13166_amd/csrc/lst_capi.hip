@@ -268,6 +268,15 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     x.ls_chunk = (int4 *)take(16 * (k->ls > 0 ? k->ls : 1));
     x.ls_top = (unsigned long long *)take(8);
     x.t3_mds = (int4 *)take(16 * (k->t3 > 0 ? k->t3 : 1));
+    x.t3_wcnt = (int32_t *)take(4 * (k->ls / 64 + 1));
+    x.t3_woff = (int64_t *)take(8 * (k->ls / 64 + 2));
+    x.t3_nw = (int64_t *)take(8);
+    x.t3_pos = (int64_t *)take(8 * (k->ls + 1));
+    x.t3_bits = (unsigned long long *)take(8 * kT3MaxMasks * (k->ls / 64 + 1));
+    x.t3_cn = (int2 *)take(8 * (k->ls > 0 ? k->ls : 1));
+    x.t3_ovf = (int32_t *)take(4 * (k->ls / 64 + 1));
+    x.t3_n_ovf = (unsigned long long *)take(8);
+
     x.t3i_off = (int64_t *)take(8 * (md + 1));
     x.cap_t5pre = k->cand;
     x.t5_pre = (int2 *)take(8 * (k->cand > 0 ? k->cand : 1));
@@ -501,6 +510,7 @@ lst_status lst_get_tuning(const lst_ctx *c, lst_tuning *t) {
     t->bin_split = c->tune.bin_split;
     for (int i = 0; i < kStages; ++i) t->tile_per[i] = c->tune.per[i];
     t->eval_blocks = c->tune.eval_blocks;
+    t->t3_masks = c->tune.t3_masks;
     return LST_OK;
 }
 
@@ -511,10 +521,12 @@ lst_status lst_set_tuning(lst_ctx *c, const lst_tuning *t) {
         n.bin_split = t->bin_split;
         for (int i = 0; i < kStages; ++i) n.per[i] = t->tile_per[i];
         n.eval_blocks = t->eval_blocks;
+        n.t3_masks = t->t3_masks;
     }
     if (!tuning_valid(n))
-        return fail(c, LST_E_INVAL, "unsupported tuning (bin_split %d, tiles %d %d %d %d %d, eval_blocks %d)",
-                    n.bin_split, n.per[0], n.per[1], n.per[2], n.per[3], n.per[4], n.eval_blocks);
+        return fail(c, LST_E_INVAL,
+                    "unsupported tuning (bin_split %d, tiles %d %d %d %d %d, eval_blocks %d, t3_masks %d)",
+                    n.bin_split, n.per[0], n.per[1], n.per[2], n.per[3], n.per[4], n.eval_blocks, n.t3_masks);
     c->tune = n;
     return LST_OK;
 }

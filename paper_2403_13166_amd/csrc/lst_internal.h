@@ -28,11 +28,14 @@ struct Tuning {
     int32_t bin_split;                // sensor ranges (blocks) per event in hit binning, 1..64
     int32_t per[kStages];
     int32_t eval_blocks;              // persistent blocks of the compaction kernels
+    int32_t t3_masks;                 // pass masks kept per wavefront in the T3 stage, 1..kT3MaxMasks
 };
-constexpr Tuning kDefaultTuning = {4, {4, 8, 2, 2, 1}, kEvalBlocks};
+constexpr int kT3MaxMasks = 8;
+constexpr Tuning kDefaultTuning = {4, {4, 8, 2, 2, 1}, kEvalBlocks, kT3MaxMasks};
 inline bool tuning_valid(const Tuning &t) {
     if (t.bin_split < 1 || t.bin_split > 64) return false;
     if (t.eval_blocks < 256 || t.eval_blocks > kMaxStride) return false;
+    if (t.t3_masks < 1 || t.t3_masks > kT3MaxMasks) return false;
     for (int i = 0; i < kStages; ++i) {
         const int v = t.per[i];
         if (v < 1 || v > 8 || (v & (v - 1)) || !(kPerMask[i] & v)) return false;
@@ -74,6 +77,15 @@ struct Work {
     unsigned long long *ls_top;       // [1] records written
     // T3
     int4 *t3_mds;                     // [cap_t3] MDs (A, B, C)
+    int32_t *t3_wcnt;                 // [cap_ls / 64 + 1] T3 per wavefront of inner LSs
+    int64_t *t3_woff;                 // [cap_ls / 64 + 2] their exclusive scan
+    unsigned long long *t3_bits;      // [(cap_ls / 64 + 1) * kT3MaxMasks] pass masks
+    int64_t *t3_nw;                   // [1] wavefronts of the build
+    int64_t *t3_pos;                  // [cap_ls + 1] first T3 position of every inner LS
+    int2 *t3_cn;                      // [cap_ls] candidate range of every inner LS
+    int32_t *t3_ovf;                  // [cap_ls / 64 + 1] wavefronts beyond the kept masks
+    unsigned long long *t3_n_ovf;     // [1] their number
+
     int64_t *t3i_off;                 // [cap_md + 1] T3 by inner MD (they are sorted by it)
     // T5
     int64_t cap_t5pre;

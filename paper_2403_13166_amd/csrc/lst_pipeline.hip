@@ -1508,74 +1508,294 @@ __global__ __launch_bounds__(kBlock) void k_ls_place(LsArgs a, const int64_t *ls
     }
 }
 
-__global__ void k_zero_u64(unsigned long long *p) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+// the LS stage's record counter and the T3 stage's list counter (one launch
+// for both stages)
+__global__ void k_zero_counters(unsigned long long *p, unsigned long long *q) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *p = 0ull;
+        *q = 0ull;
+    }
 }
 
 // ------------------------------------------------------------ T3 stage
-// Anchor: the inner LS (A, B); candidates: every LS starting at B, which the
-// LS output (sorted by inner MD) holds contiguously. T3 come out sorted by
-// inner LS, hence by inner MD A: the next stage reads T3 starting at an MD
-// as one contiguous range. info = {first outer LS, n outer LS, A, B}.
+// T3 come out sorted by inner LS, hence by inner MD A: the next stage reads
+// the T3 starting at an MD as one contiguous range.
+//
+// T3 stage without the tile compaction. A wavefront takes 64 consecutive
+// inner LSs (A, B); the candidates of LS l are the LSs starting at B, a
+// contiguous range of the LS list, and the wavefront's candidates, numbered
+// in (inner LS, candidate) order through an inclusive scan of the per-LS
+// counts, go 64 at a time to its lanes (a lane finds its inner LS by binary
+// search of the scan held in registers). The first kernel counts survivors
+// per wavefront, keeps its first pass masks (a tuning) and every LS's candidate
+// range, and lists the wavefronts with more candidates than the masks cover.
+// After a scan of the counts over wavefronts the second kernel writes every
+// survivor of the other wavefronts at its final place (the wavefront's offset
+// plus the survivors before it) from the masks alone, with every inner LS's
+// first T3 position; a third does the listed wavefronts, evaluating the
+// candidates beyond the masks again; the last turns the positions into the
+// CSR of T3 by inner MD.
+constexpr int kT3Blocks = 4096;           // grid of the count and write kernels (more than the resident blocks)
+constexpr int kT3OvfBlocks = 64;          // grid of the kernel for the listed wavefronts
 
-struct T3Stage {
+struct T3Direct {
     const int2 *ls_md;
     const int64_t *ls_off;        // CSR of LS by inner MD (entries may exceed cap_ls after an overflow)
     int64_t cap_ls;
     const float4 *md_a;
     const float2 *md_o;
     const float2 *md_rq;
-    const ModConst *mod;
     CutParams p;
-    int32_t n_mod;
+    int32_t *wcnt;                // [cap_ls / 64 + 1] survivors per wavefront
+    int64_t *woff;                // [cap_ls / 64 + 2] their exclusive scan
+    unsigned long long *bits;     // [(cap_ls / 64 + 1) * kT3MaxMasks] pass masks
+    int masks;                    // masks kept per wavefront (1..kT3MaxMasks)
+    int64_t *nw;                  // [1] wavefronts of this build
+    int2 *cn;                     // [cap_ls] first candidate and candidate count of every inner LS
+    int32_t *ovf;                 // [cap_ls / 64 + 1] wavefronts with more than 64 masks candidates
+    unsigned long long *n_ovf;    // [1] their number (zeroed before the count kernel)
+    int64_t *pos;                 // [cap_ls + 1] first T3 position of every inner LS
     int2 *t3_ls;
     int4 *t3_mds;
-    static constexpr int kEnt = 0;
-    static constexpr int kStage = 2;
-    static constexpr int kWin = 512;             // anchors staged per tile
-    static constexpr bool kUnitCount = false;
-    static constexpr int kMinBlocks = 8;       // resident blocks per CU the register budget must allow
-    static constexpr int kPhases = 1;            // cut phases (later ones on queued survivors)
-    struct Rec { int li, lo, A, B, C; };
-    struct Mid {};
-
-    __device__ int64_t lsoff(int64_t md) const {
-        const int64_t v = ls_off[md];
-        return v < cap_ls ? v : cap_ls;
-    }
-    __device__ int64_t count(int64_t l1) const {
-        const int B = ls_md[l1].y;
-        return lsoff(B + 1) - lsoff(B);
-    }
-    __device__ void info(int64_t l1, int32_t *f) const {
-        const int2 lm = ls_md[l1];
-        const int64_t o0 = lsoff(lm.y);
-        f[0] = (int32_t)o0; f[1] = (int32_t)(lsoff(lm.y + 1) - o0); f[2] = lm.x; f[3] = lm.y;
-    }
-    template <class LDS>
-    __device__ void prepare(LDS &, int64_t, int) const {}
-    template <class LDS>
-    __device__ bool eval(int64_t l1, int32_t local, const int32_t *f, const LDS &, Rec &r, Mid &) const {
-        const int lo = f[0] + local;
-        const int A = f[2], B = f[3];
-        const int C = ls_md[lo].y;
-        r.li = (int)l1; r.lo = lo; r.A = A; r.B = B; r.C = C;
-        const float4 a = md_a[A], c = md_a[C];
-        const float2 qa = md_rq[A], qc = md_rq[C];
-        float cv, sg;
-        if (!pair_pass_rq(p, P3{a.x, a.y, a.z}, qa, P3{c.x, c.y, c.z}, qc, cv, sg)) return false;
-        if (!signbit(md_rq[B].y)) {                 // barrel middle MD: direction cut
-            const float4 b = md_a[B];
-            const float2 o = md_o[B];
-            if (!md_dir_pass(p, P3{b.x, b.y, b.z}, o.x, o.y, fminf(cv, p.cmax), sg)) return false;
-        }
-        return true;
-    }
-    __device__ void write(int64_t pos, const Rec &r) const {
-        t3_ls[pos] = make_int2(r.li, r.lo);
-        t3_mds[pos] = make_int4(r.A, r.B, r.C, 0);
-    }
+    int64_t cap_t3;
+    int64_t *counts;
 };
+
+__device__ __forceinline__ int64_t t3_lsoff(const T3Direct &d, int64_t md) {
+    const int64_t v = d.ls_off[md];
+    return v < d.cap_ls ? v : d.cap_ls;
+}
+
+// One wavefront's inner LSs: per lane its MDs, first candidate, candidate
+// count and the inclusive scan of the counts.
+struct T3Wave {
+    int64_t l1;
+    bool act;
+    int2 lm;
+    int c0, n, incl, tot;
+    float ax, ay, az, qax, qay, bx, by, bz, obx, oby, qby;
+};
+
+// kCn: the candidate ranges kept by the count kernel instead of the CSR
+template <bool kCn>
+__device__ __forceinline__ T3Wave t3_wave(const T3Direct &d, int64_t w, int64_t n_ls, int lane) {
+    T3Wave v;
+    v.l1 = w * 64 + lane;
+    v.act = v.l1 < n_ls;
+    const int64_t li = v.act ? v.l1 : n_ls - 1;
+    v.lm = d.ls_md[li];
+    if constexpr (kCn) {
+        const int2 cn = d.cn[li];
+        v.c0 = cn.x;
+        v.n = v.act ? cn.y : 0;
+    } else {
+        const int64_t c0 = t3_lsoff(d, v.lm.y);
+        v.c0 = (int)c0;
+        v.n = v.act ? (int)(t3_lsoff(d, v.lm.y + 1) - c0) : 0;
+    }
+    int incl = v.n;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const int o = __shfl_up(incl, s, 64);
+        if (lane >= s) incl += o;
+    }
+    v.incl = incl;
+    v.tot = __shfl(incl, 63, 64);
+    return v;
+}
+
+// the MD coordinates the cuts need (read only where candidates are evaluated)
+__device__ __forceinline__ void t3_wave_pts(const T3Direct &d, T3Wave &v) {
+    const float4 a = d.md_a[v.lm.x], b = d.md_a[v.lm.y];
+    const float2 qa = d.md_rq[v.lm.x], qb = d.md_rq[v.lm.y], ob = d.md_o[v.lm.y];
+    v.ax = a.x; v.ay = a.y; v.az = a.z; v.qax = qa.x; v.qay = qa.y;
+    v.bx = b.x; v.by = b.y; v.bz = b.z; v.obx = ob.x; v.oby = ob.y; v.qby = qb.y;
+}
+
+// the lane whose candidate range holds candidate j (j < tot): the first lane
+// with inclusive count above j
+__device__ __forceinline__ int t3_owner(int incl, int j) {
+    int pos = 0;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        const int v = __shfl(incl, pos + s - 1, 64);
+        if (v <= j) pos += s;
+    }
+    return pos;
+}
+
+// Candidate j0 + lane of the wavefront (all lanes call): its outer LS, the
+// lane of its inner LS and that LS's MD coordinates.
+struct T3Cand {
+    bool has;
+    int lo, own;
+    float ax, ay, az, qax, qay, bx, by, bz, obx, oby, qby;
+};
+
+__device__ __forceinline__ T3Cand t3_cand(const T3Wave &v, int j0, int lane) {
+    T3Cand c;
+    const int j = j0 + lane;
+    c.has = j < v.tot;
+    c.own = t3_owner(v.incl, c.has ? j : v.tot - 1);
+    const int excl = __shfl(v.incl - v.n, c.own, 64), c0 = __shfl(v.c0, c.own, 64);
+    c.lo = c0 + ((c.has ? j : v.tot - 1) - excl);
+    c.ax = __shfl(v.ax, c.own, 64); c.ay = __shfl(v.ay, c.own, 64); c.az = __shfl(v.az, c.own, 64);
+    c.qax = __shfl(v.qax, c.own, 64); c.qay = __shfl(v.qay, c.own, 64);
+    c.bx = __shfl(v.bx, c.own, 64); c.by = __shfl(v.by, c.own, 64); c.bz = __shfl(v.bz, c.own, 64);
+    c.obx = __shfl(v.obx, c.own, 64); c.oby = __shfl(v.oby, c.own, 64); c.qby = __shfl(v.qby, c.own, 64);
+    return c;
+}
+
+// the T3 cuts of a candidate with its outer MD C loaded: beam-line pair cuts
+// on (A, C), then the direction cut of a barrel middle MD B
+__device__ __forceinline__ bool t3_cuts(const T3Direct &d, const T3Cand &k, const float4 &c, const float2 &qc) {
+    float cv, sg;
+    bool pass = pair_pass_rq(d.p, P3{k.ax, k.ay, k.az}, make_float2(k.qax, k.qay), P3{c.x, c.y, c.z}, qc, cv, sg);
+    if (pass && !signbit(k.qby)) pass = md_dir_pass(d.p, P3{k.bx, k.by, k.bz}, k.obx, k.oby, fminf(cv, d.p.cmax), sg);
+    return k.has && pass;
+}
+
+// pass mask of the candidates j0 + lane (one window of 64)
+__device__ __forceinline__ unsigned long long t3_eval(const T3Direct &d, const T3Wave &v, int j0, int lane,
+                                                      int *lo_out, int *own_out) {
+    const T3Cand k = t3_cand(v, j0, lane);
+    *lo_out = k.lo;
+    *own_out = k.own;
+    const int C = d.ls_md[k.lo].y;
+    return __ballot(t3_cuts(d, k, d.md_a[C], d.md_rq[C]));
+}
+
+// pass masks of two windows, their loads issued together
+__device__ __forceinline__ void t3_eval2(const T3Direct &d, const T3Wave &v, int j0, int lane,
+                                         unsigned long long *m0, unsigned long long *m1) {
+    const T3Cand k0 = t3_cand(v, j0, lane), k1 = t3_cand(v, j0 + 64, lane);
+    const int C0 = d.ls_md[k0.lo].y, C1 = d.ls_md[k1.lo].y;
+    const float4 c0 = d.md_a[C0], c1 = d.md_a[C1];
+    const float2 q0 = d.md_rq[C0], q1 = d.md_rq[C1];
+    *m0 = __ballot(t3_cuts(d, k0, c0, q0));
+    *m1 = __ballot(t3_cuts(d, k1, c1, q1));
+}
+
+__global__ __launch_bounds__(kBlock) void k_t3_count(T3Direct d) {
+    // wavefront index made uniform, so that per-wavefront values load as scalars
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t n_ls = dev_count(d.counts + LST_COUNT_LS, d.cap_ls);
+    const int64_t nwaves = (n_ls + 63) / 64;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *d.nw = nwaves;
+    const int64_t ntiles = (nwaves + kBlock / 64 - 1) / (kBlock / 64);
+    const TileWalk walk(ntiles);
+    for (int64_t tile = walk.first; tile < walk.end; tile += walk.step) {
+        const int64_t w = tile * (kBlock / 64) + wv;
+        if (w >= nwaves) continue;                 // wavefront-uniform
+        T3Wave v = t3_wave<false>(d, w, n_ls, lane);
+        if (v.act) d.cn[v.l1] = make_int2(v.c0, v.n);
+        t3_wave_pts(d, v);
+        int cnt = 0;
+        for (int j0 = 0, it = 0; j0 < v.tot; j0 += 128, it += 2) {
+            unsigned long long m0, m1 = 0ull;
+            if (j0 + 64 < v.tot) {
+                t3_eval2(d, v, j0, lane, &m0, &m1);
+            } else {
+                int lo, own;
+                m0 = t3_eval(d, v, j0, lane, &lo, &own);
+            }
+            cnt += __popcll(m0) + __popcll(m1);
+            if (lane == 0) {
+                if (it < d.masks) d.bits[w * kT3MaxMasks + it] = m0;
+                if (it + 1 < d.masks) d.bits[w * kT3MaxMasks + it + 1] = m1;
+            }
+        }
+        if (lane == 0) {
+            d.wcnt[w] = cnt;
+            if (v.tot > 64 * d.masks) d.ovf[atomicAdd(d.n_ovf, 1ull)] = (int32_t)w;
+        }
+    }
+}
+
+// Write the T3 of wavefront w at their final places and the first T3
+// position of each of its inner LSs. kEval: candidates beyond the kept masks
+// are evaluated again (the listed wavefronts); otherwise there are none.
+template <bool kEval>
+__device__ __forceinline__ void t3_write_wave(const T3Direct &d, T3Wave &v, int64_t w, int lane) {
+    const unsigned long long lt = (1ull << lane) - 1;
+    const int64_t base = d.woff[w];
+    const int mine = v.incl - v.n;                 // the lane's first candidate
+    int64_t run = 0, before = 0;
+    for (int j0 = 0, it = 0; j0 < v.tot; j0 += 64, ++it) {
+        int lo, own;
+        unsigned long long m;
+        if (!kEval || it < d.masks) {
+            m = d.bits[w * kT3MaxMasks + it];
+            const int j = j0 + lane < v.tot ? j0 + lane : v.tot - 1;
+            own = t3_owner(v.incl, j);
+            const int excl = __shfl(v.incl - v.n, own, 64), c0 = __shfl(v.c0, own, 64);
+            lo = c0 + (j - excl);
+        } else {
+            if (it == d.masks) t3_wave_pts(d, v);
+            m = t3_eval(d, v, j0, lane, &lo, &own);
+        }
+        const int k = mine - j0;                   // the lane's candidates before this window
+        before += __popcll(k <= 0 ? 0ull : (k >= 64 ? m : m & ((1ull << k) - 1)));
+        const int A = __shfl(v.lm.x, own, 64), B = __shfl(v.lm.y, own, 64);
+        if ((m >> lane) & 1ull) {
+            const int64_t p = base + run + __popcll(m & lt);
+            if (p < d.cap_t3) {
+                d.t3_ls[p] = make_int2((int)(w * 64 + own), lo);
+                d.t3_mds[p] = make_int4(A, B, d.ls_md[lo].y, 0);
+            }
+        }
+        run += __popcll(m);
+    }
+    if (v.act) {
+        const int64_t p = base + before;
+        d.pos[v.l1] = p < d.cap_t3 ? p : d.cap_t3;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_t3_write(T3Direct d) {
+    // wavefront index made uniform, so that per-wavefront values load as scalars
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t n_ls = dev_count(d.counts + LST_COUNT_LS, d.cap_ls);
+    const int64_t nwaves = (n_ls + 63) / 64;
+    const int64_t total = d.woff[nwaves];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d.counts[LST_COUNT_T3] = total;
+        d.pos[n_ls] = total < d.cap_t3 ? total : d.cap_t3;
+    }
+    const int64_t ntiles = (nwaves + kBlock / 64 - 1) / (kBlock / 64);
+    const TileWalk walk(ntiles);
+    for (int64_t tile = walk.first; tile < walk.end; tile += walk.step) {
+        const int64_t w = tile * (kBlock / 64) + wv;
+        if (w >= nwaves) continue;                 // wavefront-uniform
+        T3Wave v = t3_wave<true>(d, w, n_ls, lane);
+        if (v.tot > 64 * d.masks) continue;        // a listed wavefront
+        t3_write_wave<false>(d, v, w, lane);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_t3_write_listed(T3Direct d) {
+    const int lane = threadIdx.x & 63;
+    const int64_t n_ls = dev_count(d.counts + LST_COUNT_LS, d.cap_ls);
+    const int64_t n = (int64_t)*d.n_ovf;
+    const int64_t step = (int64_t)gridDim.x * (kBlock / 64);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + wv; i < n; i += step) {
+        const int64_t w = d.ovf[i];
+        T3Wave v = t3_wave<true>(d, w, n_ls, lane);
+        t3_write_wave<true>(d, v, w, lane);
+    }
+}
+
+// CSR of T3 by inner MD: the T3 of MD m start at the first T3 of its first LS
+__global__ __launch_bounds__(kBlock) void k_t3_md_off(T3Direct d, const int64_t *n_md_dev, int64_t cap_md,
+                                                      int64_t *t3i_off) {
+    const int64_t n_md = dev_count(n_md_dev, cap_md);
+    const int64_t n_ls = dev_count(d.counts + LST_COUNT_LS, d.cap_ls);
+    for (int64_t m = grid_tid(); m <= n_md; m += grid_stride()) {
+        const int64_t l = t3_lsoff(d, m);
+        t3i_off[m] = d.pos[l < n_ls ? l : n_ls];
+    }
+}
 
 // ------------------------------------------------------------ T5 stage
 // In two passes so that the FP64 fits run on dense lanes:
@@ -1899,7 +2119,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
     mark(ev, 16, st);
     LsArgs la{w.md_a, w.md_o, w.md_rq, w.md_mod_off, a.g, a.p, w.ls_cnt, w.ls_chunk, w.cap_ls, w.ls_top, cnt,
               w.cap_md};
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.ls_top);
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, w.ls_top, w.t3_n_ovf);
     {
         const int64_t tiles = (w.cap_md + 64 * kLsWaves - 1) / (64 * kLsWaves);
         int nb = (int)(tiles < kLsBlocks ? tiles : kLsBlocks);
@@ -1915,11 +2135,23 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
 
     if (a.stop_before == 4) return hipGetLastError();
     // a4: triplets, anchored on the inner LS
-    T3Stage t3{o.ls_md, w.ls_off, w.cap_ls, w.md_a, w.md_o, w.md_rq, a.g.mod, a.p, n_mod, o.t3_ls, w.t3_mds};
+    T3Direct t3{o.ls_md, w.ls_off, w.cap_ls, w.md_a, w.md_o, w.md_rq, a.p, w.t3_wcnt, w.t3_woff, w.t3_bits,
+                a.tune.t3_masks, w.t3_nw, w.t3_cn, w.t3_ovf, w.t3_n_ovf, w.t3_pos, o.t3_ls, w.t3_mds, w.cap_t3,
+                cnt};
     mark(ev, 18, st);
-    run_stage(t3, cnt + LST_COUNT_LS, w.cap_ls, w, cnt + LST_COUNT_T3, w.cap_t3, cnt, st, ev, 4, a.tune);
-    hipLaunchKernelGGL(k_fill_offsets<T3InKey>, dim3(grid_for(w.cap_t3 + 1)), dim3(kBlock), 0, st, T3InKey{w.t3_mds},
-                       cnt + LST_COUNT_T3, w.cap_t3, cnt + LST_COUNT_MD, w.cap_md, w.t3i_off);
+    {
+        const int64_t tiles = (w.cap_ls + kBlock - 1) / kBlock;
+        int nb = (int)(tiles < kT3Blocks ? tiles : kT3Blocks);
+        nb = round_up_xcd(nb < 1 ? 1 : nb);
+        mark(ev, 8, st);
+        hipLaunchKernelGGL(k_t3_count, dim3(nb), dim3(kBlock), 0, st, t3);
+        mark(ev, 9, st);
+        scan(CntF{w.t3_wcnt}, w.t3_nw, w.cap_ls / 64 + 1, w, w.t3_woff, nullptr, st);
+        hipLaunchKernelGGL(k_t3_write, dim3(nb), dim3(kBlock), 0, st, t3);
+        hipLaunchKernelGGL(k_t3_write_listed, dim3(kT3OvfBlocks), dim3(kBlock), 0, st, t3);
+        hipLaunchKernelGGL(k_t3_md_off, dim3(grid_for(w.cap_md + 1)), dim3(kBlock), 0, st, t3,
+                           (const int64_t *)(cnt + LST_COUNT_MD), w.cap_md, w.t3i_off);
+    }
     mark(ev, 19, st);
 
     if (a.stop_before == 5) return hipGetLastError();

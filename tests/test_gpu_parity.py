@@ -270,9 +270,11 @@ def test_tunings_change_nothing_but_speed(builder_f, geo_f):
     ref = run_gpu(builder_f, ev, precision=B.LST_PREC_BF16)
     default = B.lst_get_tuning(builder_f.ctx)
     variants = [
-        {"bin_split": 1, "tile_per": [2, 2, 1, 1, 1], "eval_blocks": 256},
-        {"bin_split": 32, "tile_per": [8, 8, 4, 4, 2], "eval_blocks": 8192},
-        {"bin_split": 8, "tile_per": [2, 8, 4, 1, 2], "eval_blocks": 1024},
+        # t3_masks 1 and 2 send most T3 wavefronts to the kernel for those
+        # with more candidates than the kept pass masks
+        {"bin_split": 1, "tile_per": [2, 2, 1, 1, 1], "eval_blocks": 256, "t3_masks": 1},
+        {"bin_split": 32, "tile_per": [8, 8, 4, 4, 2], "eval_blocks": 8192, "t3_masks": 8},
+        {"bin_split": 8, "tile_per": [2, 8, 4, 1, 2], "eval_blocks": 1024, "t3_masks": 2},
     ]
     try:
         for t in variants:
@@ -286,7 +288,9 @@ def test_tunings_change_nothing_but_speed(builder_f, geo_f):
                     {"bin_split": 4, "tile_per": [1, 4, 2, 2, 1], "eval_blocks": 4096},
                     {"bin_split": 4, "tile_per": [4, 4, 2, 2, 4], "eval_blocks": 4096},
                     {"bin_split": 4, "tile_per": [4, 3, 2, 2, 1], "eval_blocks": 4096},
-                    {"bin_split": 4, "tile_per": [4, 4, 2, 2, 1], "eval_blocks": 100}):
+                    {"bin_split": 4, "tile_per": [4, 4, 2, 2, 1], "eval_blocks": 100},
+                    {"bin_split": 4, "tile_per": [4, 4, 2, 2, 1], "eval_blocks": 4096, "t3_masks": 0},
+                    {"bin_split": 4, "tile_per": [4, 4, 2, 2, 1], "eval_blocks": 4096, "t3_masks": 9}):
             before = B.lst_get_tuning(builder_f.ctx)
             with pytest.raises(B.LstError) as ei:
                 B.lst_set_tuning(builder_f.ctx, bad)

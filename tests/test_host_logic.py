@@ -25,20 +25,24 @@ def test_caps_growth_covers_counts_and_is_bounded():
 
 def test_tuning_struct_roundtrip():
     from paper_2403_13166_amd import binding as B
-    d = {"bin_split": 8, "tile_per": [2, 8, 4, 1, 2], "eval_blocks": 2048}
+    d = {"bin_split": 8, "tile_per": [2, 8, 4, 1, 2], "eval_blocks": 2048, "t3_masks": 3}
     assert B.LstTuning.from_dict(d).as_dict() == d
+    d.pop("t3_masks")                                   # optional: the default
+    assert B.LstTuning.from_dict(d).as_dict()["t3_masks"] == B.T3_MASKS_DEFAULT
 
 
 def test_autotune_search_with_fake_context(monkeypatch):
     from paper_2403_13166_amd import autotune as AT
     from paper_2403_13166_amd import binding as B
-    state = {"tuning": {"bin_split": 4, "tile_per": [4, 4, 2, 2, 1], "eval_blocks": 4096}, "timing": False}
+    state = {"tuning": {"bin_split": 4, "tile_per": [4, 4, 2, 2, 1], "eval_blocks": 4096, "t3_masks": 8},
+             "timing": False}
 
     def fake_times(ctx):
         t = state["tuning"]
         # T5 pre-cuts fastest at 4, binning fastest at 64, eval grid fastest at 2048; others flat
         return {"build": 1.0 + abs(t["eval_blocks"] - 2048) / 8192, "bin": 0.5 - 0.001 * t["bin_split"],
-                "md": 0.1, "ls": 1.0, "t3": 0.05, "t5": 1.0 / t["tile_per"][3], "score": 0.2}
+                "md": 0.1, "ls": 1.0, "t3": 0.05 + 0.01 * (t["t3_masks"] == 2), "t5": 1.0 / t["tile_per"][3],
+                "score": 0.2}
 
     monkeypatch.setattr(B, "lst_set_timing", lambda ctx, on: state.update(timing=on))
     monkeypatch.setattr(B, "lst_get_tuning", lambda ctx: {k: (list(v) if isinstance(v, list) else v)
@@ -56,6 +60,7 @@ def test_autotune_search_with_fake_context(monkeypatch):
     assert best["tile_per"][3] == 4 and best["bin_split"] == 64 and best["eval_blocks"] == 2048
     assert best["tile_per"][0] == 4                     # flat timings: no move without a clear gain
     assert best["tile_per"][1] == 4                     # the line-segment stage has no tiles: not searched
+    assert best["tile_per"][2] == 2 and best["t3_masks"] == 8   # nor the T3 stage; masks: no clear gain
     assert len(table) == len(AT.KNOBS) and state["tuning"] == best
 
     class ChangingBuilder(FakeBuilder):
