@@ -216,7 +216,53 @@ def measure_extras(b, dx, dy, dz, ds, doff, stream, prec, geo, evs):
             t5[mname] = {"t5_ms": float(v[0]), "dnn_ms": float(v[1]), "build_ms": float(v[2])}
         B.lst_set_timing(b.ctx, False)
         out["t5_stage_by_mode"] = t5
+        out["displaced"] = measure_displaced(b, dx, dy, dz, ds, doff, stream, prec, geo)
     return out
+
+
+CUBE_BINS = (0.0, 1.0, 2.0, 2.5, 3.0, 3.6)
+
+
+def measure_displaced(b, dx, dy, dz, ds, doff, stream, prec, geo):
+    """Displaced workload (Sec. 3, muon-cube sample): 64 events of 200 muons
+    from vertices uniform in a 5 cm cube, built with the default and the
+    relaxed cut sets; track efficiency (muons with at least 10 hits that have
+    a T5 with more than 75 % of its hits from them) per bin of transverse
+    vertex radius, and the batch time. Also the time of the benchmark batch
+    under the relaxed cuts (their cost on PU200-like occupancy)."""
+    import torch
+    from paper_2403_13166_amd import binding as B, train as TR
+    from paper_2403_13166_amd.runtime import Builder
+    from paper_2403_13166_amd.synth import events as E, geometry as G, model as M
+    dev = dx.device
+    gd = G.make_geometry(True, G.DISPLACED_PARAMS)
+    cube = [E.make_event(geo, E.muon_cube_config(200), (9, 5000 + e)) for e in range(64)]
+    x, y, z, s, off = E.concat_events(cube)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    cx, cy, cz, cs, coff = T(x), T(y), T(z), T(s), T(off)
+    truth = np.concatenate([np.where(e.truth >= 0, e.truth + 1000 * i, -1) for i, e in enumerate(cube)])
+    rv = np.concatenate([np.hypot(e.tracks[:, 5], e.tracks[:, 6]) for e in cube])
+    nh = np.concatenate([np.bincount(e.truth[e.truth >= 0], minlength=len(e.tracks)) for e in cube])
+    ids = np.concatenate([np.arange(len(e.tracks)) + 1000 * i for i, e in enumerate(cube)])
+    bins = np.digitize(rv, CUBE_BINS) - 1
+    res = {"events": len(cube), "muons_per_event": 200, "hits": int(len(x)), "r_vertex_bins_cm": list(CUBE_BINS),
+           "muons_per_bin": [int(np.count_nonzero((nh >= 10) & (bins == k))) for k in range(len(CUBE_BINS) - 1)],
+           "relaxed_params": dict(G.DISPLACED_PARAMS)}
+    bd = Builder(gd.to_blob(), M.make_model().to_blob(), dev.index or 0)
+    with torch.cuda.stream(stream):
+        for name, bb in (("default_cuts", b), ("relaxed_cuts", bd)):
+            h = bb.build(cx, cy, cz, cs, event_offsets=coff, precision=prec).to_host()
+            real, tid = TR.t5_truth(h.md_hits, h.t5_mds(), truth)
+            found = np.isin(ids, np.unique(tid[real]))
+            eff = [float(np.mean(found[(nh >= 10) & (bins == k)])) for k in range(len(CUBE_BINS) - 1)]
+            ms = _time_ms(lambda: bb.launch(cx, cy, cz, cs, event_offsets=coff, precision=prec), stream, reps=5)
+            res[name] = {"efficiency_by_r_vertex": eff, "t5": int(len(h.t5_t3)), "batch_ms": ms,
+                         "events_per_s": len(cube) / (ms * 1e-3)}
+        bd.build(dx, dy, dz, ds, event_offsets=doff, precision=prec)
+        ms = _time_ms(lambda: bd.launch(dx, dy, dz, ds, event_offsets=doff, precision=prec), stream, reps=5)
+        res["benchmark_batch_relaxed_cuts"] = {"batch_ms": ms, "counts": [int(v) for v in bd.device_counts()[:4]]}
+    bd.close()
+    return res
 
 
 def measure_end_to_end(b, step, dev_hits, host_hits, counts, stream, reps):

@@ -13,6 +13,11 @@ Hits are recorded where the helix crosses a sensor surface (barrel cylinders,
 endcap planes), smeared, and assigned to the module containing the smeared
 point. Events mimic the workloads of the paper's Sec. 3 (HL-LHC pile-up)
 with synthetic numbers: PU200-like occupancy is 6000 tracks + 100k noise hits.
+
+Displaced workload (Sec. 3, the "muon-cube" sample): muons from vertices
+uniform in a 5 cm cube centred on the nominal interaction point, so their
+helices start at (x_v, y_v, z_v) instead of the beam line; each track then
+carries x_v and y_v as two more truth columns.
 """
 from __future__ import annotations
 
@@ -37,6 +42,7 @@ class EventConfig:
     n_noise: int
     with_endcap: bool
     sigma_scale: float = 1.0   # 0 -> noise-free hit positions
+    cube: float = 0.0          # side of the vertex cube (x, y, z uniform); 0 -> vertices on the beam line
 
 
 # Single barrel-only event of 100 tracks, pT in [1, 10] GeV, |eta| < 0.8.
@@ -52,6 +58,13 @@ def batch_event_config(rng: np.random.Generator) -> EventConfig:
     return EventConfig(f"batch-{nt}trk-{nn}noise", nt, 1 / 50.0, 1 / 0.8, 2.4, 5.0, nn, True)
 
 
+def muon_cube_config(n_muons: int = 50, side: float = 5.0, n_noise: int = 0) -> EventConfig:
+    """Displaced workload: n_muons muons, pT in [0.8, 50] GeV (1/pT uniform),
+    |eta| < 2.4, vertices uniform in a cube of the given side (cm)."""
+    return EventConfig(f"muon-cube-{n_muons}mu-{side:g}cm", n_muons, 1 / 50.0, 1 / 0.8, 2.4, 0.0, n_noise, True,
+                       cube=side)
+
+
 def pileup_event_config(pu: float) -> EventConfig:
     """Serving workload: 30 tracks and 500 noise hits per unit of pile-up."""
     return EventConfig(f"pu{pu:.0f}", int(round(30 * pu)), 1 / 50.0, 1 / 0.8, 2.4, 5.0,
@@ -65,7 +78,7 @@ class Event:
     z: np.ndarray
     sensor: np.ndarray   # i32
     truth: np.ndarray    # i32 track id, -1 noise
-    # per-track truth (f64): q, pt, eta, phi0, zv
+    # per-track truth (f64): q, pt, eta, phi0, zv (and x_v, y_v for displaced vertices)
     tracks: np.ndarray
 
     @property
@@ -86,8 +99,36 @@ def helix_point(q, R, phi0, zv, lam, s):
     return chord * np.cos(ang), chord * np.sin(ang), zv + s * lam
 
 
-def _track_hits(geo: Geometry, q, pt, eta, phi0, zv, sigma_scale, rng):
-    """All sensor crossings of the given tracks -> (x, y, z, sensor, track_index)."""
+def _first_cylinder_crossing(q, R, phi0, xv, yv, rr):
+    """Transverse arc length of the first crossing of radius rr by helices
+    starting at (xv, yv) inside it, and whether there is one within half a
+    turn: the first sign change of |V + P(s)|^2 - rr^2 on a grid of 512 steps
+    in s / 2R over (0, pi / 2], refined by 60 bisections."""
+    def f(h, q, R, phi0, xv, yv):
+        ch = 2.0 * R * np.sin(h)
+        ang = phi0 - q * h
+        return (xv + ch * np.cos(ang)) ** 2 + (yv + ch * np.sin(ang)) ** 2 - rr * rr
+
+    hs = np.linspace(0.0, 0.5 * math.pi, 513)[1:]
+    col = lambda a: a[:, None]
+    vals = f(hs[None, :], col(q), col(R), col(phi0), col(xv), col(yv))
+    pos = vals >= 0.0
+    ok = pos.any(axis=1)
+    k = np.argmax(pos, axis=1)
+    hi = hs[k]
+    lo = np.where(k > 0, hs[np.maximum(k - 1, 0)], 0.0)
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        up = f(mid, q, R, phi0, xv, yv) >= 0.0
+        hi = np.where(up, mid, hi)
+        lo = np.where(up, lo, mid)
+    return np.where(ok, 2.0 * R * hi, 0.0), ok
+
+
+def _track_hits(geo: Geometry, q, pt, eta, phi0, zv, sigma_scale, rng, xv=None, yv=None):
+    """All sensor crossings of the given tracks -> (x, y, z, sensor, track_index).
+    xv, yv: transverse vertex positions (None: on the beam line)."""
+    displaced = xv is not None
     prm = geo.params
     kb = prm["k_b"]
     g = prm["gap"]
@@ -102,9 +143,14 @@ def _track_hits(geo: Geometry, q, pt, eta, phi0, zv, sigma_scale, rng):
     # barrel cylinders: anchor (r) and other (r + gap)
     for li, rk in enumerate(BARREL_RADII):
         for which, rr in ((0, rk), (1, rk + g)):
-            ok = c * rr < 1.0
-            s = np.where(ok, np.arcsin(np.minimum(1.0, c * rr)) / c, 0.0)
-            x, y, z = helix_point(q, R, phi0, zv, lam, s)
+            if displaced:
+                s, ok = _first_cylinder_crossing(q, R, phi0, xv, yv, rr)
+                x, y, z = helix_point(q, R, phi0, zv, lam, s)
+                x, y = x + xv, y + yv
+            else:
+                ok = c * rr < 1.0
+                s = np.where(ok, np.arcsin(np.minimum(1.0, c * rr)) / c, 0.0)
+                x, y, z = helix_point(q, R, phi0, zv, lam, s)
             phi = np.arctan2(y, x) + rng.normal(0.0, 1.0, pt.shape) * (s_rphi / rr)
             zz = z + rng.normal(0.0, 1.0, pt.shape) * s_z
             mod = geo.barrel_module(np.full(pt.shape, li), zz, phi)
@@ -121,6 +167,8 @@ def _track_hits(geo: Geometry, q, pt, eta, phi0, zv, sigma_scale, rng):
                     ok = np.isfinite(s) & (s > 0) & (c * s <= math.pi / 2)
                     s = np.where(ok, s, 0.0)
                     x, y, _ = helix_point(q, R, phi0, zv, lam, s)
+                    if displaced:
+                        x, y = x + xv, y + yv
                     r = np.hypot(x, y)
                     phi = np.arctan2(y, x)
                     rr = r + rng.normal(0.0, 1.0, pt.shape) * s_r
@@ -179,6 +227,9 @@ def make_tracks(cfg: EventConfig, rng: np.random.Generator, n: int | None = None
     invpt = rng.uniform(cfg.invpt_lo, cfg.invpt_hi, n)
     eta = rng.uniform(-cfg.eta_max, cfg.eta_max, n)
     phi0 = rng.uniform(0.0, TWO_PI, n)
+    if cfg.cube > 0:
+        v = rng.uniform(-0.5 * cfg.cube, 0.5 * cfg.cube, (n, 3))
+        return np.stack([q, 1.0 / invpt, eta, phi0, v[:, 2], v[:, 0], v[:, 1]], axis=1)
     zv = rng.normal(0.0, cfg.zv_sigma, n) if cfg.zv_sigma > 0 else np.zeros(n)
     return np.stack([q, 1.0 / invpt, eta, phi0, zv], axis=1)
 
@@ -186,7 +237,8 @@ def make_tracks(cfg: EventConfig, rng: np.random.Generator, n: int | None = None
 def make_event_from_tracks(geo: Geometry, tracks: np.ndarray, n_noise: int, sigma_scale: float,
                            rng: np.random.Generator, shuffle: bool = True) -> Event:
     q, pt, eta, phi0, zv = (tracks[:, i] for i in range(5))
-    xs, ys, zs, sens, tid = _track_hits(geo, q, pt, eta, phi0, zv, sigma_scale, rng)
+    xv, yv = (tracks[:, 5], tracks[:, 6]) if tracks.shape[1] > 5 else (None, None)
+    xs, ys, zs, sens, tid = _track_hits(geo, q, pt, eta, phi0, zv, sigma_scale, rng, xv, yv)
     if n_noise > 0:
         nx, ny, nz, ns = _noise_hits(geo, n_noise, rng)
         xs = np.concatenate([xs, nx]); ys = np.concatenate([ys, ny]); zs = np.concatenate([zs, nz])

@@ -85,6 +85,22 @@ DEFAULT_PARAMS = {
     "reserved0": 0.0, "reserved1": 0.0, "reserved2": 0.0, "reserved3": 0.0,
 }
 
+# Relaxed beam constraints for the displaced workload (vertices in a 5 cm
+# cube, so transverse displacements d0 up to 2.5 sqrt 2 = 3.5 cm). Every cut
+# that ties a pair of points to the beam line does so through a circle through
+# the origin, whose half-curvature for a straight track of impact parameter d0
+# through points at radii r_A < r_B is d0 / (r_A r_B). The pT threshold sets
+# c_max = k_b / (2 pT_min); the lowest threshold at which every circle with
+# c <= c_max still reaches the outermost sensors (c_max r < 1 at r = 110 cm)
+# is 0.63 GeV. At 0.65 GeV (c_max = 0.0088 / cm) a track of pT p passes the
+# innermost barrel pair (23, 36 cm) up to d0 = (c_max - k_b / 2p) * 23 * 36:
+# 1.4 cm at 0.8 GeV, 4.9 cm at 2 GeV, more at larger radii. The z0
+# extrapolation of a track starting at r_v <= 3.5 cm misses its vertex z by
+# up to |cot theta| r_v (5.5 * 3.5 = 19 cm at |eta| = 2.4) on top of
+# |z_v| <= 2.5 cm: z_lum 25 cm. The module map, the windows and the fits all
+# follow from these parameters.
+DISPLACED_PARAMS = {"pt_min": 0.65, "z_lum": 25.0}
+
 # Map-building tolerances: beyond the selection envelope, windows are widened
 # by 5 sigma of the hit resolution plus this many cm.
 MAP_EXTRA_CM = 0.5
