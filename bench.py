@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # elementwise kernel), kept with the hash of the kernel sources they were
 # taken on: a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    "ls stage": {"bytes": 176.03e6, "source_sha1": "c90bb9fb23fb5bcf9aa218c31c8087638dd28c3b"},
+    "ls stage": {"bytes": 176.09e6, "source_sha1": "f1f0c53a0d486a547f0e3b1c1b6a543f193a6826"},
 }
 KERNEL_SOURCES = ("paper_2403_13166_amd/csrc/lst_pipeline.hip", "paper_2403_13166_amd/csrc/lst_device.h",
                   "paper_2403_13166_amd/csrc/lst_internal.h")
