@@ -245,6 +245,51 @@ def test_edge_cases(builder_f, geo_f):
     assert np.array_equal(out.t5_t3, ref.t5_t3) and np.array_equal(out.md_hits, ref.md_hits)
 
 
+@pytest.mark.parametrize("stage", ["ls", "t3", "t5"])
+def test_capacity_overflow_of_one_stage(geo_f, mdl, stage):
+    """One capacity too small, the others ample: the call reports
+    LST_E_CAPACITY with that stage's full required count, and the growing
+    builder then returns the reference objects."""
+    from paper_2403_13166_amd import binding as B
+    from paper_2403_13166_amd.runtime import Builder, Caps
+    ev = E.make_event(geo_f, E.PU200, (1, 8))
+    b = Builder(geo_f.to_blob(), mdl.to_blob(), 0)
+    ref = run_gpu(b, ev)
+    n = {"ls": len(ref.ls_md), "t3": len(ref.t3_ls), "t5": len(ref.t5_t3)}
+    full = Caps(hits=ev.n, events=1, md=2 * len(ref.md_hits), ls=2 * n["ls"], t3=2 * n["t3"], t5=2 * n["t5"],
+                cand=40_000_000)
+    small = Caps(**{**full.__dict__, stage: 1000})
+    dev = b.device
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    x, y, z, s = (T(a) for a in (ev.x, ev.y, ev.z, ev.sensor))
+    h = B.LstHits(x.data_ptr(), y.data_ptr(), z.data_ptr(), s.data_ptr(), ev.n)
+    b.caps = None
+    b.reserve(small)
+    st = B.lst_build_objects(b.ctx, h, B.LstOptions(0, 0, float("nan"), 0), small.c(), b._objects_struct(False),
+                             b._ws_ptr(), b.ws_bytes, torch.cuda.current_stream(dev).cuda_stream, check=False)
+    assert st == B.LST_E_CAPACITY
+    c = b.device_counts()
+    got = {"ls": c[1], "t3": c[2], "t5": c[3]}[stage]
+    _say(f"{stage} capacity 1000: reported {got}, required {n[stage]}")
+    assert got == n[stage]                    # the full count, although only 1000 were stored
+    out = b.build(x, y, z, s, caps=small).to_host()
+    for k in ("md_hits", "ls_md", "t3_ls", "t5_t3", "t5_score"):
+        assert np.array_equal(getattr(out, k), getattr(ref, k)), k
+    b.close()
+
+
+def test_mds_without_segments(builder_f, geo_f, mdl):
+    """Hits on one barrel layer only: MDs but no LS, so the T3 stage runs on
+    an empty list (its CSR by MD must be all zero) and nothing follows."""
+    ev = E.make_event(geo_f, E.PU200, (1, 9))
+    m = ev.sensor // 2
+    keep = (geo_f.kind[m] == 0) & (geo_f.layer[m] == 3)
+    one = E.Event(ev.x[keep], ev.y[keep], ev.z[keep], ev.sensor[keep], ev.truth[keep], ev.tracks)
+    gh = run_gpu(builder_f, one)
+    assert len(gh.md_hits) > 100 and len(gh.ls_md) == 0 and len(gh.t3_ls) == 0 and len(gh.t5_t3) == 0
+    check_parity(geo_f, mdl, one, gh, label="one layer")
+
+
 def test_dense_sensor_range_parity(builder_f, geo_f, mdl):
     """A PU200-like event plus 40k noise hits on the first sensor-id range:
     that range holds ~53k hits, more than one fine-binning block gathers
