@@ -1011,11 +1011,12 @@ __global__ __launch_bounds__(kBlock) void k_fill_offsets(KF key, const int64_t *
 // per-A counts gives the CSR offsets of LS by inner MD, and a placement kernel
 // stores each record at offset[A] + rank.
 
-constexpr int kLsWaves = kBlock / 64;
+constexpr int kLsWaves = 1;             // wavefronts per block of the eval kernel (one tile each)
+constexpr int kLsBlock = 64 * kLsWaves;
 constexpr int kLsRunsPerRound = 2;      // trimmed runs staged per lane at a time (even)
 constexpr int kLsQCap = 128;            // queue entries per wavefront (up to 63 waiting + 64 new)
 constexpr int kLsOutCap = 256;          // survivors held per wavefront before a write-out
-constexpr int kLsBlocks = 1280;         // persistent blocks of the eval kernel
+constexpr int kLsBlocks = 32768;        // blocks of the eval kernel (one per tile of 64 MDs at the benchmark's sizes)
 constexpr float kLsCrossMargin = 1e-3f; // cm: slack of the phi-window cross products
 // queue entry tag: bits 0-5 owner lane, 6 bends positive, 7 / 8 direction cut
 // on A / on B (barrel MDs)
@@ -1412,7 +1413,7 @@ struct LsCursor {
     }
 };
 
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_ls_eval(LsArgs a) {
+__global__ __launch_bounds__(kLsBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_ls_eval(LsArgs a) {
     __shared__ LsLds L;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t n_md = dev_count(a.counts + LST_COUNT_MD, a.cap_md);
@@ -2125,7 +2126,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
         int nb = (int)(tiles < kLsBlocks ? tiles : kLsBlocks);
         nb = round_up_xcd(nb < 1 ? 1 : nb);
         mark(ev, 6, st);
-        hipLaunchKernelGGL(k_ls_eval, dim3(nb), dim3(kBlock), 0, st, la);
+        hipLaunchKernelGGL(k_ls_eval, dim3(nb), dim3(kLsBlock), 0, st, la);
         mark(ev, 7, st);
         scan(CntF{w.ls_cnt}, cnt + LST_COUNT_MD, w.cap_md, w, w.ls_off, nullptr, st);
         hipLaunchKernelGGL(k_ls_place, dim3(grid_for(w.cap_ls)), dim3(kBlock), 0, st, la, (const int64_t *)w.ls_off,
