@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # elementwise kernel), kept with the hash of the kernel sources they were
 # taken on: a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    "ls stage": {"bytes": 176.09e6, "source_sha1": "f1f0c53a0d486a547f0e3b1c1b6a543f193a6826"},
+    "ls stage": {"bytes": 151.90e6, "source_sha1": "587612820b58eaa135c9ea106eb79c81feff90bf"},
 }
 KERNEL_SOURCES = ("paper_2403_13166_amd/csrc/lst_pipeline.hip", "paper_2403_13166_amd/csrc/lst_device.h",
                   "paper_2403_13166_amd/csrc/lst_internal.h")
