@@ -15,6 +15,9 @@ Also measured (reported beside the headline, never as `value`):
   * per-stage windows of the eval kernels and of the whole stages (scans,
     copies and CSR fills included), with compulsory bytes per stage;
   * the plain and served paths on the same Poisson arrivals (PCIe included);
+  * event-level concurrency: 1, 2, 4 and 8 builders, each replaying the
+    graph of the build of its own copy of the batch on its own HIP stream
+    (events/s per stream count);
   * the FP64 oracle on a bounded sample of the same events, on one thread and
     on one thread per usable host core (host CPU model stated).
 """
@@ -79,6 +82,9 @@ def parse():
                     help="Poisson arrival rates (events/s) of the served streams; the largest saturates the GPU")
     ap.add_argument("--skip-extras", action="store_true",
                     help="skip the standalone scoring, edge-classifier and pre-DNN measurements")
+    ap.add_argument("--streams", default="1,2,4,8",
+                    help="stream counts of the event-level concurrency scan, one batch and builder per stream "
+                         "(empty: skip)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device copy of this size after the timed region (HBM counter scale)")
     return ap.parse_args()
@@ -90,6 +96,91 @@ def make_batch(n_events: int, batch_seed: int):
     rng = E.event_rng(2, batch_seed)
     evs = [E.make_event(geo, E.batch_event_config(rng), (2, batch_seed, e)) for e in range(n_events)]
     return geo, evs
+
+
+def sized_builder(geo_blob, model_blob, d, mode, prec):
+    """A builder whose capacities fit the batch d = (x, y, z, sensor, event
+    offsets) on the device with 10 % headroom: one eager build (which grows
+    and retries as needed), then buffers reserved for its counts. Returns the
+    builder and the device counts of that build."""
+    import torch
+    from paper_2403_13166_amd.runtime import Builder, Caps
+    b = Builder(geo_blob, model_blob, 0)
+    first = b.build(*d[:4], event_offsets=d[4], mode=mode, precision=prec)
+    counts = list(first.counts())
+    torch.cuda.synchronize()
+    c0 = b.device_counts()
+    caps = Caps(hits=int(d[0].shape[0]), events=int(d[4].shape[0]) - 1, md=int(counts[0] * 1.1) + 1024,
+                ls=int(counts[1] * 1.1) + 1024, t3=int(counts[2] * 1.1) + 1024, t5=int(counts[3] * 1.1) + 1024,
+                cand=int(c0[5] * 1.1) + 4096)
+    b.caps = None
+    b.reserve(caps)
+    return b, c0
+
+
+def measure_streams(a, geo, host_batch, tuned, mode, prec):
+    """Event-level concurrency, the analogue of the paper's throughput at 1,
+    2, 4 and 8 CUDA streams (Sec. 3): k builders, each with its own context,
+    workspace, HIP stream, device copy of the benchmark batch and captured
+    graph of its build, all replaying together; events/s over rounds in which
+    every stream replays its graph once. Every builder's counts after the
+    timed rounds must equal those of its eager sizing build."""
+    import torch
+    from paper_2403_13166_amd import binding as B
+    from paper_2403_13166_amd.synth import model as M
+    ks = sorted({int(k) for k in a.streams.split(",") if k.strip()})
+    if not ks:
+        return None
+    dev = torch.device("cuda", 0)
+    T = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).to(dev)
+    gblob, mblob = geo.to_blob(), M.make_model().to_blob()
+    # (builder, stream, graph, counts, inputs): the inputs stay referenced
+    # here while the graph that reads them exists
+    units = []
+    for i in range(ks[-1]):
+        d = tuple(T(v) for v in host_batch)
+        b, c0 = sized_builder(gblob, mblob, d, mode, prec)
+        B.lst_set_tuning(b.ctx, tuned)
+        st = torch.cuda.Stream(device=dev)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(st):
+            b.launch(*d[:4], event_offsets=d[4], mode=mode, precision=prec)
+            st.synchronize()
+            with torch.cuda.graph(g, stream=st, capture_error_mode="relaxed"):
+                b.launch(*d[:4], event_offsets=d[4], mode=mode, precision=prec)
+            st.synchronize()
+        units.append((b, st, g, c0, d))
+        print(f"streams: builder {i} sized and captured ({b.ws_bytes / 2**30:.2f} GiB workspace)",
+              file=sys.stderr, flush=True)
+    rounds = max(a.steps, 20)
+    rows = []
+    for k in ks:
+        def go(n):
+            for _ in range(n):
+                for b, st, g, _, _ in units[:k]:
+                    with torch.cuda.stream(st):
+                        g.replay()
+        go(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        go(rounds)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        rows.append({"streams": k, "events_per_s": k * a.events * rounds / wall, "ms_per_round": wall / rounds * 1e3})
+        print(f"streams {k}: {rows[-1]['events_per_s']:.1f} events/s, {rows[-1]['ms_per_round']:.3f} ms per round",
+              file=sys.stderr, flush=True)
+    for b, st, g, c0, _ in units:
+        chk = b.device_counts()
+        assert chk[:4] == c0[:4] and chk[4] == 0, (chk, c0)
+    out = {"builders": len(units), "events_per_batch": a.events, "rounds": rounds,
+           "batch": "each builder replays its own device copy of the benchmark batch",
+           "workspace_bytes_per_builder": units[0][0].ws_bytes, "rows": rows}
+    torch.cuda.synchronize()
+    builders = [u[0] for u in units]
+    units.clear()                   # graphs and their inputs first, then the contexts
+    for b in builders:
+        b.close()
+    return out
 
 
 def stage_bytes(c, n_hits, n_ev, n_mod, n_sens):
@@ -370,17 +461,7 @@ def main():
     dev = torch.device("cuda", 0)
     T = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).to(dev)
     dx, dy, dz, ds, doff = T(x), T(y), T(z), T(s), T(off)
-    b = Builder(geo.to_blob(), M.make_model().to_blob(), 0)
-
-    # size the capacities with one eager build (grows and retries as needed)
-    first = b.build(dx, dy, dz, ds, event_offsets=doff, mode=mode, precision=prec)
-    counts = list(first.counts())
-    torch.cuda.synchronize()
-    c0 = b.device_counts()
-    caps = Caps(hits=len(x), events=a.events, md=int(counts[0] * 1.1) + 1024, ls=int(counts[1] * 1.1) + 1024,
-                t3=int(counts[2] * 1.1) + 1024, t5=int(counts[3] * 1.1) + 1024, cand=int(c0[5] * 1.1) + 4096)
-    b.caps = None
-    b.reserve(caps)
+    b, c0 = sized_builder(geo.to_blob(), M.make_model().to_blob(), (dx, dy, dz, ds, doff), mode, prec)
     B.lst_set_timing(b.ctx, True)
 
     stream = torch.cuda.Stream(device=dev)
@@ -477,6 +558,9 @@ def main():
         extras = measure_extras(b, dx, dy, dz, ds, doff, stream, prec, geo, evs)
         extras["batched_with_pcie"] = e2e
 
+    # ---------------- event-level concurrency: one builder, batch and graph per HIP stream
+    streams = measure_streams(a, geo, (x, y, z, s, off), tuned, mode, prec) if a.streams.strip() else None
+
     # ---------------- served path: Poisson streams of PU-varying events with
     # continuous batching over HBM-budgeted slots (latency = arrival -> objects on host)
     served = None
@@ -547,7 +631,7 @@ def main():
         "algorithmic_bytes": sb, "implementation_bytes": implementation_bytes(final),
         "objects_per_event": {"md": per_ev[0], "ls": per_ev[1], "t3": per_ev[2], "t5": per_ev[3]},
         "max_candidates_per_stage": int(final[5]), "t5_pre_candidates": int(final[6]),
-        "served": served, "extras": extras,
+        "served": served, "streams": streams, "extras": extras,
         "input_generation_s": t_gen, "stage_timing": timing_src,
         "tuning": tuned, "autotune": tune_table,
     }
