@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--serve-events", type=int, default=5000,
                     help="events per served stream (0: skip the serving measurement)")
-    ap.add_argument("--serve-rates", default="500,20000",
+    ap.add_argument("--serve-rates", default="500,100000",
                     help="Poisson arrival rates (events/s) of the served streams; the largest saturates the GPU")
     ap.add_argument("--skip-extras", action="store_true",
                     help="skip the standalone scoring, edge-classifier and pre-DNN measurements")

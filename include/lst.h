@@ -323,8 +323,8 @@ lst_status lst_graph_components(lst_ctx *ctx, int64_t n_nodes, const int32_t *sr
  * writes its objects in candidate order whatever the tiling, so a tuning only
  * changes speed (the autotuner in the Python package times them).
  *   bin_split    sensor-id ranges per event in hit binning, each sorted by one
- *                block in LDS (1..64; raised at launch to the number of ranges
- *                of at most 1024 sensor ids that cover the geometry);
+ *                block in LDS (1..256; raised at launch to the number of ranges
+ *                of at most 512 sensor ids that cover the geometry);
  *   tile_per[s]  candidates per thread of a 256-thread compaction tile, for
  *                stage s = 0 MD {2,4,8}, 3 T5 FP32 pre-cuts {1,2,4}, 4 T5
  *                FP64 fits {1,2}; entries 1 ({2,4,8}) and 2 ({1,2,4}) are

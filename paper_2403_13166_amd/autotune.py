@@ -23,7 +23,7 @@ import statistics
 
 from . import binding as B
 
-BIN_SPLITS = (1, 48, 64)      # sensor ranges per event (raised to what the geometry needs)
+BIN_SPLITS = (1, 96, 128)     # sensor ranges per event (raised to what the geometry needs)
 EVAL_BLOCKS = (1024, 2048, 4096, 8192)
 T3_MASKS = (2, 4, 8)
 # (knob, stage index or None, choices, timing window)

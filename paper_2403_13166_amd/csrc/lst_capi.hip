@@ -160,9 +160,10 @@ lst_status lst_load_geometry(lst_ctx *c, const void *blob, size_t nbytes) {
     GeomHost g;
     std::string err;
     if (!parse_geometry(blob, nbytes, g, err)) return fail(c, LST_E_INVAL, "%s", err.c_str());
-    // hit binning sorts at most kBinRangesMax ranges of 1024 sensors per event
-    if (2 * (int64_t)g.n_mod > 1024ll * kBinRangesMax)
-        return fail(c, LST_E_INVAL, "geometry blob: %d modules, at most %d supported", g.n_mod, 512 * kBinRangesMax);
+    // hit binning sorts at most kBinRangesMax ranges of kBinRangeSensors sensors per event
+    if (2 * (int64_t)g.n_mod > (int64_t)kBinRangeSensors * kBinRangesMax)
+        return fail(c, LST_E_INVAL, "geometry blob: %d modules, at most %d supported", g.n_mod,
+                    kBinRangeSensors / 2 * kBinRangesMax);
     const size_t nm = (size_t)g.n_mod;
     const std::vector<ModConst> &mods = g.mods;
     const std::vector<ModBox> &boxes = g.boxes;
@@ -243,8 +244,9 @@ static size_t layout(const lst_ctx *c, const lst_caps *k, char *base, Work *w) {
     x.bin_hit = (float4 *)take(16 * hits);
     // coarse binning tiles: every event adds at most one partial tile
     x.max_bin_tiles = hits / kBinTileHits + ev + 1;
-    // ranges per event: enough for 1024 sensor ids each, or the largest bin_split
-    const int64_t nr_max = (nsens + 1023) / 1024 > 64 ? (nsens + 1023) / 1024 : 64;
+    // ranges per event: enough for kBinRangeSensors sensor ids each, or the largest bin_split
+    const int64_t nr_need = (nsens + kBinRangeSensors - 1) / kBinRangeSensors;
+    const int64_t nr_max = nr_need > kBinSplitMax ? nr_need : kBinSplitMax;
     x.max_bin_entries = x.max_bin_tiles * nr_max;
     x.bin_tbase = (int64_t *)take(8 * (ev + 1));
     x.bin_nent = (int64_t *)take(8);

@@ -16,6 +16,8 @@ constexpr int kEvalBlocks = 8192;     // compaction blocks (256 CUs x 32), defau
 constexpr int kMaxStride = 8192;      // grid cap of grid-stride kernels
 constexpr int kMaxRecBytes = 48;      // largest per-candidate record a stage compacts
 constexpr int kBinRangesMax = 1024;   // sensor ranges per event in hit binning, at most
+constexpr int kBinRangeSensors = 512; // sensor ids of one binning range, at most
+constexpr int kBinSplitMax = 256;     // largest tuned count of binning ranges per event
 constexpr int kBinTileHits = 2048;     // hits of one binning tile
 
 // Launch shapes (never change results: outputs are in candidate order for any
@@ -33,7 +35,7 @@ struct Tuning {
 constexpr int kT3MaxMasks = 8;
 constexpr Tuning kDefaultTuning = {4, {4, 8, 2, 2, 1}, kEvalBlocks, kT3MaxMasks};
 inline bool tuning_valid(const Tuning &t) {
-    if (t.bin_split < 1 || t.bin_split > 64) return false;
+    if (t.bin_split < 1 || t.bin_split > kBinSplitMax) return false;
     if (t.eval_blocks < 256 || t.eval_blocks > kMaxStride) return false;
     if (t.t3_masks < 1 || t.t3_masks > kT3MaxMasks) return false;
     for (int i = 0; i < kStages; ++i) {

@@ -516,10 +516,10 @@ static void run_stage(const S &s, const int64_t *n_dev, int64_t n_cap, const Wor
 
 constexpr int kBinTile = kBinTileHits;  // hits of one coarse tile
 constexpr int kBinThreads = 256;
-constexpr int kFineRange = 1024;        // sensor ids of one range, at most
+constexpr int kFineRange = kBinRangeSensors;   // sensor ids of one range, at most
 constexpr int kMaxRanges = kBinRangesMax;
 constexpr int kFineThreads = 512;       // threads of a fine-pass block
-constexpr int kFineSrcCap = 12288;      // hits of a range gathered through LDS (16-bit indices)
+constexpr int kFineSrcCap = 12224;      // hits of a range gathered through LDS (16-bit indices; four blocks fit one CU's LDS)
 
 // q = v / d for 0 <= v < 2^24, d >= 1: FP32 reciprocal estimate, made exact
 __device__ __forceinline__ int div_small(int v, int d, float inv) {

@@ -39,7 +39,7 @@ def test_autotune_search_with_fake_context(monkeypatch):
 
     def fake_times(ctx):
         t = state["tuning"]
-        # T5 pre-cuts fastest at 4, binning fastest at 64, eval grid fastest at 2048; others flat
+        # T5 pre-cuts fastest at 4, binning fastest at 128, eval grid fastest at 2048; others flat
         return {"build": 1.0 + abs(t["eval_blocks"] - 2048) / 8192, "bin": 0.5 - 0.001 * t["bin_split"],
                 "md": 0.1, "ls": 1.0, "t3": 0.05 + 0.01 * (t["t3_masks"] == 2), "t5": 1.0 / t["tile_per"][3],
                 "score": 0.2}
@@ -57,7 +57,7 @@ def test_autotune_search_with_fake_context(monkeypatch):
             return [10, 20, 30, 40, 0, 0, 0, 0]
 
     best, table = AT.autotune(FakeBuilder(), lambda: None, lambda: None, reps=1)
-    assert best["tile_per"][3] == 4 and best["bin_split"] == 64 and best["eval_blocks"] == 2048
+    assert best["tile_per"][3] == 4 and best["bin_split"] == 128 and best["eval_blocks"] == 2048
     assert best["tile_per"][0] == 4                     # flat timings: no move without a clear gain
     assert best["tile_per"][1] == 4                     # the line-segment stage has no tiles: not searched
     assert best["tile_per"][2] == 2 and best["t3_masks"] == 8   # nor the T3 stage; masks: no clear gain
