@@ -644,8 +644,8 @@ __device__ __forceinline__ int key_bits(int n) { return n > 1 ? 32 - __clz(n - 1
 // loads of a batch before its stores avoids that serialisation.
 __device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // vmcnt(0)
 
-// Coarse pass: wavefront w of a tile takes the tile's hits [w * 1024, (w + 1) * 1024)
-// in 16 rounds of 64, all loaded up front, and ranks each hit among the
+// Coarse pass: wavefront w of a tile takes the tile's hits [w * 512, (w + 1) * 512)
+// in 8 rounds of 64, all loaded up front, and ranks each hit among the
 // wavefront's hits of the same range (running counters per wavefront); the
 // wavefronts' counts then give every hit its position in input order.
 __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const float *x, const float *y, const float *z,
