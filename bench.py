@@ -391,7 +391,7 @@ def measure_end_to_end(b, step, dev_hits, host_hits, counts, stream, reps):
 
 def host_cpu():
     """Model name and logical CPU count of this host, and the CPUs this
-    process may run on (the CPU share of a GPU machine)."""
+    process may run on (its share of the host when the host is shared)."""
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -444,7 +444,7 @@ def cpu_baseline(geo, evs, seconds):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (events shard by event "
+        print(f"bench.py runs on one GPU: the library has no multi-GPU path (events shard by event "
               f"with no collectives); got --gpus {a.gpus}", file=sys.stderr)
         sys.exit(2)
     import torch
