@@ -18,7 +18,7 @@ constexpr int kMaxRecBytes = 48;      // largest per-candidate record a stage co
 constexpr int kBinRangesMax = 1024;   // sensor ranges per event in hit binning, at most
 constexpr int kBinRangeSensors = 512; // sensor ids of one binning range, at most
 constexpr int kBinSplitMax = 256;     // largest tuned count of binning ranges per event
-constexpr int kBinTileHits = 2048;     // hits of one binning tile
+constexpr int kBinTileHits = 4096;     // hits of one binning tile
 
 // Launch shapes (never change results: outputs are in candidate order for any
 // tiling). Stage order: MD, LS, T3, T5 pre-cuts, T5 fit.

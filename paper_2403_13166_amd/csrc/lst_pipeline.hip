@@ -515,7 +515,8 @@ static void run_stage(const S &s, const int64_t *n_dev, int64_t n_cap, const Wor
 // Hits with an out-of-range sensor id set error bit 0 and are dropped.
 
 constexpr int kBinTile = kBinTileHits;  // hits of one coarse tile
-constexpr int kBinThreads = 256;
+constexpr int kBinThreads = 256;        // threads of a coarse count block
+constexpr int kScatterThreads = 512;    // threads of a coarse scatter block: eight wavefronts of 512 hits
 constexpr int kFineRange = kBinRangeSensors;   // sensor ids of one range, at most
 constexpr int kMaxRanges = kBinRangesMax;
 constexpr int kFineThreads = 512;       // threads of a fine-pass block
@@ -648,12 +649,12 @@ __device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0
 // in 8 rounds of 64, all loaded up front, and ranks each hit among the
 // wavefront's hits of the same range (running counters per wavefront); the
 // wavefronts' counts then give every hit its position in input order.
-__global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const float *x, const float *y, const float *z,
+__global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(const float *x, const float *y, const float *z,
                                                              const int32_t *sensor, const int64_t *ev_off, int n_ev,
                                                              int n_sens, int nr, int rw, const int64_t *tbase,
                                                              const int64_t *cpos, float4 *tmp, int32_t *tsens) {
-    constexpr int kWaves = kBinThreads / 64;
-    constexpr int kRounds = kBinTile / kBinThreads;
+    constexpr int kWaves = kScatterThreads / 64;
+    constexpr int kRounds = kBinTile / kScatterThreads;
     __shared__ int64_t s_base[kMaxRanges];
     __shared__ int32_t s_wc[kWaves][kMaxRanges];
     int e;
@@ -662,7 +663,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const float *x, con
     const int64_t h0 = ld_scalar(ev_off + e) + t * kBinTile, he = ld_scalar(ev_off + e + 1);
     const int64_t h1 = h0 + kBinTile < he ? h0 + kBinTile : he;
     const int64_t ebase = tbase[e] * nr + t;
-    for (int r = threadIdx.x; r < nr; r += kBinThreads) {
+    for (int r = threadIdx.x; r < nr; r += kScatterThreads) {
         s_base[r] = cpos[ebase + (int64_t)r * nt];
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) s_wc[w][r] = 0;
@@ -693,7 +694,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const float *x, con
     }
     __syncthreads();
     // exclusive prefix over the wavefronts, per range
-    for (int r = threadIdx.x; r < nr; r += kBinThreads) {
+    for (int r = threadIdx.x; r < nr; r += kScatterThreads) {
         int run = 0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
@@ -2093,7 +2094,7 @@ hipError_t run_pipeline(const RunArgs &a, const Work &w, const Outputs &o, hipSt
         hipLaunchKernelGGL(k_bin_count, dim3(grid_t), dim3(kBinThreads), 0, st, a.sensor, a.ev_off, a.n_ev, n_sens, nr,
                            rw, (const int64_t *)w.bin_tbase, w.bin_cnt, cnt);
         scan(CntF{w.bin_cnt}, w.bin_nent, w.max_bin_entries, w, w.bin_cpos, nullptr, st);
-        hipLaunchKernelGGL(k_bin_scatter, dim3(grid_t), dim3(kBinThreads), 0, st, a.x, a.y, a.z, a.sensor, a.ev_off,
+        hipLaunchKernelGGL(k_bin_scatter, dim3(grid_t), dim3(kScatterThreads), 0, st, a.x, a.y, a.z, a.sensor, a.ev_off,
                            a.n_ev, n_sens, nr, rw, (const int64_t *)w.bin_tbase, (const int64_t *)w.bin_cpos,
                            w.bin_tmp, w.bin_tsens);
         const int xcd_map = a.n_ev >= kXcds ? 1 : 0;
